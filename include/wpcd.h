@@ -1,0 +1,201 @@
+/*
+ * wpcd.h -- C ABI of the MI355X (gfx950) wave-packet continuum discretisation
+ * (WPCD) library for two-body partial-wave scattering.
+ *
+ * For every (potential sample, partial-wave channel) item the library
+ *   1. projects the potential onto N_WP momentum wave packets   (wpcd_project),
+ *   2. diagonalises H = H0 + V in the free wave-packet basis    (wpcd_eigh),
+ *   3. builds the on-shell T-matrix at every bin energy from the eigenpairs and
+ *      the energy-averaged scattering-packet resolvent          (wpcd_tmatrix),
+ *   4. turns S = 1 - i pi p t into phase shifts, Stapp mixing angles
+ *      (wpcd_observables) and total cross sections            (wpcd_sigma_tot).
+ * The method is that of Miller, Ekstroem and Forssen, "Wave-packet continuum
+ * discretisation for nucleon-nucleon scattering predictions" (arXiv:2106.00454):
+ * Sec. 3.1 (wave packets, diagonalisation, scattering-packet bins, coupled
+ * channels), Sec. 3.2 (LS equation in the packet basis, energy averaging,
+ * potential projection, five-step recipe), App. A (S-matrix, Stapp
+ * parametrisation, total cross section) and App. B (resolvent in a packet basis).
+ *
+ * Units and conventions
+ *   momenta k in fm^-1; reduced potential U = m_N V/(hbar c)^2 in fm; energies as
+ *   k^2 in fm^-2; states <k'|k> = delta(k'-k)/(k'k), so the LS kernel carries no
+ *   2/pi; T_lab in MeV (non-relativistic, equal masses: p = sqrt(m_N T_lab/2)/(hbar c),
+ *   m_N = 938.918 MeV, hbar c = 197.327 MeV fm); phase shifts and mixing angles in
+ *   degrees, principal values in (-90, 90]; cross sections in mb.
+ *   Momentum wave packets (f = 1, N_i = dk_i); on-shell momentum of bin k is its
+ *   midpoint kbar_k; H0 diagonal e_k = (k_{k-1}^2 + k_{k-1} k_k + k_k^2)/3.
+ *   Coupled channels (n_ch = 2) stack two copies of the free basis channel-major:
+ *   basis row r = a*N + i for orbital index a (0: l = J-1, 1: l = J+1) and bin i.
+ *
+ * Ownership and memory
+ *   All array arguments of the compute calls are DEVICE pointers owned by the
+ *   caller; the library never frees them.  Host pointers are marked "_host".
+ *   The context owns the resident grids (bounds, H0, Gauss nodes) and every batch
+ *   owns the device workspace of its eigensolver; both are freed by their destroy
+ *   call.  Compute calls are asynchronous on the given HIP stream; results are
+ *   valid once that stream has been synchronised.
+ *
+ * Errors
+ *   Every call returns a status: WPCD_OK or a negative WPCD_ERR_*.  Argument
+ *   checks happen before any launch and return WPCD_ERR_INVALID with nothing
+ *   enqueued.  A failed HIP call returns WPCD_ERR_DEVICE.  wpcd_last_error()
+ *   returns a thread-local message describing the last failure of this thread.
+ *   Per-item numerical failures are written to caller-provided int32 status
+ *   arrays (one entry per item) instead of failing the whole call.
+ *
+ * Threading: one context per device; calls on one context must not run
+ * concurrently from several host threads.
+ */
+#ifndef WPCD_H
+#define WPCD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WPCD_OK = 0,
+  WPCD_ERR_INVALID = -1,     /* bad argument, detected before any launch     */
+  WPCD_ERR_NOMEM = -2,       /* device allocation failed                     */
+  WPCD_ERR_DEVICE = -3,      /* a HIP runtime call failed                    */
+  WPCD_ERR_NOCONV = -4,      /* per item: Jacobi sweep cap reached           */
+  WPCD_ERR_AGAIN = -5,       /* reserved (asynchronous completion pending)   */
+  WPCD_ERR_BUSY = -6,        /* reserved (admission queue full)              */
+  WPCD_ERR_NUMERIC = -7,     /* per item: NaN/Inf, zero eigenvalue, a
+                                scattering family with < 2 members, unsorted
+                                or zero-width scattering bins               */
+  WPCD_ERR_UNSUPPORTED = -8  /* size or mode not supported by this build     */
+};
+
+/* Arithmetic of the eigensolver and T contraction.
+ * WPCD_MIXED: FP32 one-sided Jacobi held in LDS, then FP64 refinement of every
+ *             eigenpair; FP32 T contraction over an FP64 resolvent table.
+ * WPCD_F64:   FP64 one-sided Jacobi in device memory, FP64 T contraction.   */
+enum { WPCD_MIXED = 0, WPCD_F64 = 1 };
+
+/* Element type of the fine-mesh potential passed to wpcd_project. */
+enum { WPCD_DTYPE_F32 = 0, WPCD_DTYPE_F64 = 1 };
+
+typedef struct wpcd_context* wpcd_ctx;
+typedef struct wpcd_batch_s* wpcd_batch;
+
+typedef struct {
+  int32_t max_sweeps;    /* Jacobi sweep cap (default 30)                       */
+  int32_t refine_steps;  /* FP64 refinement steps in WPCD_MIXED (default 2, 0..4) */
+  double jacobi_tol_f32; /* one-sided Jacobi: skip a pair once |w_p.w_q| <=
+                            tol*|w_p||w_q| (FP32 path; default 2e-7)            */
+  double jacobi_tol_f64; /* same for the FP64 path (default 1e-15)              */
+} wpcd_config;
+
+/* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */
+int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg);
+void wpcd_destroy(wpcd_ctx ctx);
+const char* wpcd_last_error(void);
+/* Library version string (static storage). */
+const char* wpcd_version(void);
+
+/* ---------------------------------------------------------------- grids ----
+ * Register a momentum bin grid (Sec. 3.2, step 1): k_bounds_host[0] = 0 <
+ * k_1 < ... < k_N, N = n_wp >= 2, n_gauss in [1, 16] Gauss-Legendre nodes per
+ * bin for the projection.  The library computes and keeps resident on the
+ * device the bin widths, midpoints, boundary energies, H0 diagonal, nodes and
+ * weights.  Returns a grid id >= 0 in *grid_id.                              */
+int wpcd_grid_create(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_gauss, int* grid_id);
+/* Copy the grid's Gauss nodes and weights (N*n_gauss each, bin-major) to host
+ * memory, e.g. to evaluate a potential at exactly the nodes the library uses.  */
+int wpcd_grid_nodes(wpcd_ctx ctx, int grid_id, double* nodes_host, double* weights_host);
+
+/* ---------------------------------------------------------------- batches --
+ * One item = one channel of one potential sample.  n_ch = 1 (uncoupled) or 2
+ * (coupled, l = J-1 and J+1); J weights the item by 2J+1 in wpcd_sigma_tot;
+ * items with equal sample_id (0 <= sample_id < n_samples) are summed into one
+ * cross section.  Items are packed in the order given; per item with
+ * N = n_wp of its grid, n = n_ch*N and M = n_ch*N*n_gauss the packed arrays hold
+ *   u_fine  : M*M   (row-major, channel-major rows and columns, symmetric)
+ *   v64     : n*n   (row-major, symmetric)
+ *   eval    : n     (ascending)
+ *   evec    : n*n   (row-major: evec[r*n + m] = <x_r|z_m>, eigenvector m is
+ *                    column m)
+ *   t       : 2*N*n_ch*n_ch doubles (complex interleaved re,im; index
+ *                    ((k*n_ch + a)*n_ch + b))
+ *   delta   : N*n_ch  (index k*n_ch + a)
+ *   mix     : N       (Stapp eps_J for coupled items, 0 for uncoupled)
+ *   s_dev   : N*n_ch  (1 - |S_aa|, a diagnostic of non-unitarity)
+ * wpcd_batch_create validates the items, uploads their descriptors and
+ * allocates the eigensolver workspace of the batch.                          */
+typedef struct {
+  int32_t grid_id;
+  int32_t n_ch;
+  int32_t J;
+  int32_t sample_id;
+} wpcd_item;
+
+typedef struct {
+  int64_t u_elems, v_elems, eval_elems, t_doubles, delta_elems, mix_elems;
+  int32_t n_items, n_samples, max_n, max_nbins;
+} wpcd_batch_layout;
+
+int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wpcd_batch* out);
+void wpcd_batch_destroy(wpcd_batch b);
+int wpcd_batch_layout_get(wpcd_batch b, wpcd_batch_layout* out);
+/* Per-item element offsets into the packed arrays (host arrays of n_items;
+ * any pointer may be NULL).                                                  */
+int wpcd_batch_offsets(wpcd_batch b, int64_t* u_off_host, int64_t* v_off_host, int64_t* eval_off_host,
+                       int64_t* t_off_host, int64_t* delta_off_host, int64_t* mix_off_host);
+
+/* ------------------------------------------------------------ compute calls --
+ * wpcd_project (Sec. 3.2, the packet potential matrix as a double bin integral):
+ *   V_(a,i),(b,j) = (dk_i dk_j)^(-1/2) sum_{alpha in i, beta in j}
+ *                   w_alpha k_alpha w_beta k_beta U_(a,alpha),(b,beta)
+ * from U at the grid's Gauss nodes.  u_dtype selects FP32 (accumulated in FP32)
+ * or FP64 (accumulated in FP64) input; V is written as FP64.                 */
+int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hipStream_t stream);
+
+/* wpcd_eigh (Sec. 3.1, H = C D C^T; Sec. 3.2, step 2): eigenpairs of
+ * H = diag(e, .., e) + V, eigenvalues ascending.  status[i] >= 0 is the number
+ * of Jacobi sweeps item i used; WPCD_ERR_NOCONV if the sweep cap was reached
+ * (results still written), WPCD_ERR_NUMERIC on NaN/Inf.  In WPCD_MIXED mode the
+ * FP32 eigenpairs are refined in FP64 (Newton-type update of all eigenpairs
+ * with a Rayleigh-Ritz solve inside clusters of close eigenvalues).          */
+int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
+              hipStream_t stream);
+
+/* wpcd_tmatrix (Sec. 3.1, scattering-packet bins; Sec. 3.2, steps 3-5 and the
+ * energy average; App. B): for every bin k and channels a, b
+ *   T_ab(k) = V_(a,k),(b,k) + sum_m VC_(a,k),m VC_(b,k),m gbar_km,
+ *   VC_r,m = (eps_m - e_r) C_r,m   (exact for eigenpairs of H0 + V),
+ * gbar_km = resolvent of packet m averaged over the free bin k.  Eigenvalues
+ * below 0 (bound) or above k_N^2 (discrete states of the cut-off Hamiltonian)
+ * contribute ln((E_k - eps)/(E_{k-1} - eps))/(E_k - E_{k-1}); the others are
+ * dealt round-robin into n_ch families, each with bins B_1 = 0,
+ * B_j = (eps_{j-1} + eps_j)/2, B_{n+1} = eps_n + (B_n - B_{n-1})/2.
+ * status[i] = 0 or WPCD_ERR_NUMERIC.  mode as in wpcd_eigh (contraction
+ * precision; the resolvent table is always FP64).                           */
+int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const double* evec, int mode,
+                 double* t, int32_t* status, hipStream_t stream);
+
+/* wpcd_observables (App. A, S = 1 - i pi p t, Stapp parametrisation; Sec. 3.1,
+ * t(q,q) = T_kk/(dk_k q^2) at q = kbar_k): per item and bin, phase shifts
+ * delta_a = arg(S_aa)/2, for coupled items eps_J = asin(Im(S12 exp(-i(d_- + d_+))))/2
+ * with S12 = (S_12 + S_21)/2, and s_dev = 1 - |S_aa|.  s_dev may be NULL.   */
+int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* mix_deg, double* s_dev,
+                     hipStream_t stream);
+
+/* wpcd_sigma_tot (App. A total cross section by the optical theorem in partial
+ * waves; Sec. 5.1.1 mid-point linear interpolation):
+ *   sigma(p) = 10 * pi/(2 p^2) sum_items (2J+1) sum_a (1 - Re S_aa(p)) [mb]
+ * with S rebuilt from (delta, eps) linearly interpolated in q between bin
+ * midpoints after unwrapping modulo 180 degrees (end segments extrapolated).
+ * tlab_mev: device array of n_tlab energies, each with 0 < p <= k_N of every
+ * item's grid (else NaN is written); sigma_mb: device array n_samples*n_tlab,
+ * index s*n_tlab + j.                                                       */
+int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev,
+                   int n_tlab, double* sigma_mb, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WPCD_H */

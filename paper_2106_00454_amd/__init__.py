@@ -1,0 +1,279 @@
+"""MI355X (gfx950) wave-packet continuum discretisation (WPCD) library.
+
+Thin ctypes binding of ``libwpcd.so`` (C ABI in ``include/wpcd.h``).  This
+module only marshals arguments: every step of the computation runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  If the
+library has not been built, every entry point raises ``RuntimeError`` -- there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwpcd.so")
+
+WPCD_OK = 0
+WPCD_ERR_INVALID = -1
+WPCD_ERR_NOMEM = -2
+WPCD_ERR_DEVICE = -3
+WPCD_ERR_NOCONV = -4
+WPCD_ERR_AGAIN = -5
+WPCD_ERR_BUSY = -6
+WPCD_ERR_NUMERIC = -7
+WPCD_ERR_UNSUPPORTED = -8
+
+MIXED = 0
+F64 = 1
+DTYPE_F32 = 0
+DTYPE_F64 = 1
+
+#: every symbol declared in include/wpcd.h
+EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wpcd_grid_create",
+           "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
+           "wpcd_batch_offsets", "wpcd_project", "wpcd_eigh", "wpcd_tmatrix", "wpcd_observables",
+           "wpcd_sigma_tot")
+
+
+class WPCDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"wpcd error {code}: {msg}")
+        self.code = code
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("jacobi_tol_f32", ctypes.c_double), ("jacobi_tol_f64", ctypes.c_double)]
+
+
+class _Item(ctypes.Structure):
+    _fields_ = [("grid_id", ctypes.c_int32), ("n_ch", ctypes.c_int32), ("J", ctypes.c_int32),
+                ("sample_id", ctypes.c_int32)]
+
+
+class _Layout(ctypes.Structure):
+    _fields_ = [("u_elems", ctypes.c_int64), ("v_elems", ctypes.c_int64), ("eval_elems", ctypes.c_int64),
+                ("t_doubles", ctypes.c_int64), ("delta_elems", ctypes.c_int64), ("mix_elems", ctypes.c_int64),
+                ("n_items", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("max_n", ctypes.c_int32),
+                ("max_nbins", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises RuntimeError if libwpcd.so is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2106_00454_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    sig = {
+        "wpcd_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(_Config)]),
+        "wpcd_destroy": (None, [vp]),
+        "wpcd_last_error": (ctypes.c_char_p, []),
+        "wpcd_version": (ctypes.c_char_p, []),
+        "wpcd_grid_create": (i32, [vp, ctypes.POINTER(ctypes.c_double), i32, i32, ctypes.POINTER(i32)]),
+        "wpcd_grid_nodes": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "wpcd_batch_create": (i32, [vp, ctypes.POINTER(_Item), i32, ctypes.POINTER(vp)]),
+        "wpcd_batch_destroy": (None, [vp]),
+        "wpcd_batch_layout_get": (i32, [vp, ctypes.POINTER(_Layout)]),
+        "wpcd_batch_offsets": (i32, [vp] + [ctypes.POINTER(i64)] * 6),
+        "wpcd_project": (i32, [vp, dp, i32, dp, vp]),
+        "wpcd_eigh": (i32, [vp, dp, i32, dp, dp, dp, vp]),
+        "wpcd_tmatrix": (i32, [vp, dp, dp, dp, i32, dp, dp, vp]),
+        "wpcd_observables": (i32, [vp, dp, dp, dp, dp, vp]),
+        "wpcd_sigma_tot": (i32, [vp, dp, dp, dp, i32, dp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code: int) -> None:
+    if code != WPCD_OK:
+        raise WPCDError(code, lib().wpcd_last_error().decode())
+
+
+def version() -> str:
+    return lib().wpcd_version().decode()
+
+
+def _ptr(t, dtype, numel, name):
+    """Device pointer of a contiguous CUDA tensor with at least numel elements."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: needs {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Grid:
+    id: int
+    k_bounds: np.ndarray
+    n_gauss: int
+    nodes: np.ndarray
+    weights: np.ndarray
+
+    @property
+    def n_wp(self) -> int:
+        return self.k_bounds.size - 1
+
+
+class Context:
+    def __init__(self, device: int = 0, max_sweeps: int = 30, refine_steps: int = 2,
+                 jacobi_tol_f32: float = 2e-7, jacobi_tol_f64: float = 1e-15):
+        L = lib()
+        cfg = _Config(max_sweeps, refine_steps, jacobi_tol_f32, jacobi_tol_f64)
+        h = ctypes.c_void_p()
+        _check(L.wpcd_create(ctypes.byref(h), device, ctypes.byref(cfg)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wpcd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grid(self, k_bounds, n_gauss: int = 8) -> Grid:
+        k = np.ascontiguousarray(k_bounds, dtype=np.float64)
+        gid = ctypes.c_int()
+        _check(lib().wpcd_grid_create(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k.size - 1,
+                                      n_gauss, ctypes.byref(gid)))
+        m = (k.size - 1) * n_gauss
+        nodes, weights = np.empty(m), np.empty(m)
+        _check(lib().wpcd_grid_nodes(self._h, gid.value, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return Grid(gid.value, k, n_gauss, nodes, weights)
+
+    def batch(self, items) -> "Batch":
+        """items: iterable of (grid, n_ch, J, sample_id)."""
+        return Batch(self, list(items))
+
+
+class Batch:
+    def __init__(self, ctx: Context, items):
+        self.ctx = ctx
+        arr = (_Item * len(items))()
+        self.grids = []
+        for i, (g, n_ch, J, sid) in enumerate(items):
+            arr[i] = _Item(g.id, n_ch, J, sid)
+            self.grids.append(g)
+        self.items = items
+        h = ctypes.c_void_p()
+        _check(lib().wpcd_batch_create(ctx._h, arr, len(items), ctypes.byref(h)))
+        self._h = h
+        lay = _Layout()
+        _check(lib().wpcd_batch_layout_get(h, ctypes.byref(lay)))
+        self.layout = {f: getattr(lay, f) for f, _ in _Layout._fields_}
+        offs = [np.zeros(len(items), dtype=np.int64) for _ in range(6)]
+        _check(lib().wpcd_batch_offsets(h, *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) for o in offs]))
+        self.u_off, self.v_off, self.eval_off, self.t_off, self.delta_off, self.mix_off = offs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wpcd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ buffers
+    def alloc(self, device="cuda"):
+        """Output buffers of the whole path as torch tensors on `device`."""
+        import torch
+        L = self.layout
+        f64 = dict(dtype=torch.float64, device=device)
+        return {
+            "v64": torch.empty(L["v_elems"], **f64),
+            "eval": torch.empty(L["eval_elems"], **f64),
+            "evec": torch.empty(L["v_elems"], **f64),
+            "t": torch.empty(L["t_doubles"], **f64),
+            "delta": torch.empty(L["delta_elems"], **f64),
+            "mix": torch.empty(L["mix_elems"], **f64),
+            "s_dev": torch.empty(L["delta_elems"], **f64),
+            "eig_status": torch.empty(L["n_items"], dtype=torch.int32, device=device),
+            "t_status": torch.empty(L["n_items"], dtype=torch.int32, device=device),
+        }
+
+    # ------------------------------------------------------------ steps
+    def project(self, u, v64, stream=None):
+        import torch
+        dt = DTYPE_F32 if u.dtype == torch.float32 else DTYPE_F64
+        _check(lib().wpcd_project(self._h, _ptr(u, u.dtype, self.layout["u_elems"], "u"), dt,
+                                  _ptr(v64, torch.float64, self.layout["v_elems"], "v64"), _stream(stream)))
+
+    def eigh(self, v64, mode, eval_, evec, status, stream=None):
+        import torch
+        L = self.layout
+        _check(lib().wpcd_eigh(self._h, _ptr(v64, torch.float64, L["v_elems"], "v64"), mode,
+                               _ptr(eval_, torch.float64, L["eval_elems"], "eval"),
+                               _ptr(evec, torch.float64, L["v_elems"], "evec"),
+                               _ptr(status, torch.int32, L["n_items"], "status"), _stream(stream)))
+
+    def tmatrix(self, v64, eval_, evec, mode, t, status, stream=None):
+        import torch
+        L = self.layout
+        _check(lib().wpcd_tmatrix(self._h, _ptr(v64, torch.float64, L["v_elems"], "v64"),
+                                  _ptr(eval_, torch.float64, L["eval_elems"], "eval"),
+                                  _ptr(evec, torch.float64, L["v_elems"], "evec"), mode,
+                                  _ptr(t, torch.float64, L["t_doubles"], "t"),
+                                  _ptr(status, torch.int32, L["n_items"], "status"), _stream(stream)))
+
+    def observables(self, t, delta, mix, s_dev=None, stream=None):
+        import torch
+        L = self.layout
+        sd = _ptr(s_dev, torch.float64, L["delta_elems"], "s_dev") if s_dev is not None else ctypes.c_void_p(0)
+        _check(lib().wpcd_observables(self._h, _ptr(t, torch.float64, L["t_doubles"], "t"),
+                                      _ptr(delta, torch.float64, L["delta_elems"], "delta"),
+                                      _ptr(mix, torch.float64, L["mix_elems"], "mix"), sd, _stream(stream)))
+
+    def sigma_tot(self, delta, mix, tlab, sigma, stream=None):
+        import torch
+        L = self.layout
+        n_tlab = tlab.numel()
+        _check(lib().wpcd_sigma_tot(self._h, _ptr(delta, torch.float64, L["delta_elems"], "delta"),
+                                    _ptr(mix, torch.float64, L["mix_elems"], "mix"),
+                                    _ptr(tlab, torch.float64, n_tlab, "tlab"), n_tlab,
+                                    _ptr(sigma, torch.float64, L["n_samples"] * n_tlab, "sigma"),
+                                    _stream(stream)))
+
+    def run(self, u, bufs, mode, tlab=None, sigma=None, stream=None):
+        """The whole path a1..a9 for this batch on one stream."""
+        self.project(u, bufs["v64"], stream)
+        self.eigh(bufs["v64"], mode, bufs["eval"], bufs["evec"], bufs["eig_status"], stream)
+        self.tmatrix(bufs["v64"], bufs["eval"], bufs["evec"], mode, bufs["t"], bufs["t_status"], stream)
+        self.observables(bufs["t"], bufs["delta"], bufs["mix"], bufs["s_dev"], stream)
+        if tlab is not None:
+            self.sigma_tot(bufs["delta"], bufs["mix"], tlab, sigma, stream)

@@ -1,0 +1,387 @@
+// Host side of the C ABI: contexts, resident grids, batches and the compute
+// entry points declared in include/wpcd.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "handles.h"
+#include "internal.h"
+
+using namespace wpcd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? WPCD_ERR_NOMEM : WPCD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define WPCD_HIP(call, what)              \
+  do {                                    \
+    hipError_t e_ = (call);               \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n, with
+// P_n'(x) = n (x P_n - P_{n-1})/(x^2 - 1) and w = 2/((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int iter = 0; iter < 100; ++iter) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) <= 1e-16) {
+        // derivative at the converged root
+        p0 = 1.0;
+        p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        break;
+      }
+    }
+    x[n - 1 - i] = z;  // ascending
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wpcd_last_error(void) { return g_err.c_str(); }
+const char* wpcd_version(void) { return "wpcd-gfx950 0.1"; }
+
+int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
+  if (!out) return fail(WPCD_ERR_INVALID, "wpcd_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  WPCD_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= ndev)
+    return fail(WPCD_ERR_INVALID, "wpcd_create: device %d out of range (%d devices)", hip_device, ndev);
+  wpcd_config c{30, 2, 2e-7, 1e-15};
+  if (cfg) c = *cfg;
+  if (c.max_sweeps < 1 || c.max_sweeps > 60) return fail(WPCD_ERR_INVALID, "max_sweeps must be in [1, 60]");
+  if (c.refine_steps < 0 || c.refine_steps > 4) return fail(WPCD_ERR_INVALID, "refine_steps must be in [0, 4]");
+  if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
+  WPCD_HIP(hipSetDevice(hip_device), "hipSetDevice");
+  wpcd_context* ctx = new (std::nothrow) wpcd_context;
+  if (!ctx) return fail(WPCD_ERR_NOMEM, "wpcd_create: host allocation");
+  ctx->device = hip_device;
+  ctx->cfg = c;
+  *out = ctx;
+  return WPCD_OK;
+}
+
+void wpcd_destroy(wpcd_ctx ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  for (auto& g : ctx->grids) hipFree(g.dbuf);
+  delete ctx;
+}
+
+int wpcd_grid_create(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_gauss, int* grid_id) {
+  if (!ctx || !k_bounds_host || !grid_id) return fail(WPCD_ERR_INVALID, "wpcd_grid_create: NULL argument");
+  if (n_wp < 2 || n_wp > kMaxN) return fail(WPCD_ERR_INVALID, "n_wp must be in [2, %d]", kMaxN);
+  if (n_gauss < 1 || n_gauss > 16) return fail(WPCD_ERR_INVALID, "n_gauss must be in [1, 16]");
+  if (k_bounds_host[0] != 0.0) return fail(WPCD_ERR_INVALID, "k_bounds[0] must be 0");
+  for (int i = 1; i <= n_wp; ++i)
+    if (!(k_bounds_host[i] > k_bounds_host[i - 1]) || !isfinite(k_bounds_host[i]))
+      return fail(WPCD_ERR_INVALID, "k_bounds must increase strictly (index %d)", i);
+  WPCD_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  GridHost g;
+  g.N = n_wp;
+  g.ng = n_gauss;
+  g.kb.assign(k_bounds_host, k_bounds_host + n_wp + 1);
+  std::vector<double> x, w;
+  gauss_legendre(n_gauss, x, w);
+  const int N = n_wp, ng = n_gauss;
+  std::vector<double> eb(N + 1), dk(N), kbar(N), e0(N), wk((size_t)N * ng), rsdk(N);
+  g.nodes.resize((size_t)N * ng);
+  g.weights.resize((size_t)N * ng);
+  for (int j = 0; j <= N; ++j) eb[j] = g.kb[j] * g.kb[j];
+  for (int i = 0; i < N; ++i) {
+    const double a = g.kb[i], b = g.kb[i + 1];
+    dk[i] = b - a;
+    kbar[i] = 0.5 * (a + b);
+    e0[i] = (a * a + a * b + b * b) / 3.0;  // bin average of k^2
+    rsdk[i] = 1.0 / sqrt(dk[i]);
+    for (int q = 0; q < ng; ++q) {
+      const double node = 0.5 * (b - a) * x[q] + 0.5 * (b + a);
+      const double wt = 0.5 * (b - a) * w[q];
+      g.nodes[(size_t)i * ng + q] = node;
+      g.weights[(size_t)i * ng + q] = wt;
+      wk[(size_t)i * ng + q] = wt * node;
+    }
+  }
+  const size_t total = (size_t)(N + 1) * 2 + (size_t)N * 4 + (size_t)N * ng;
+  std::vector<double> host(total);
+  size_t o = 0;
+  auto put = [&](const std::vector<double>& v) {
+    const size_t at = o;
+    std::copy(v.begin(), v.end(), host.begin() + o);
+    o += v.size();
+    return at;
+  };
+  const size_t o_kb = put(g.kb), o_eb = put(eb), o_dk = put(dk), o_kbar = put(kbar), o_e0 = put(e0), o_wk = put(wk),
+               o_rs = put(rsdk);
+  WPCD_HIP(hipMalloc(&g.dbuf, total * sizeof(double)), "hipMalloc(grid)");
+  hipError_t e = hipMemcpy(g.dbuf, host.data(), total * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(g.dbuf);
+    return hip_fail(e, "hipMemcpy(grid)");
+  }
+  g.dev = GridDev{g.dbuf + o_kb, g.dbuf + o_eb, g.dbuf + o_dk, g.dbuf + o_kbar, g.dbuf + o_e0, g.dbuf + o_wk,
+                  g.dbuf + o_rs, N, ng};
+  ctx->grids.push_back(std::move(g));
+  *grid_id = (int)ctx->grids.size() - 1;
+  return WPCD_OK;
+}
+
+int wpcd_grid_nodes(wpcd_ctx ctx, int grid_id, double* nodes_host, double* weights_host) {
+  if (!ctx || grid_id < 0 || grid_id >= (int)ctx->grids.size())
+    return fail(WPCD_ERR_INVALID, "wpcd_grid_nodes: bad context or grid id");
+  const GridHost& g = ctx->grids[grid_id];
+  if (nodes_host) std::copy(g.nodes.begin(), g.nodes.end(), nodes_host);
+  if (weights_host) std::copy(g.weights.begin(), g.weights.end(), weights_host);
+  return WPCD_OK;
+}
+
+void wpcd_batch_destroy(wpcd_batch b) {
+  if (!b) return;
+  hipSetDevice(b->ctx->device);
+  hipFree(b->d_items);
+  hipFree(b->d_grids);
+  hipFree(b->d_sample_ptr);
+  hipFree(b->d_sample_items);
+  hipFree(b->d_x32);
+  hipFree(b->d_work);
+  hipFree(b->d_cl);
+  delete b;
+}
+
+int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wpcd_batch* out) {
+  if (!ctx || !items_host || !out) return fail(WPCD_ERR_INVALID, "wpcd_batch_create: NULL argument");
+  *out = nullptr;
+  if (n_items < 1) return fail(WPCD_ERR_INVALID, "wpcd_batch_create: n_items must be >= 1");
+  WPCD_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  wpcd_batch_s* b = new (std::nothrow) wpcd_batch_s;
+  if (!b) return fail(WPCD_ERR_NOMEM, "wpcd_batch_create: host allocation");
+  b->ctx = ctx;
+  b->n_items = n_items;
+  b->h_items.resize(n_items);
+  int max_sample = -1;
+  for (int i = 0; i < n_items; ++i) {
+    const wpcd_item& in = items_host[i];
+    if (in.grid_id < 0 || in.grid_id >= (int)ctx->grids.size()) {
+      delete b;
+      return fail(WPCD_ERR_INVALID, "item %d: unknown grid id %d", i, in.grid_id);
+    }
+    if (in.n_ch != 1 && in.n_ch != 2) {
+      delete b;
+      return fail(WPCD_ERR_INVALID, "item %d: n_ch must be 1 or 2", i);
+    }
+    if (in.J < 0 || (in.n_ch == 2 && in.J < 1) || in.sample_id < 0) {
+      delete b;
+      return fail(WPCD_ERR_INVALID, "item %d: need J >= 0 (>= 1 if coupled) and sample_id >= 0", i);
+    }
+    const GridHost& g = ctx->grids[in.grid_id];
+    const int n = in.n_ch * g.N;
+    if (n > kMaxN) {
+      delete b;
+      return fail(WPCD_ERR_UNSUPPORTED, "item %d: n = %d exceeds %d", i, n, kMaxN);
+    }
+    ItemDev& d = b->h_items[i];
+    d.grid = in.grid_id;
+    d.nch = in.n_ch;
+    d.N = g.N;
+    d.n = n;
+    d.ng = g.ng;
+    d.J = in.J;
+    d.sample = in.sample_id;
+    d.pad = 0;
+    const int64_t M = (int64_t)n * g.ng;
+    d.u_off = b->u_elems;
+    d.v_off = b->v_elems;
+    d.e_off = b->eval_elems;
+    d.t_off = b->t_doubles;
+    d.d_off = b->delta_elems;
+    d.m_off = b->mix_elems;
+    d.w_off = b->work_doubles;
+    b->u_elems += M * M;
+    b->v_elems += (int64_t)n * n;
+    b->eval_elems += n;
+    b->t_doubles += 2LL * g.N * in.n_ch * in.n_ch;
+    b->delta_elems += (int64_t)g.N * in.n_ch;
+    b->mix_elems += g.N;
+    b->work_doubles += eig_work_doubles(n);
+    b->max_n = std::max(b->max_n, n);
+    b->max_nbins = std::max(b->max_nbins, g.N);
+    max_sample = std::max(max_sample, in.sample_id);
+  }
+  b->n_samples = max_sample + 1;
+  // per-sample item lists (CSR)
+  std::vector<int32_t> sptr(b->n_samples + 1, 0), sitems(n_items);
+  for (int i = 0; i < n_items; ++i) sptr[items_host[i].sample_id + 1]++;
+  for (int s = 0; s < b->n_samples; ++s) sptr[s + 1] += sptr[s];
+  {
+    std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+    for (int i = 0; i < n_items; ++i) sitems[fill[items_host[i].sample_id]++] = i;
+  }
+  std::vector<GridDev> gd(ctx->grids.size());
+  for (size_t i = 0; i < gd.size(); ++i) gd[i] = ctx->grids[i].dev;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 1);
+  };
+  alloc((void**)&b->d_items, sizeof(ItemDev) * n_items);
+  alloc((void**)&b->d_grids, sizeof(GridDev) * gd.size());
+  alloc((void**)&b->d_sample_ptr, sizeof(int32_t) * sptr.size());
+  alloc((void**)&b->d_sample_items, sizeof(int32_t) * sitems.size());
+  alloc((void**)&b->d_x32, sizeof(float) * b->v_elems);
+  alloc((void**)&b->d_work, sizeof(double) * b->work_doubles);
+  alloc((void**)&b->d_cl, sizeof(int32_t) * b->eval_elems);
+  if (e == hipSuccess) e = hipMemcpy(b->d_items, b->h_items.data(), sizeof(ItemDev) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_grids, gd.data(), sizeof(GridDev) * gd.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_sample_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_sample_items, sitems.data(), sizeof(int32_t) * sitems.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    wpcd_batch_destroy(b);
+    return hip_fail(e, "wpcd_batch_create");
+  }
+  *out = b;
+  return WPCD_OK;
+}
+
+int wpcd_batch_layout_get(wpcd_batch b, wpcd_batch_layout* out) {
+  if (!b || !out) return fail(WPCD_ERR_INVALID, "wpcd_batch_layout_get: NULL argument");
+  out->u_elems = b->u_elems;
+  out->v_elems = b->v_elems;
+  out->eval_elems = b->eval_elems;
+  out->t_doubles = b->t_doubles;
+  out->delta_elems = b->delta_elems;
+  out->mix_elems = b->mix_elems;
+  out->n_items = b->n_items;
+  out->n_samples = b->n_samples;
+  out->max_n = b->max_n;
+  out->max_nbins = b->max_nbins;
+  return WPCD_OK;
+}
+
+int wpcd_batch_offsets(wpcd_batch b, int64_t* u_off, int64_t* v_off, int64_t* eval_off, int64_t* t_off,
+                       int64_t* delta_off, int64_t* mix_off) {
+  if (!b) return fail(WPCD_ERR_INVALID, "wpcd_batch_offsets: NULL batch");
+  for (int i = 0; i < b->n_items; ++i) {
+    const ItemDev& d = b->h_items[i];
+    if (u_off) u_off[i] = d.u_off;
+    if (v_off) v_off[i] = d.v_off;
+    if (eval_off) eval_off[i] = d.e_off;
+    if (t_off) t_off[i] = d.t_off;
+    if (delta_off) delta_off[i] = d.d_off;
+    if (mix_off) mix_off[i] = d.m_off;
+  }
+  return WPCD_OK;
+}
+
+int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hipStream_t stream) {
+  if (!b || !u_fine || !v64) return fail(WPCD_ERR_INVALID, "wpcd_project: NULL argument");
+  if (u_dtype != WPCD_DTYPE_F32 && u_dtype != WPCD_DTYPE_F64)
+    return fail(WPCD_ERR_INVALID, "wpcd_project: unknown u_dtype %d", u_dtype);
+  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIP(launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64, stream),
+           "wpcd_project launch");
+  return WPCD_OK;
+}
+
+int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
+              hipStream_t stream) {
+  if (!b || !v64 || !eval || !evec || !status) return fail(WPCD_ERR_INVALID, "wpcd_eigh: NULL argument");
+  if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_eigh: unknown mode %d", mode);
+  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  const wpcd_config& c = b->ctx->cfg;
+  if (mode == WPCD_MIXED) {
+    if (b->max_n > kMaxLdsN)
+      return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED holds n <= %d in LDS (batch has n = %d)", kMaxLdsN,
+                  b->max_n);
+    if (c.refine_steps < 1)
+      return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED needs refine_steps >= 1");
+    WPCD_HIP(launch_jacobi_f32_lds(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, eval, status,
+                                   c.max_sweeps, (float)c.jacobi_tol_f32, stream),
+             "wpcd_eigh: FP32 Jacobi launch");
+    WPCD_HIP(launch_refine(b->d_items, b->n_items, b->d_grids, v64, b->d_x32, evec, eval, b->d_work, b->d_cl, status,
+                           c.refine_steps, stream),
+             "wpcd_eigh: FP64 refinement launch");
+  } else {
+    WPCD_HIP(launch_jacobi_f64_global(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_work, evec, eval,
+                                      status, c.max_sweeps, c.jacobi_tol_f64, stream),
+             "wpcd_eigh: FP64 Jacobi launch");
+  }
+  return WPCD_OK;
+}
+
+int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const double* evec, int mode, double* t,
+                 int32_t* status, hipStream_t stream) {
+  if (!b || !v64 || !eval || !evec || !t || !status) return fail(WPCD_ERR_INVALID, "wpcd_tmatrix: NULL argument");
+  if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_tmatrix: unknown mode %d", mode);
+  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIP(launch_tmatrix(b->d_items, b->n_items, b->max_n, b->d_grids, v64, eval, evec, mode, t, status, stream),
+           "wpcd_tmatrix launch");
+  return WPCD_OK;
+}
+
+int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* mix_deg, double* s_dev,
+                     hipStream_t stream) {
+  if (!b || !t || !delta_deg || !mix_deg) return fail(WPCD_ERR_INVALID, "wpcd_observables: NULL argument");
+  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIP(launch_observables(b->d_items, b->n_items, b->max_nbins, b->d_grids, t, delta_deg, mix_deg, s_dev, stream),
+           "wpcd_observables launch");
+  return WPCD_OK;
+}
+
+int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev, int n_tlab,
+                   double* sigma_mb, hipStream_t stream) {
+  if (!b || !delta_deg || !mix_deg || !tlab_mev || !sigma_mb)
+    return fail(WPCD_ERR_INVALID, "wpcd_sigma_tot: NULL argument");
+  if (n_tlab < 1 || n_tlab > 1024) return fail(WPCD_ERR_INVALID, "wpcd_sigma_tot: n_tlab must be in [1, 1024]");
+  if (b->max_nbins > 1200) return fail(WPCD_ERR_UNSUPPORTED, "wpcd_sigma_tot: more than 1200 bins");
+  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIP(launch_sigma(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples, b->d_grids, delta_deg, mix_deg,
+                        tlab_mev, n_tlab, sigma_mb, stream),
+           "wpcd_sigma_tot launch");
+  return WPCD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Device helpers shared by the eigensolver kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wpcd {
+
+// ---------------------------------------------------------------------------
+// Sums over aligned groups of G lanes (G = 4, 8 or 16) with DPP lane swizzles.
+// Every lane of a group ends with the bitwise-same total: each butterfly stage
+// adds the same two partial sums in either order, and IEEE addition is
+// commutative, so control decisions taken on the result are group-uniform.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int kQuadXor1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+  if (G >= 2) v += dpp_f32<kQuadXor1>(v);
+  if (G >= 4) v += dpp_f32<kQuadXor2>(v);
+  if (G >= 8) v += dpp_f32<kRowHalfMirror>(v);
+  if (G >= 16) v += dpp_f32<kRowMirror>(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+  if (G >= 2) v += dpp_f64<kQuadXor1>(v);
+  if (G >= 4) v += dpp_f64<kQuadXor2>(v);
+  if (G >= 8) v += dpp_f64<kRowHalfMirror>(v);
+  if (G >= 16) v += dpp_f64<kRowMirror>(v);
+  return v;
+}
+
+// Round-robin ("circle") ordering of a parallel Jacobi sweep over ne (even)
+// indices: position 0 keeps index 0, position q >= 1 holds
+// 1 + ((q - 1 + step) mod (ne - 1)); pairs are positions (i, ne-1-i).  Over
+// ne-1 steps every unordered pair meets exactly once and the pairs of one step
+// are disjoint, so they can be rotated concurrently (Sec. 4.2, parallel
+// cyclic-order Jacobi; Golub & Van Loan, parallel ordering).
+__device__ __forceinline__ int rr_index(int pos, int step, int ne) {
+  if (pos == 0) return 0;
+  int v = pos - 1 + step;
+  const int m = ne - 1;
+  v -= (v / m) * m;
+  return 1 + v;
+}
+
+// Rotation of the one-sided (Hestenes) Jacobi method: with Gram entries
+// al = |w_p|^2, be = |w_q|^2, ga = w_p.w_q, the plane rotation
+//   w_p <- c w_p - s w_q,  w_q <- s w_p + c w_q
+// with t = s/c the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be-al)/(2ga),
+// makes the two columns orthogonal.
+template <typename T>
+__device__ __forceinline__ void hestenes_rotation(T al, T be, T ga, T& c, T& s) {
+  const T zeta = (be - al) / (T(2) * ga);
+  const T t = copysign(T(1), zeta) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+  c = T(1) / sqrt(T(1) + t * t);
+  s = c * t;
+}
+
+// One-sided cyclic Jacobi on the n columns of W (column-major, leading
+// dimension ld) resident in LDS, executed by a whole work-group of BLOCK
+// threads in lane groups of G; each group owns one column pair per step and
+// keeps it in registers (RMAX >= ceil(n/G) rows per lane).  A pair is rotated
+// while |w_p.w_q| > tol |w_p||w_q|.  rot_flag must point to max_sweeps zeroed
+// shared ints.  Returns the number of sweeps run, or max_sweeps + 1 if the last
+// allowed sweep still rotated (not converged).  Ends with a barrier.
+template <typename T, int BLOCK, int G, int RMAX>
+__device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag) {
+  const int npair = (n + 1) >> 1;
+  const int ne = npair << 1;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    for (int step = 0; step < ne - 1; ++step) {
+      for (int pr = grp; pr < npair; pr += ngrp) {
+        const int p = rr_index(pr, step, ne);
+        const int q = rr_index(ne - 1 - pr, step, ne);
+        if (p >= n || q >= n) continue;  // the padding index of odd n
+        T* wp = W + (int64_t)p * ld;
+        T* wq = W + (int64_t)q * ld;
+        T xp[RMAX], xq[RMAX];
+        T al = T(0), be = T(0), ga = T(0);
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) {
+          const int r = lane + k * G;
+          T a = T(0), b = T(0);
+          if (r < n) {
+            a = wp[r];
+            b = wq[r];
+          }
+          xp[k] = a;
+          xq[k] = b;
+          al = fma(a, a, al);
+          be = fma(b, b, be);
+          ga = fma(a, b, ga);
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        ga = group_sum<G>(ga);
+        if (fabs(ga) > tol * sqrt(al * be)) {
+          T c, s;
+          hestenes_rotation(al, be, ga, c, s);
+#pragma unroll
+          for (int k = 0; k < RMAX; ++k) {
+            const int r = lane + k * G;
+            if (r < n) {
+              wp[r] = c * xp[k] - s * xq[k];
+              wq[r] = s * xp[k] + c * xq[k];
+            }
+          }
+          if (lane == 0) rot_flag[sweep] = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (rot_flag[sweep] == 0) return sweep + 1;
+  }
+  return max_sweeps + 1;
+}
+
+// Work-group reductions through a small shared scratch array (>= BLOCK/64 slots).
+template <int BLOCK, typename T, typename Op>
+__device__ T block_reduce(T v, T* scratch, Op op) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x / 64;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[w] = v;
+  __syncthreads();
+  T r = scratch[0];
+  for (int i = 1; i < BLOCK / 64; ++i) r = op(r, scratch[i]);
+  __syncthreads();
+  return r;
+}
+
+}  // namespace wpcd

@@ -1,0 +1,39 @@
+// Host-side handle types of the C ABI (shared by the library's host sources).
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+namespace wpcd {
+
+struct GridHost {
+  int N = 0, ng = 0;
+  std::vector<double> kb, nodes, weights;
+  double* dbuf = nullptr;
+  GridDev dev{};
+};
+
+}  // namespace wpcd
+
+
+struct wpcd_context {
+  int device = 0;
+  wpcd_config cfg{};
+  std::vector<wpcd::GridHost> grids;
+};
+
+struct wpcd_batch_s {
+  wpcd_ctx ctx = nullptr;
+  int n_items = 0, n_samples = 0, max_n = 0, max_nbins = 0;
+  std::vector<wpcd::ItemDev> h_items;
+  wpcd::ItemDev* d_items = nullptr;
+  wpcd::GridDev* d_grids = nullptr;
+  int32_t* d_sample_ptr = nullptr;
+  int32_t* d_sample_items = nullptr;
+  int64_t u_elems = 0, v_elems = 0, eval_elems = 0, t_doubles = 0, delta_elems = 0, mix_elems = 0, work_doubles = 0;
+  float* d_x32 = nullptr;
+  double* d_work = nullptr;
+  int32_t* d_cl = nullptr;
+};
+

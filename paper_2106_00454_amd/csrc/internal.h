@@ -1,0 +1,77 @@
+// Internal declarations of the WPCD HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "wpcd.h"
+
+namespace wpcd {
+
+// Device view of a resident bin grid.
+struct GridDev {
+  const double* kb;    // N+1 bin boundaries k_j
+  const double* eb;    // N+1 boundary energies k_j^2
+  const double* dk;    // N bin widths
+  const double* kbar;  // N midpoints
+  const double* e0;    // N free-Hamiltonian diagonal <k^2> over the bin
+  const double* wk;    // N*ng Gauss weight times node, bin-major
+  const double* rsdk;  // N 1/sqrt(dk)
+  int32_t N;
+  int32_t ng;
+};
+
+// Device descriptor of one item of a batch.
+struct ItemDev {
+  int32_t grid;    // index into the grid table
+  int32_t nch;     // 1 or 2
+  int32_t N;       // bins
+  int32_t n;       // nch*N
+  int32_t ng;      // Gauss nodes per bin
+  int32_t J;
+  int32_t sample;
+  int32_t pad;
+  int64_t u_off;   // elements into u_fine
+  int64_t v_off;   // elements into v64 / evec (n*n)
+  int64_t e_off;   // elements into eval (n)
+  int64_t t_off;   // doubles into t (2*N*nch*nch)
+  int64_t d_off;   // elements into delta / s_dev (N*nch)
+  int64_t m_off;   // elements into mix (N)
+  int64_t w_off;   // elements into the per-item eigensolver workspace
+};
+
+// Largest matrix the FP32 LDS eigensolver holds (n*n floats must fit 160 KiB).
+constexpr int kMaxLdsN = 200;
+// Largest item the library accepts in this build.
+constexpr int kMaxN = 1200;
+// Largest cluster handled by one Rayleigh-Ritz solve in the refinement.
+constexpr int kMaxCluster = 64;
+
+// Kernel launchers (each returns hipSuccess or the launch error).
+hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const void* u,
+                          int u_dtype, double* v64, hipStream_t s);
+hipError_t launch_jacobi_f32_lds(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
+                                 const double* v64, float* evec32, double* eval, int32_t* status, int max_sweeps,
+                                 float tol, hipStream_t s);
+hipError_t launch_jacobi_f64_global(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
+                                    const double* v64, double* work, double* evec, double* eval, int32_t* status,
+                                    int max_sweeps, double tol, hipStream_t s);
+hipError_t launch_refine(const ItemDev* items, int n_items, const GridDev* grids, const double* v64,
+                         const float* x32, double* evec, double* eval, double* work, int32_t* cl, int32_t* status,
+                         int steps, hipStream_t s);
+hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
+                          const double* eval, const double* evec, int mode, double* t, int32_t* status,
+                          hipStream_t s);
+hipError_t launch_observables(const ItemDev* items, int n_items, int max_nbins, const GridDev* grids,
+                              const double* t, double* delta, double* mix, double* s_dev, hipStream_t s);
+hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
+                        int n_samples, const GridDev* grids, const double* delta, const double* mix,
+                        const double* tlab, int n_tlab, double* sigma, hipStream_t s);
+
+// Per-item device work-space (doubles) of the eigensolvers for an n x n item:
+// P1 | Y | S | G for the refinement (the FP64 Jacobi uses P1).
+inline int64_t eig_work_doubles(int n) { return 4LL * n * n; }
+
+}  // namespace wpcd
