@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Channel-solves per second of the WPCD path on one MI355X.
+
+Workload: coupled S-D channel (l = 0/2, J = 1) with three central Yukawa terms
+and a tensor-like coupling, N_WP = 100 momentum bins on [0, 4] fm^-1 (200 x 200
+H), 8 Gauss points per bin; every item is a distinct seeded potential sample.
+One step = the whole path over one batch of items already resident in HBM:
+projection of the FP32 fine-mesh potential, FP32 Jacobi in LDS plus FP64
+refinement, T at all 100 bin energies, phase shifts / mixing angles and the
+total cross section at 30 T_lab values per item.
+
+Also reported: the plain FP64 path (one item per launch sequence, synchronised
+per item) on the same GPU, per-stage times from the library's event timers,
+the roofline of the dominant kernel, and the FP64 CPU oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "channel-solves/sec (coupled, N_WP=100, all bin energies) batched vs plain; p99 ms"
+N_WP = 100
+N_CH = 2
+N_TLAB = 30
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # TFLOP/s, non-packed FP32 FMA
+PEAK_FP64_MFMA = 78.6                               # TFLOP/s, published dense FP64 matrix peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------- CPU oracle
+_W = {}
+
+
+def _worker_init():
+    from oracle import wpcd as ow
+    from synth import configs
+    k = configs.grid("coupled_yukawa")
+    x, _ = ow.gauss_nodes(k, configs.N_GAUSS)
+    _W["k"] = k
+    _W["terms"] = configs.coupled_yukawa_terms(x)
+
+
+def _worker_item(sid: int) -> float:
+    from oracle import observables as oo
+    from oracle import wpcd as ow
+    from synth import configs
+    k = _W["k"]
+    u = sum(c * t for c, t in zip(configs.yukawa_coefficients(sid), _W["terms"]))
+    t0 = time.perf_counter()
+    r = ow.solve_channel(k, configs.N_GAUSS, u, N_CH)
+    _, kbar, _ = ow.bins(k)
+    oo.sigma_tot([(1, r["delta"], r["mix"])], kbar, np.linspace(1.0, 350.0, N_TLAB), k[-1])
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(seconds: float) -> dict:
+    """The oracle as it stands, one item per task, on all host cores."""
+    cores = os.cpu_count() or 1
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=ctx, initializer=_worker_init) as ex:
+        list(ex.map(_worker_item, range(cores)))          # warm every worker
+        done, t0 = 0, time.perf_counter()
+        chunk = 4 * cores
+        while time.perf_counter() - t0 < seconds:
+            list(ex.map(_worker_item, range(done, done + chunk)))
+            done += chunk
+        wall = time.perf_counter() - t0
+    return {"value": done / wall, "unit": "channel-solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} coupled N_WP=100 items (a1-a9 incl. sigma_tot), FP64 NumPy/LAPACK, "
+                      f"one single-threaded process per core, {wall:.1f} s wall"}
+
+
+# ----------------------------------------------------------------- GPU path
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--plain-items", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: items are independent and this build has no multi-GPU path "
+              "(sharding by parameter sample is described in DESIGN.md); run with --gpus 1", flush=True)
+        return 2
+
+    import torch
+    import paper_2106_00454_amd as wp
+    from synth import configs
+    from synth import device as sdev
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = wp.Context(0)
+    k = configs.grid("coupled_yukawa")
+    g = ctx.grid(k, configs.N_GAUSS)
+    B = args.batch
+    coeffs = np.array([configs.yukawa_coefficients(s) for s in range(B)])
+    b = ctx.batch([(g, N_CH, 1, s) for s in range(B)])
+    log(f"staging {B} items: {b.layout['u_elems'] * 4 / 1e9:.1f} GB of FP32 fine-mesh potentials")
+    terms = configs.coupled_yukawa_terms(g.nodes)
+    u = sdev.pack_coupled_yukawa(b.layout["u_elems"], b.u_off, g.nodes, coeffs, torch.float32, terms=terms)
+    bufs = b.alloc()
+    tlab = torch.linspace(1.0, 350.0, N_TLAB, dtype=torch.float64, device=dev)
+    sigma = torch.empty(B * N_TLAB, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        b.run(u, bufs, wp.MIXED, tlab, sigma)
+    torch.cuda.synchronize()
+    st_e = bufs["eig_status"].cpu().numpy()
+    st_t = bufs["t_status"].cpu().numpy()
+    if (st_e <= 0).any() or (st_t != 0).any():
+        log(f"item failures: eig {int((st_e <= 0).sum())} tmatrix {int((st_t != 0).sum())}")
+    sweeps = st_e[st_e > 0].astype(np.float64)
+
+    ctx.profile(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for i in range(args.steps):
+        b.run(u, bufs, wp.MIXED, tlab, sigma)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.profile(False)
+    step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    value = B * args.steps / wall
+    log(f"batched: {value:.0f} channel-solves/s, {wall / args.steps * 1e3:.2f} ms/step")
+
+    # roofline of the dominant kernel group
+    n = N_CH * N_WP
+    avg = {s: (ms / cnt if cnt else 0.0) for s, (ms, cnt) in stages.items()}
+    jac_flops = float(np.sum(sweeps)) / len(sweeps) * B * (n * (n - 1) / 2) * 12 * n
+    ref_flops = B * 2 * 6.0 * n ** 3
+    cand = {
+        "jacobi_f32": {"bound": "alu", "achieved": jac_flops / (avg["jacobi_f32"] * 1e-3) / 1e12,
+                       "peak": PEAK_FP32_VALU, "unit": "TFLOP/s"},
+        "refine": {"bound": "mfma", "achieved": ref_flops / (avg["refine"] * 1e-3) / 1e12,
+                   "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s"},
+    }
+    dom = max(("jacobi_f32", "refine"), key=lambda s: stages[s][0])
+    roof = dict(cand[dom])
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg[dom]
+
+    # plain FP64 path: one item per launch sequence, synchronised per item
+    P = args.plain_items
+    plain_lat = []
+    pbs = []
+    for s in range(P):
+        pb = ctx.batch([(g, N_CH, 1, 0)])
+        pu = sdev.pack_coupled_yukawa(pb.layout["u_elems"], pb.u_off, g.nodes, coeffs[s:s + 1], torch.float64,
+                                      terms=terms)
+        pbs.append((pb, pu, pb.alloc(), torch.empty(N_TLAB, dtype=torch.float64, device=dev)))
+    pb, pu, pbuf, psig = pbs[0]
+    pb.run(pu, pbuf, wp.F64, tlab, psig)          # warm-up
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for pb, pu, pbuf, psig in pbs:
+        t1 = time.perf_counter()
+        pb.run(pu, pbuf, wp.F64, tlab, psig)
+        torch.cuda.synchronize()
+        plain_lat.append((time.perf_counter() - t1) * 1e3)
+    plain_wall = time.perf_counter() - tp0
+    plain_lat = np.array(plain_lat)
+    plain = {"value": P / plain_wall, "unit": "channel-solves/s", "items": P,
+             "p50_ms": float(np.percentile(plain_lat, 50)), "p99_ms": float(np.percentile(plain_lat, 99))}
+    log(f"plain FP64: {plain['value']:.1f} channel-solves/s, p50 {plain['p50_ms']:.2f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.1f} channel-solves/s on {cpu['cores']} cores")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "channel-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "coupled S-D Yukawa+tensor channel, N_WP=100 (200x200 H), 8 Gauss/bin, "
+                               "T at all 100 bin energies, sigma_tot at 30 T_lab",
+                   "items_per_step": B, "n_wp": N_WP, "n_ch": N_CH, "input_dtype": "f32"},
+        "latency_ms": {"step_p50": float(np.percentile(step_ms, 50)), "step_p99": float(np.percentile(step_ms, 99))},
+        "plain_f64": plain,
+        "speedup_vs_plain": value / plain["value"],
+        "jacobi_sweeps_mean": float(sweeps.mean()) if sweeps.size else None,
+        "stages_ms_per_step": {s: ms / args.steps for s, (ms, cnt) in stages.items() if cnt},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -195,6 +195,27 @@ int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* m
 int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev,
                    int n_tlab, double* sigma_mb, hipStream_t stream);
 
+/* ------------------------------------------------------------ stage timers --
+ * When enabled, every compute call records a pair of HIP events on its stream
+ * around each kernel group it launches (the eigensolver counts as two stages:
+ * the Jacobi sweeps and the refinement).  wpcd_stage_times waits for the
+ * recorded events, adds their elapsed times to per-stage totals and returns
+ * the totals in milliseconds and the number of launches per stage (arrays of
+ * WPCD_N_STAGES, host memory, either may be NULL).  Enabling (again) resets
+ * the totals.  Timing adds two event records per kernel group.              */
+enum {
+  WPCD_STAGE_PROJECT = 0,
+  WPCD_STAGE_JACOBI_F32 = 1,
+  WPCD_STAGE_JACOBI_F64 = 2,
+  WPCD_STAGE_REFINE = 3,
+  WPCD_STAGE_TMATRIX = 4,
+  WPCD_STAGE_OBSERVABLES = 5,
+  WPCD_STAGE_SIGMA = 6,
+  WPCD_N_STAGES = 7
+};
+int wpcd_profile_enable(wpcd_ctx ctx, int on);
+int wpcd_stage_times(wpcd_ctx ctx, double* ms_host, int64_t* launches_host);
+
 #ifdef __cplusplus
 }
 #endif

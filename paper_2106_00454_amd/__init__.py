@@ -36,7 +36,9 @@ DTYPE_F64 = 1
 EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wpcd_grid_create",
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
            "wpcd_batch_offsets", "wpcd_project", "wpcd_eigh", "wpcd_tmatrix", "wpcd_observables",
-           "wpcd_sigma_tot")
+           "wpcd_sigma_tot", "wpcd_profile_enable", "wpcd_stage_times")
+
+STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma")
 
 
 class WPCDError(RuntimeError):
@@ -91,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "wpcd_tmatrix": (i32, [vp, dp, dp, dp, i32, dp, dp, vp]),
         "wpcd_observables": (i32, [vp, dp, dp, dp, dp, vp]),
         "wpcd_sigma_tot": (i32, [vp, dp, dp, dp, i32, dp, vp]),
+        "wpcd_profile_enable": (i32, [vp, i32]),
+        "wpcd_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -173,6 +177,17 @@ class Context:
         _check(lib().wpcd_grid_nodes(self._h, gid.value, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return Grid(gid.value, k, n_gauss, nodes, weights)
+
+    def profile(self, on: bool = True) -> None:
+        """Enable (and reset) or disable the library's per-stage event timers."""
+        _check(lib().wpcd_profile_enable(self._h, 1 if on else 0))
+
+    def stage_times(self) -> dict:
+        """{stage: (total_ms, launches)} accumulated since profile(True)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int64 * len(STAGES))()
+        _check(lib().wpcd_stage_times(self._h, ms, n))
+        return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
 
     def batch(self, items) -> "Batch":
         """items: iterable of (grid, n_ch, J, sample_id)."""

@@ -40,6 +40,26 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// Runs `launch` (returning hipError_t) between two events on `stream` when the
+// context's stage timers are on.
+template <class F>
+hipError_t timed(wpcd_ctx ctx, int stage, hipStream_t stream, F launch) {
+  if (!ctx->profiling) return launch();
+  wpcd_context::Pending p{stage, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&p.start);
+  if (e == hipSuccess) e = hipEventCreate(&p.stop);
+  if (e == hipSuccess) e = hipEventRecord(p.start, stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(p.stop, stream);
+  if (e == hipSuccess) {
+    ctx->pending.push_back(p);
+  } else {
+    if (p.start) hipEventDestroy(p.start);
+    if (p.stop) hipEventDestroy(p.stop);
+  }
+  return e;
+}
+
 // Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n, with
 // P_n'(x) = n (x P_n - P_{n-1})/(x^2 - 1) and w = 2/((1 - x^2) P_n'(x)^2).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
@@ -107,6 +127,11 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
 void wpcd_destroy(wpcd_ctx ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
+  for (auto& p : ctx->pending) {
+    hipEventSynchronize(p.stop);
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
   for (auto& g : ctx->grids) hipFree(g.dbuf);
   delete ctx;
 }
@@ -188,6 +213,7 @@ void wpcd_batch_destroy(wpcd_batch b) {
   hipFree(b->d_x32);
   hipFree(b->d_work);
   hipFree(b->d_cl);
+  hipFree(b->d_lam);
   delete b;
 }
 
@@ -272,6 +298,7 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   alloc((void**)&b->d_x32, sizeof(float) * b->v_elems);
   alloc((void**)&b->d_work, sizeof(double) * b->work_doubles);
   alloc((void**)&b->d_cl, sizeof(int32_t) * b->eval_elems);
+  alloc((void**)&b->d_lam, sizeof(double) * b->eval_elems);
   if (e == hipSuccess) e = hipMemcpy(b->d_items, b->h_items.data(), sizeof(ItemDev) * n_items, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_grids, gd.data(), sizeof(GridDev) * gd.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -321,7 +348,8 @@ int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hip
   if (u_dtype != WPCD_DTYPE_F32 && u_dtype != WPCD_DTYPE_F64)
     return fail(WPCD_ERR_INVALID, "wpcd_project: unknown u_dtype %d", u_dtype);
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64, stream),
+  WPCD_HIP(timed(b->ctx, WPCD_STAGE_PROJECT, stream,
+                 [&] { return launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64, stream); }),
            "wpcd_project launch");
   return WPCD_OK;
 }
@@ -338,15 +366,24 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                   b->max_n);
     if (c.refine_steps < 1)
       return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED needs refine_steps >= 1");
-    WPCD_HIP(launch_jacobi_f32_lds(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, eval, status,
-                                   c.max_sweeps, (float)c.jacobi_tol_f32, stream),
+    WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream,
+                   [&] {
+                     return launch_jacobi_f32_lds(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, eval,
+                                                  status, c.max_sweeps, (float)c.jacobi_tol_f32, stream);
+                   }),
              "wpcd_eigh: FP32 Jacobi launch");
-    WPCD_HIP(launch_refine(b->d_items, b->n_items, b->d_grids, v64, b->d_x32, evec, eval, b->d_work, b->d_cl, status,
-                           c.refine_steps, stream),
+    WPCD_HIP(timed(b->ctx, WPCD_STAGE_REFINE, stream,
+                   [&] {
+                     return launch_refine(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, evec, eval,
+                                          b->d_lam, b->d_work, b->d_cl, status, c.refine_steps, stream);
+                   }),
              "wpcd_eigh: FP64 refinement launch");
   } else {
-    WPCD_HIP(launch_jacobi_f64_global(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_work, evec, eval,
-                                      status, c.max_sweeps, c.jacobi_tol_f64, stream),
+    WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F64, stream,
+                   [&] {
+                     return launch_jacobi_f64_global(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_work, evec,
+                                                     eval, status, c.max_sweeps, c.jacobi_tol_f64, stream);
+                   }),
              "wpcd_eigh: FP64 Jacobi launch");
   }
   return WPCD_OK;
@@ -357,7 +394,11 @@ int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const doub
   if (!b || !v64 || !eval || !evec || !t || !status) return fail(WPCD_ERR_INVALID, "wpcd_tmatrix: NULL argument");
   if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_tmatrix: unknown mode %d", mode);
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(launch_tmatrix(b->d_items, b->n_items, b->max_n, b->d_grids, v64, eval, evec, mode, t, status, stream),
+  WPCD_HIP(timed(b->ctx, WPCD_STAGE_TMATRIX, stream,
+                 [&] {
+                   return launch_tmatrix(b->d_items, b->n_items, b->max_n, b->d_grids, v64, eval, evec, mode, t, status,
+                                         stream);
+                 }),
            "wpcd_tmatrix launch");
   return WPCD_OK;
 }
@@ -366,7 +407,11 @@ int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* m
                      hipStream_t stream) {
   if (!b || !t || !delta_deg || !mix_deg) return fail(WPCD_ERR_INVALID, "wpcd_observables: NULL argument");
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(launch_observables(b->d_items, b->n_items, b->max_nbins, b->d_grids, t, delta_deg, mix_deg, s_dev, stream),
+  WPCD_HIP(timed(b->ctx, WPCD_STAGE_OBSERVABLES, stream,
+                 [&] {
+                   return launch_observables(b->d_items, b->n_items, b->max_nbins, b->d_grids, t, delta_deg, mix_deg,
+                                             s_dev, stream);
+                 }),
            "wpcd_observables launch");
   return WPCD_OK;
 }
@@ -378,9 +423,55 @@ int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg,
   if (n_tlab < 1 || n_tlab > 1024) return fail(WPCD_ERR_INVALID, "wpcd_sigma_tot: n_tlab must be in [1, 1024]");
   if (b->max_nbins > 1200) return fail(WPCD_ERR_UNSUPPORTED, "wpcd_sigma_tot: more than 1200 bins");
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(launch_sigma(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples, b->d_grids, delta_deg, mix_deg,
-                        tlab_mev, n_tlab, sigma_mb, stream),
+  WPCD_HIP(timed(b->ctx, WPCD_STAGE_SIGMA, stream,
+                 [&] {
+                   return launch_sigma(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples, b->d_grids,
+                                       delta_deg, mix_deg, tlab_mev, n_tlab, sigma_mb, stream);
+                 }),
            "wpcd_sigma_tot launch");
+  return WPCD_OK;
+}
+
+int wpcd_profile_enable(wpcd_ctx ctx, int on) {
+  if (!ctx) return fail(WPCD_ERR_INVALID, "wpcd_profile_enable: NULL context");
+  WPCD_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  for (auto& p : ctx->pending) {
+    hipEventSynchronize(p.stop);
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  ctx->pending.clear();
+  for (int i = 0; i < WPCD_N_STAGES; ++i) {
+    ctx->stage_ms[i] = 0.0;
+    ctx->stage_launches[i] = 0;
+  }
+  ctx->profiling = on != 0;
+  return WPCD_OK;
+}
+
+int wpcd_stage_times(wpcd_ctx ctx, double* ms_host, int64_t* launches_host) {
+  if (!ctx) return fail(WPCD_ERR_INVALID, "wpcd_stage_times: NULL context");
+  WPCD_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipError_t err = hipSuccess;
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(p.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.start, p.stop);
+    if (e == hipSuccess) {
+      ctx->stage_ms[p.stage] += ms;
+      ctx->stage_launches[p.stage] += 1;
+    } else if (err == hipSuccess) {
+      err = e;
+    }
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  ctx->pending.clear();
+  if (err != hipSuccess) return hip_fail(err, "wpcd_stage_times");
+  for (int i = 0; i < WPCD_N_STAGES; ++i) {
+    if (ms_host) ms_host[i] = ctx->stage_ms[i];
+    if (launches_host) launches_host[i] = ctx->stage_launches[i];
+  }
   return WPCD_OK;
 }
 

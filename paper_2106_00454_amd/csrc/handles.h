@@ -21,6 +21,15 @@ struct wpcd_context {
   int device = 0;
   wpcd_config cfg{};
   std::vector<wpcd::GridHost> grids;
+  // stage timers
+  bool profiling = false;
+  struct Pending {
+    int stage;
+    hipEvent_t start, stop;
+  };
+  std::vector<Pending> pending;
+  double stage_ms[WPCD_N_STAGES] = {0};
+  int64_t stage_launches[WPCD_N_STAGES] = {0};
 };
 
 struct wpcd_batch_s {
@@ -35,5 +44,6 @@ struct wpcd_batch_s {
   float* d_x32 = nullptr;
   double* d_work = nullptr;
   int32_t* d_cl = nullptr;
+  double* d_lam = nullptr;  // Rayleigh quotients of the current refinement step
 };
 

@@ -58,9 +58,9 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, int n_items, int max_n, c
 hipError_t launch_jacobi_f64_global(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
                                     const double* v64, double* work, double* evec, double* eval, int32_t* status,
                                     int max_sweeps, double tol, hipStream_t s);
-hipError_t launch_refine(const ItemDev* items, int n_items, const GridDev* grids, const double* v64,
-                         const float* x32, double* evec, double* eval, double* work, int32_t* cl, int32_t* status,
-                         int steps, hipStream_t s);
+hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
+                         const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
+                         int32_t* status, int steps, hipStream_t s);
 hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                           const double* eval, const double* evec, int mode, double* t, int32_t* status,
                           hipStream_t s);
@@ -71,7 +71,7 @@ hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const i
                         const double* tlab, int n_tlab, double* sigma, hipStream_t s);
 
 // Per-item device work-space (doubles) of the eigensolvers for an n x n item:
-// P1 | Y | S | G for the refinement (the FP64 Jacobi uses P1).
-inline int64_t eig_work_doubles(int n) { return 4LL * n * n; }
+// P1 | Y | S | G | W5 | W6 for the refinement (the FP64 Jacobi uses P1).
+inline int64_t eig_work_doubles(int n) { return 6LL * n * n; }
 
 }  // namespace wpcd

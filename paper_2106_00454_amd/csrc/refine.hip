@@ -1,24 +1,30 @@
 // FP64 refinement of all eigenpairs produced by the FP32 eigensolver.
 //
-// One step (Ogita & Aishima, "Iterative refinement for symmetric eigenvalue
-// decomposition", Japan J. Indust. Appl. Math. 35 (2018)) for X ~ eigenvectors
-// of A = H0 + V in FP64:
+// One Newton-type step (after Ogita & Aishima, "Iterative refinement for
+// symmetric eigenvalue decomposition", Japan J. Indust. Appl. Math. 35 (2018))
+// for X ~ eigenvectors of A = H0 + V, all in FP64:
 //   Y = A X,  S = X^T Y,  G = X^T X,  R = I - G,  lam_i = S_ii / G_ii,
-//   delta = 2 (|S - diag(lam)|_F + |A|_F |R|_F),
-//   E_ij = (S_ij + lam_j R_ij)/(lam_j - lam_i)  if |lam_j - lam_i| > delta,
-//   E_ij = R_ij / 2                              otherwise (and on i = j),
-//   X <- X + X E.
-// Eigenvalues closer than delta form clusters (maximal runs of consecutive
-// gaps <= delta) that a Newton step cannot separate; the cluster kernel then
-// solves the Rayleigh-Ritz problem X_c^T A X_c in FP64 for every cluster and
-// rotates X_c onto its eigenvectors.  All clusters of an item are solved at
-// once as one block-diagonal matrix by the one-sided Jacobi kernel core:
-// columns of different blocks are exactly orthogonal, so no rotation mixes
-// blocks.
+//   E_ij = (S_ij + lam_j R_ij)/(lam_j - lam_i),  E_ii = R_ii/2,
+//   X <- X (I + E).
+// The first-order update is only accurate where |E_ij| is small.  A pair is
+// called close when c |S_ij + lam_j R_ij| >= |lam_j - lam_i| (or the same with
+// lam_i in the numerator), c = 1000, i.e. when its predicted correction would
+// reach 1e-3; close pairs take E_ij = R_ij/2 (orthogonalisation only) and every
+// maximal index range spanned by close pairs (a chain) is solved exactly by
+// Rayleigh-Ritz: with P = (I + E)[:, chain], X P spans the refined chain
+// subspace and (X P)^T A (X P) = P^T S P, whose eigenvectors Q (FP64 one-sided
+// Jacobi, all chains at once as one block-diagonal matrix) rotate the chain:
+// the update becomes X <- X M with M = I + E except M[:, chain] = P Q.
+// This replaces the published cluster threshold (a Frobenius-norm bound that
+// is far too coarse for an FP32 starting point and lets badly conditioned
+// Newton updates through) by a direct bound on the size of each update.
 //
-// The four n x n products per step are dense FP64 contractions and run on the
-// matrix cores (v_mfma_f64_16x16x4f64), one work-group per item walking its
-// 64 x 64 output tiles; 16 x 16 blocks entirely beyond n are skipped.
+// Kernels per step: Y = A X, {S, G} = X^T {Y, X} and X M are dense FP64
+// contractions on the matrix cores (v_mfma_f64_16x16x4f64), one work-group per
+// 64 x 64 output tile of one item (S and G: upper tiles only, mirrored);
+// refine_chain_kernel (one work-group per item) forms the Rayleigh quotients,
+// the chains and the Rayleigh-Ritz rotations.  A final kernel sorts the
+// eigenpairs by eigenvalue and writes them to the caller's arrays.
 #include <float.h>
 
 #include "devutil.h"
@@ -29,39 +35,60 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlock = 256;   // 4 wavefronts
-constexpr int kTM = 64;       // output tile
-constexpr int kTK = 16;       // K chunk
-constexpr int kLdT = kTM + 4; // LDS row stride of a staged tile (doubles)
-constexpr int kChunk = 64;    // columns per Rayleigh-Ritz batch
+constexpr int kBlock = 256;    // 4 wavefronts
+constexpr int kTM = 64;        // output tile edge
+constexpr int kTK = 32;        // reduction chunk
+constexpr int kLdT = kTM + 4;  // LDS stride of a staged operand tile (doubles)
+constexpr int kMaxChain = 64;  // columns in Rayleigh-Ritz chains per item
+constexpr double kCloseC = 1000.0;
 
-// Stage a 64 x 16 operand tile into LDS as T[k*kLdT + i], element (i,k) = f(r0+i, k0+k)
-// (zero outside [0,n) x [0,kn)).  KC: the source is contiguous along k.
+// --------------------------------------------------------------- GEMM tiles
+// acc = sum_k A(m0+i, k) B(k, c0+j) over one 64 x 64 tile; fa(i,k) gives A,
+// fb(j,k) gives B(k,j) (both take (output index, reduction index)).  AKC/BKC:
+// whether the operand's source is contiguous along k (chooses the thread map
+// of the global loads).  Operands are zero outside rows/cols/K.  The next
+// chunk is loaded into registers while the current one is multiplied.
+// v_mfma_f64_16x16x4f64: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// D[i][j] in lane j + 16*(i % 4), register i / 4.
 template <bool KC, class F>
-__device__ __forceinline__ void stage(double* T, int r0, int k0, int n_i, int n_k, const F& f) {
+__device__ __forceinline__ void fetch(double (&r)[8], int r0, int k0, int n_i, int n_k, const F& f) {
   const int tid = threadIdx.x;
-  if (KC) {
-    const int i = tid >> 2, kb = (tid & 3) * 4;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = kb + j;
-      T[k * kLdT + i] = (r0 + i < n_i && k0 + k < n_k) ? f(r0 + i, k0 + k) : 0.0;
+  for (int h = 0; h < 2; ++h) {
+    if (KC) {  // i = tid/8 + 32h, k = 4*(tid%8) + j
+      const int i = (tid >> 3) + 32 * h, kb = (tid & 7) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kb + j;
+        r[4 * h + j] = (r0 + i < n_i && k0 + k < n_k) ? f(r0 + i, k0 + k) : 0.0;
+      }
+    } else {  // k = tid/16 + 16h, i = 4*(tid%16) + j
+      const int k = (tid >> 4) + 16 * h, ib = (tid & 15) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = ib + j;
+        r[4 * h + j] = (r0 + i < n_i && k0 + k < n_k) ? f(r0 + i, k0 + k) : 0.0;
+      }
     }
-  } else {
-    const int k = tid >> 4, ib = (tid & 15) * 4;
+  }
+}
+template <bool KC>
+__device__ __forceinline__ void stash(double* T, const double (&r)[8]) {
+  const int tid = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = ib + j;
-      T[k * kLdT + i] = (r0 + i < n_i && k0 + k < n_k) ? f(r0 + i, k0 + k) : 0.0;
+  for (int h = 0; h < 2; ++h) {
+    if (KC) {
+      const int i = (tid >> 3) + 32 * h, kb = (tid & 7) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) T[(kb + j) * kLdT + i] = r[4 * h + j];
+    } else {
+      const int k = (tid >> 4) + 16 * h, ib = (tid & 15) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) T[k * kLdT + ib + j] = r[4 * h + j];
     }
   }
 }
 
-// acc = sum_k A(m0+i, k) B(k, c0+j) over one 64 x 64 output tile.
-// A(i,k) = fa(i,k) for i < rows, k < K; B(k,j) = fb(j,k) for j < cols, k < K.
-// Both functors take (output index, reduction index): for a row-major matrix M
-// the A operand M is RowMajor (fa(i,k) = M[i][k]) and the B operand M is
-// RowMajorT (fb(j,k) = M[k][j]); A = M^T is RowMajorT and B = M^T is RowMajor.
 template <bool AKC, bool BKC, class FA, class FB>
 __device__ void gemm_tile(double* As, double* Bs, int m0, int c0, int rows, int cols, int K, const FA& fa,
                           const FB& fb, d4 (&acc)[2][2]) {
@@ -76,12 +103,20 @@ __device__ void gemm_tile(double* As, double* Bs, int m0, int c0, int rows, int 
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) live[bi][bj] = (m0 + wr + bi * 16 < rows) && (c0 + wc + bj * 16 < cols);
+  double ra[8], rb[8];
+  fetch<AKC>(ra, m0, 0, rows, K, fa);
+  fetch<BKC>(rb, c0, 0, cols, K, fb);
   for (int k0 = 0; k0 < K; k0 += kTK) {
-    stage<AKC>(As, m0, k0, rows, K, fa);
-    stage<BKC>(Bs, c0, k0, cols, K, fb);
+    __syncthreads();  // previous chunk fully consumed
+    stash<AKC>(As, ra);
+    stash<BKC>(Bs, rb);
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kTK; ks += 4) {
+    if (k0 + kTK < K) {
+      fetch<AKC>(ra, m0, k0 + kTK, rows, K, fa);
+      fetch<BKC>(rb, c0, k0 + kTK, cols, K, fb);
+    }
+    const int kend = (K - k0) < kTK ? ((K - k0 + 3) & ~3) : kTK;
+    for (int ks = 0; ks < kend; ks += 4) {
       const int kr = ks + (lane >> 4);
       double a[2], b[2];
 #pragma unroll
@@ -94,13 +129,9 @@ __device__ void gemm_tile(double* As, double* Bs, int m0, int c0, int rows, int 
         for (int bj = 0; bj < 2; ++bj)
           if (live[bi][bj]) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
     }
-    __syncthreads();
   }
 }
 
-// Visit the accumulator entries of a tile: g(row, col, value) for in-range entries.
-// v_mfma_f64_16x16x4f64 leaves D[i][j] in lane j + 16*(i % 4), register i / 4
-// (A[i][k] comes from lane i + 16k, B[k][j] from lane j + 16k).
 template <class G>
 __device__ __forceinline__ void tile_store(int m0, int c0, int rows, int cols, const d4 (&acc)[2][2], const G& g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -118,7 +149,8 @@ __device__ __forceinline__ void tile_store(int m0, int c0, int rows, int cols, c
     }
 }
 
-struct HOp {  // A = V + diag(e0 per channel copy)
+// ------------------------------------------------------------ operand views
+struct HOp {  // A = V + diag(e0 per channel copy), symmetric
   const double* V;
   const double* e0;
   int n, N;
@@ -128,219 +160,289 @@ struct HOp {  // A = V + diag(e0 per channel copy)
     return h;
   }
 };
-
 template <typename XT>
-struct RowMajor {  // element (r, c) of a row-major n x ld matrix
+struct RowMajor {  // A operand M (fa(i,k) = M[i][k]) or B operand M^T
   const XT* p;
   int ld;
   __device__ double operator()(int r, int c) const { return (double)p[(int64_t)r * ld + c]; }
 };
 template <typename XT>
-struct RowMajorT {  // transposed view: (i, k) -> M(k, i)
+struct RowMajorT {  // A operand M^T or B operand M (fb(j,k) = M[k][j])
   const XT* p;
   int ld;
   __device__ double operator()(int i, int k) const { return (double)p[(int64_t)k * ld + i]; }
 };
 
-struct EOp {  // B(k, j) = E(k, j), passed as fb(j, k)
-  const double* S;
-  const double* G;
-  const double* lam;  // LDS
-  double delta;
-  int n;
-  __device__ double operator()(int j, int k) const {
-    const double g = G[(int64_t)k * n + j];
-    if (j == k) return 0.5 * (1.0 - g);
-    const double d = lam[j] - lam[k];
-    const double r = -g;
-    if (fabs(d) > delta) return (S[(int64_t)k * n + j] + lam[j] * r) / d;
-    return 0.5 * r;
+// Newton correction E(k,j) for k != j (R_kj/2 for a close pair), R_jj/2 on the diagonal
+__device__ __forceinline__ double newton_e(const double* S, const double* G, const double* lam, int n, int k,
+                                           int j) {
+  const double g = G[(int64_t)k * n + j];
+  if (j == k) return 0.5 * (1.0 - g);
+  const double r = -g;
+  const double d = fabs(lam[j] - lam[k]);
+  const double s = S[(int64_t)k * n + j];
+  const double num = s + lam[j] * r;
+  if (kCloseC * fabs(num) >= d || kCloseC * fabs(s + lam[k] * r) >= d) return 0.5 * r;
+  return num / (lam[j] - lam[k]);
+}
+
+// Per-item work-space (doubles): P1 | Y | S | G | W5 | W6, each n*n.
+struct WS {
+  double *P1, *Y, *S, *G, *W5, *W6;
+  __device__ WS(double* work, const ItemDev& it) {
+    const int64_t nn = (int64_t)it.n * it.n;
+    P1 = work + it.w_off;
+    Y = P1 + nn;
+    S = Y + nn;
+    G = S + nn;
+    W5 = G + nn;
+    W6 = W5 + nn;
   }
 };
 
-// ---------------------------------------------------------------------------
-// Newton-type step: X (row-major, XT) -> Xout (row-major, FP64), lam -> eval,
-// cluster starts -> cl.  Work-space per item: P1 | Y | S | G (4 n^2 doubles);
-// X and Xout are either the caller's array (offset v_off) or P1.
+// ------------------------------------------------------------ step kernels
+// grid: x = tile (tm * nt + tc), y = item
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void refine_step_kernel(const ItemDev* __restrict__ items,
-                                                             const GridDev* __restrict__ grids,
-                                                             const double* __restrict__ v64, const XT* xin,
-                                                             int xin_ws, double* evec, int xout_ws,
-                                                             double* __restrict__ eval, double* work,
-                                                             int32_t* __restrict__ cl) {
+__global__ __launch_bounds__(kBlock) void gemm_y_kernel(const ItemDev* __restrict__ items, int item0,
+                                                        const GridDev* __restrict__ grids,
+                                                        const double* __restrict__ v64, const XT* xin, int xin_ws,
+                                                        double* work) {
+  __shared__ double As[kTK * kLdT];
+  __shared__ double Bs[kTK * kLdT];
+  const ItemDev it = items[item0 + blockIdx.y];
+  const int n = it.n;
+  const int nt = (n + kTM - 1) / kTM;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int tm = blockIdx.x / nt, tc = blockIdx.x % nt;
+  const GridDev g = grids[it.grid];
+  const WS ws(work, it);
+  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
+  d4 acc[2][2];
+  gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, HOp{v64 + it.v_off, g.e0, n, it.N},
+                         RowMajorT<XT>{X, n}, acc);
+  double* Y = ws.Y;
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Y[(int64_t)r * n + c] = v; });
+}
+
+// S = X^T Y and G = X^T X on the upper tiles (tm <= tc), mirrored on store
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restrict__ items, int item0,
+                                                         const XT* xin, int xin_ws, double* work) {
+  __shared__ double As[kTK * kLdT];
+  __shared__ double Bs[kTK * kLdT];
+  const ItemDev it = items[item0 + blockIdx.y];
+  const int n = it.n;
+  const int nt = (n + kTM - 1) / kTM;
+  int t = blockIdx.x, tm = 0;
+  while (tm < nt && t >= nt - tm) {
+    t -= nt - tm;
+    ++tm;
+  }
+  if (tm >= nt) return;
+  const int tc = tm + t;
+  const WS ws(work, it);
+  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
+  d4 acc[2][2];
+  double* S = ws.S;
+  double* G = ws.G;
+  gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajorT<XT>{X, n}, RowMajorT<double>{ws.Y, n},
+                          acc);
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+    if (r > c) return;  // one writer per symmetric pair
+    S[(int64_t)r * n + c] = v;
+    S[(int64_t)c * n + r] = v;
+  });
+  gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajorT<XT>{X, n}, RowMajorT<XT>{X, n}, acc);
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+    if (r > c) return;
+    G[(int64_t)r * n + c] = v;
+    G[(int64_t)c * n + r] = v;
+  });
+}
+
+// X' = X M, M = I + E except chain columns (cl[j] >= 0), which are column cl[j]
+// of P Q (n x T in W6).  lam_pre holds the Rayleigh quotients E was built from.
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restrict__ items, int item0,
+                                                         const XT* xin, int xin_ws, double* evec, int xout_ws,
+                                                         const double* __restrict__ lam_pre, double* work,
+                                                         const int32_t* __restrict__ cl) {
   __shared__ double As[kTK * kLdT];
   __shared__ double Bs[kTK * kLdT];
   __shared__ double lam[kMaxN];
-  __shared__ double scratch[kBlock / 64];
-  const ItemDev it = items[blockIdx.x];
+  __shared__ int cpos[kMaxN];
+  __shared__ int s_T;
+  const ItemDev it = items[item0 + blockIdx.y];
   const int n = it.n;
-  const GridDev g = grids[it.grid];
-  const HOp H{v64 + it.v_off, g.e0, n, it.N};
-  const int64_t nn = (int64_t)n * n;
-  double* P1 = work + it.w_off;
-  double* Y = P1 + nn;
-  double* S = Y + nn;
-  double* Gm = S + nn;
-  const XT* X = xin_ws ? reinterpret_cast<const XT*>(P1) : (xin + it.v_off);
-  double* Xo = xout_ws ? P1 : (evec + it.v_off);
   const int nt = (n + kTM - 1) / kTM;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int tm = blockIdx.x / nt, tc = blockIdx.x % nt;
+  const WS ws(work, it);
+  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
+  double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
+  if (threadIdx.x == 0) s_T = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    lam[i] = lam_pre[it.e_off + i];
+    cpos[i] = cl[it.e_off + i];
+    if (cpos[i] >= 0) atomicMax(&s_T, cpos[i] + 1);
+  }
+  __syncthreads();
+  const int T = s_T;
+  const double* S = ws.S;
+  const double* G = ws.G;
+  const double* MC = ws.W6;
+  auto fb = [&](int j, int k) -> double {  // M(k, j)
+    const int q = cpos[j];
+    if (q >= 0) return MC[(int64_t)k * T + q];
+    return (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j);
+  };
   d4 acc[2][2];
-
-  // Y = A X
-  for (int tm = 0; tm < nt; ++tm)
-    for (int tc = 0; tc < nt; ++tc) {
-      gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, H, RowMajorT<XT>{X, n}, acc);
-      tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Y[(int64_t)r * n + c] = v; });
-    }
-  __syncthreads();
-  // S = X^T Y and G = X^T X (upper tiles only; mirrored on store)
-  for (int tm = 0; tm < nt; ++tm)
-    for (int tc = tm; tc < nt; ++tc) {
-      gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajorT<XT>{X, n}, RowMajorT<double>{Y, n},
-                              acc);
-      // upper triangle only, mirrored: one writer per symmetric pair (deterministic)
-      tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
-        if (r > c) return;
-        S[(int64_t)r * n + c] = v;
-        S[(int64_t)c * n + r] = v;
-      });
-      gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajorT<XT>{X, n}, RowMajorT<XT>{X, n}, acc);
-      tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
-        if (r > c) return;
-        Gm[(int64_t)r * n + c] = v;
-        Gm[(int64_t)c * n + r] = v;
-      });
-    }
-  __syncthreads();
-  // Rayleigh quotients, Frobenius norms and the cluster threshold
-  for (int i = threadIdx.x; i < n; i += kBlock) lam[i] = S[(int64_t)i * n + i] / Gm[(int64_t)i * n + i];
-  __syncthreads();
-  double s2 = 0.0, r2 = 0.0, a2 = 0.0;
-  for (int64_t e = threadIdx.x; e < nn; e += kBlock) {
-    const int r = (int)(e / n), c = (int)(e - (int64_t)r * n);
-    const double sv = S[e] - (r == c ? lam[r] : 0.0);
-    const double rv = (r == c ? 1.0 : 0.0) - Gm[e];
-    const double av = H(r, c);
-    s2 = fma(sv, sv, s2);
-    r2 = fma(rv, rv, r2);
-    a2 = fma(av, av, a2);
-  }
-  auto sum = [](double a, double b) { return a + b; };
-  s2 = block_reduce<kBlock>(s2, scratch, sum);
-  r2 = block_reduce<kBlock>(r2, scratch, sum);
-  a2 = block_reduce<kBlock>(a2, scratch, sum);
-  const double delta = 2.0 * (sqrt(s2) + sqrt(a2) * sqrt(r2));
-  // cluster starts: maximal runs of consecutive eigenvalues with gaps <= delta
-  if (threadIdx.x == 0) {
-    int start = 0;
-    int32_t* c = cl + it.e_off;
-    c[0] = 0;
-    for (int i = 1; i < n; ++i) {
-      if (!(lam[i] - lam[i - 1] <= delta)) start = i;
-      c[i] = start;
-    }
-  }
-  // X <- X + X E
-  for (int tm = 0; tm < nt; ++tm)
-    for (int tc = 0; tc < nt; ++tc) {
-      gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajor<XT>{X, n}, EOp{S, Gm, lam, delta, n},
-                             acc);
-      tile_store(tm * kTM, tc * kTM, n, n, acc,
-                 [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = (double)X[(int64_t)r * n + c] + v; });
-    }
-  for (int i = threadIdx.x; i < n; i += kBlock) eval[it.e_off + i] = lam[i];
+  gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajor<XT>{X, n}, fb, acc);
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
 }
 
-// ---------------------------------------------------------------------------
-// Rayleigh-Ritz inside clusters, batched in chunks of whole clusters of at
-// most kChunk columns.  X is row-major FP64 (in place).  Work-space: Z in the
-// S region (n x T, row stride T), Q in the G region (T x T); T <= n, so both fit
-// their n x n regions.
-__global__ __launch_bounds__(kBlock) void refine_cluster_kernel(const ItemDev* __restrict__ items,
-                                                                const GridDev* __restrict__ grids,
-                                                                const double* __restrict__ v64, double* xbase,
-                                                                int x_ws, double* __restrict__ eval, double* work,
-                                                                const int32_t* __restrict__ cl,
-                                                                int32_t* __restrict__ status) {
+// ------------------------------------------------------------ chain kernel
+// One work-group per item: Rayleigh quotients, close pairs and chains, and the
+// Rayleigh-Ritz rotation of every chain.  Chains are processed in batches of
+// whole chains with at most kMaxChain columns; for a batch with columns
+// cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb), P^T S P -> LDS (kept
+// block-diagonal, one block per chain), one-sided Jacobi, Q -> LDS, and P Q ->
+// columns [pos, pos + Tb) of the n x Ttot matrix in W6.  Writes the quotients
+// to lam_pre, the refined eigenvalues to eval, and cl[j] = position of column
+// j among all chain columns, or -1.
+__global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __restrict__ items,
+                                                              double* __restrict__ lam_pre,
+                                                              double* __restrict__ eval, double* work,
+                                                              int32_t* __restrict__ cl,
+                                                              int32_t* __restrict__ status) {
+  constexpr int ldw = kMaxChain | 1;
   __shared__ double As[kTK * kLdT];
   __shared__ double Bs[kTK * kLdT];
-  __shared__ double W[kChunk * (kChunk | 1)];
-  __shared__ double shift[kChunk];
-  __shared__ double nrm[kChunk];
-  __shared__ int cols[kChunk];
-  __shared__ int blk[kChunk];  // first chunk position of each column's cluster
+  __shared__ double lam[kMaxN];
+  __shared__ int reach[kMaxN];
+  __shared__ short ch_start[kMaxN / 2];
+  __shared__ short ch_len[kMaxN / 2];
+  __shared__ double W[kMaxChain * ldw];
+  __shared__ double Qs[kMaxChain * kMaxChain];
+  __shared__ double shift[kMaxChain];
+  __shared__ double nrm[kMaxChain];
+  __shared__ int cols[kMaxChain];
+  __shared__ int blk[kMaxChain];
   __shared__ int rot_flag[64];
-  __shared__ int s_chunk_len, s_next, s_fail;
+  __shared__ int s_Ttot, s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
-  const GridDev g = grids[it.grid];
-  const HOp H{v64 + it.v_off, g.e0, n, it.N};
-  const int64_t nn = (int64_t)n * n;
-  double* P1 = work + it.w_off;
-  double* Z = P1 + 2 * nn;  // S region
-  double* Q = P1 + 3 * nn;  // G region
-  double* X = x_ws ? P1 : (xbase + it.v_off);
-  const int32_t* c = cl + it.e_off;
-  double* ev = eval + it.e_off;
-  constexpr int ldw = kChunk | 1;
-  if (threadIdx.x == 0) {
-    s_next = 0;
-    s_fail = 0;
+  const WS ws(work, it);
+  const double* S = ws.S;
+  const double* G = ws.G;
+  for (int i = threadIdx.x; i < n; i += kBlock) lam[i] = S[(int64_t)i * n + i] / G[(int64_t)i * n + i];
+  __syncthreads();
+  // reach[p] = largest q > p with (p, q) close, else p: one wavefront per row p,
+  // lanes over q (coalesced row reads), then a wavefront max
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int p = wave; p < n; p += kBlock / 64) {
+      int rq = p;
+      for (int q = p + 1 + lane; q < n; q += 64) {
+        const double r = -G[(int64_t)p * n + q];
+        const double s = S[(int64_t)p * n + q];
+        const double d = fabs(lam[q] - lam[p]);
+        if (kCloseC * fabs(s + lam[q] * r) >= d || kCloseC * fabs(s + lam[p] * r) >= d) rq = q;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(rq, off, 64);
+        rq = o > rq ? o : rq;
+      }
+      if (lane == 0) reach[p] = rq;
+    }
+    for (int p = threadIdx.x; p < n; p += kBlock) lam_pre[it.e_off + p] = lam[p];
   }
   __syncthreads();
-  while (true) {
-    // gather the next chunk of whole clusters (size >= 2)
-    if (threadIdx.x == 0) {
-      int i = s_next, len = 0;
-      while (i < n) {
-        int j = i + 1;
-        while (j < n && c[j] == i) ++j;
-        const int m = j - i;
-        if (m >= 2) {
-          if (m > kChunk) {  // too large for one Rayleigh-Ritz batch: leave it refined by Newton only
-            s_fail = 1;
-          } else if (len + m > kChunk) {
-            break;
-          } else {
-            for (int q = 0; q < m; ++q) {
-              cols[len + q] = i + q;
-              blk[len + q] = len;
-            }
-            len += m;
-          }
-        }
-        i = j;
+  // chains = unions of overlapping [p, reach[p]] with at least two columns
+  if (threadIdx.x == 0) {
+    int T = 0, fail = 0, i = 0, nch = 0;
+    int32_t* c = cl + it.e_off;
+    while (i < n) {
+      int j = reach[i], q = i;
+      while (q <= j) {
+        j = reach[q] > j ? reach[q] : j;
+        ++q;
       }
-      s_next = i;
-      s_chunk_len = len;
+      const int m = j - i + 1;
+      if (m >= 2 && m <= kMaxChain) {
+        for (int t = 0; t < m; ++t) c[i + t] = T + t;
+        ch_start[nch] = (short)i;
+        ch_len[nch] = (short)m;
+        ++nch;
+        T += m;
+      } else {
+        if (m > kMaxChain) fail = 1;  // one chain larger than a Rayleigh-Ritz batch
+        for (int t = 0; t < m; ++t) c[i + t] = -1;
+      }
+      i = j + 1;
+    }
+    s_Ttot = T;
+    s_nch = nch;
+    s_fail = fail;
+    s_c1 = 0;
+    s_pos = 0;
+  }
+  __syncthreads();
+  const int Ttot = s_Ttot;
+  const int nch = s_nch;
+  const int nt = (n + kTM - 1) / kTM;
+  double* P = ws.W5;   // n x Tb
+  double* SP = ws.Y;   // n x Tb
+  double* MC = ws.W6;  // n x Ttot
+  d4 acc[2][2];
+  while (true) {
+    // next batch: chains [c0, c1) with at most kMaxChain columns in total
+    if (threadIdx.x == 0) {
+      const int c0 = s_c1;
+      int c1 = c0, Tb = 0;
+      while (c1 < nch && Tb + ch_len[c1] <= kMaxChain) {
+        for (int t = 0; t < ch_len[c1]; ++t) {
+          cols[Tb + t] = ch_start[c1] + t;
+          blk[Tb + t] = Tb;
+        }
+        Tb += ch_len[c1];
+        ++c1;
+      }
+      s_c0 = c0;
+      s_c1 = c1;
+      s_Tb = Tb;
     }
     __syncthreads();
-    const int T = s_chunk_len;
-    if (T == 0) break;
-    d4 acc[2][2];
-    // Z = A X[:, cols]   (n x T)
-    const int nt = (n + kTM - 1) / kTM;
-    auto xcols = [&](int j, int k) { return X[(int64_t)k * n + cols[j]]; };  // B(k, j) = X(k, cols[j])
+    const int Tb = s_Tb;
+    if (Tb == 0) break;
+    const int pos = s_pos;
+    for (int64_t e = threadIdx.x; e < (int64_t)n * Tb; e += kBlock) {
+      const int k = (int)(e / Tb), t = (int)(e - (int64_t)k * Tb);
+      const int j = cols[t];
+      P[e] = (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j);
+    }
+    __syncthreads();
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile<true, false>(As, Bs, tm * kTM, 0, n, T, n, H, xcols, acc);
-      tile_store(tm * kTM, 0, n, T, acc, [&](int r, int cc, double v) { Z[(int64_t)r * T + cc] = v; });
+      gemm_tile<true, false>(As, Bs, tm * kTM, 0, n, Tb, n, RowMajor<double>{S, n}, RowMajorT<double>{P, Tb}, acc);
+      tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { SP[(int64_t)r * Tb + cc] = v; });
     }
     __syncthreads();
-    // S_c = X[:, cols]^T Z, kept block-diagonal, into W (column-major)
-    {
-      auto xt = [&](int i, int k) { return X[(int64_t)k * n + cols[i]]; };  // A(i, k) = X(k, cols[i])
-      auto zc = [&](int j, int k) { return Z[(int64_t)k * T + j]; };
-      gemm_tile<false, false>(As, Bs, 0, 0, T, T, n, xt, zc, acc);
-      tile_store(0, 0, T, T, acc, [&](int r, int cc, double v) { W[cc * ldw + r] = (blk[r] == blk[cc]) ? v : 0.0; });
-    }
+    gemm_tile<false, false>(As, Bs, 0, 0, Tb, Tb, n, RowMajorT<double>{P, Tb}, RowMajorT<double>{SP, Tb}, acc);
+    tile_store(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
+      if (r > cc) return;  // symmetric: one writer per pair
+      const double w = (blk[r] == blk[cc]) ? v : 0.0;
+      W[cc * ldw + r] = w;
+      W[r * ldw + cc] = w;
+    });
     if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
     __syncthreads();
-    // per-block Gershgorin shift making every block positive definite
-    for (int j = threadIdx.x; j < T; j += kBlock) {
-      if (blk[j] != j) continue;  // one thread per block, at its first column
+    // per-chain Gershgorin shift making every diagonal block positive definite
+    for (int j = threadIdx.x; j < Tb; j += kBlock) {
+      if (blk[j] != j) continue;
       int e = j + 1;
-      while (e < T && blk[e] == j) ++e;
+      while (e < Tb && blk[e] == j) ++e;
       double lo = DBL_MAX, hi = -DBL_MAX;
       for (int q = j; q < e; ++q) {
         double s = 0.0;
@@ -354,90 +456,134 @@ __global__ __launch_bounds__(kBlock) void refine_cluster_kernel(const ItemDev* _
       for (int q = j; q < e; ++q) shift[q] = sh;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < T; j += kBlock) W[j * ldw + j] += shift[j];
+    for (int j = threadIdx.x; j < Tb; j += kBlock) W[j * ldw + j] += shift[j];
     __syncthreads();
-    const int sw = onesided_jacobi_lds<double, kBlock, 4, 16>(W, T, ldw, 1e-15, 40, rot_flag);
+    const int sw = onesided_jacobi_lds<double, kBlock, 8, 8>(W, Tb, ldw, 1e-15, 40, rot_flag);
     if (sw > 40 && threadIdx.x == 0) s_fail = 1;
-    for (int j = threadIdx.x; j < T; j += kBlock) {
+    for (int j = threadIdx.x; j < Tb; j += kBlock) {
       double s2 = 0.0;
-      for (int r = 0; r < T; ++r) s2 = fma(W[j * ldw + r], W[j * ldw + r], s2);
+      for (int r = 0; r < Tb; ++r) s2 = fma(W[j * ldw + r], W[j * ldw + r], s2);
       nrm[j] = sqrt(s2);
     }
     __syncthreads();
-    // Q(:, rank) = w_j/|w_j| with the rank taken inside the block; eigenvalue |w_j| - shift
-    for (int j = threadIdx.x; j < T; j += kBlock) {
+    // Q(:, rank) = w_j/|w_j| with the rank inside the chain; eigenvalue |w_j| - shift
+    for (int j = threadIdx.x; j < Tb; j += kBlock) {
       const int b0 = blk[j];
       const double lj = nrm[j] - shift[j];
       int rank = b0;
-      for (int q = b0; q < T && blk[q] == b0; ++q) {
+      for (int q = b0; q < Tb && blk[q] == b0; ++q) {
         const double lq = nrm[q] - shift[q];
         rank += (lq < lj || (lq == lj && q < j)) ? 1 : 0;
       }
-      const double inv = 1.0 / nrm[j];
-      for (int r = 0; r < T; ++r) Q[(int64_t)r * T + rank] = W[j * ldw + r] * inv;
-      ev[cols[rank]] = lj;
+      for (int r = 0; r < Tb; ++r) Qs[r * kMaxChain + rank] = W[j * ldw + r] / nrm[j];
+      lam[cols[rank]] = lj;
     }
     __syncthreads();
-    // X[:, cols] <- X[:, cols] Q, through Z as staging
-    auto xa = [&](int i, int k) { return X[(int64_t)i * n + cols[k]]; };  // A(i, k) = X(i, cols[k])
-    auto qb = [&](int j, int k) { return Q[(int64_t)k * T + j]; };
+    // P Q -> chain columns [pos, pos + Tb) of MC
+    auto qb = [&](int j, int k) { return Qs[k * kMaxChain + j]; };  // B(k, j) = Q[k][j]
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile<false, false>(As, Bs, tm * kTM, 0, n, T, T, xa, qb, acc);
-      tile_store(tm * kTM, 0, n, T, acc, [&](int r, int cc, double v) { Z[(int64_t)r * T + cc] = v; });
+      gemm_tile<true, false>(As, Bs, tm * kTM, 0, n, Tb, Tb, RowMajor<double>{P, Tb}, qb, acc);
+      tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
     }
     __syncthreads();
-    for (int64_t e = threadIdx.x; e < (int64_t)n * T; e += kBlock) {
-      const int r = (int)(e / T), cc = (int)(e - (int64_t)r * T);
-      X[(int64_t)r * n + cols[cc]] = Z[(int64_t)r * T + cc];
-    }
+    if (threadIdx.x == 0) s_pos = pos + Tb;
     __syncthreads();
   }
+  for (int i = threadIdx.x; i < n; i += kBlock) eval[it.e_off + i] = lam[i];
   if (threadIdx.x == 0 && s_fail && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
-// Final pass: copy X from the work-space when the last step left it there, and
-// check the eigenvalues are ascending and finite.
+// ------------------------------------------------------------ finish
+// Sort the eigenpairs by eigenvalue (ties by index) and write them to the
+// caller's arrays; X is read from the work-space (x_ws) or from evec (then
+// staged through Y when a permutation is needed).
 __global__ __launch_bounds__(kBlock) void refine_finish_kernel(const ItemDev* __restrict__ items, double* evec,
-                                                               int x_ws, const double* work,
-                                                               const double* __restrict__ eval,
+                                                               int x_ws, double* work, double* __restrict__ eval,
                                                                int32_t* __restrict__ status) {
-  __shared__ int bad;
+  __shared__ double lam[kMaxN];
+  __shared__ int rank[kMaxN];
+  __shared__ int s_perm, s_bad;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  if (x_ws) {
-    const double* src = work + it.w_off;
-    double* dst = evec + it.v_off;
-    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kBlock) dst[e] = src[e];
+  const WS ws(work, it);
+  double* ev = eval + it.e_off;
+  double* X = evec + it.v_off;
+  if (threadIdx.x == 0) {
+    s_perm = 0;
+    s_bad = 0;
   }
-  const double* ev = eval + it.e_off;
+  __syncthreads();
   for (int i = threadIdx.x; i < n; i += kBlock) {
-    if (!isfinite(ev[i]) || (i > 0 && ev[i] < ev[i - 1])) bad = 1;
+    lam[i] = ev[i];
+    if (!isfinite(lam[i])) atomicOr(&s_bad, 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    int r = 0;
+    for (int q = 0; q < n; ++q) r += (lam[q] < lam[i] || (lam[q] == lam[i] && q < i)) ? 1 : 0;
+    rank[i] = r;
+    if (r != i) atomicOr(&s_perm, 1);
+  }
+  __syncthreads();
+  const int64_t nn = (int64_t)n * n;
+  const double* src = X;
+  if (x_ws) {
+    src = ws.P1;
+  } else if (s_perm) {
+    for (int64_t e = threadIdx.x; e < nn; e += kBlock) ws.Y[e] = X[e];
+    __syncthreads();
+    src = ws.Y;
+  }
+  if (x_ws || s_perm) {
+    for (int64_t e = threadIdx.x; e < nn; e += kBlock) {
+      const int r = (int)(e / n), c = (int)(e - (int64_t)r * n);
+      X[(int64_t)r * n + rank[c]] = src[e];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) ev[rank[i]] = lam[i];
+  if (threadIdx.x == 0 && s_bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
 }  // namespace
 
-hipError_t launch_refine(const ItemDev* items, int n_items, const GridDev* grids, const double* v64,
-                         const float* x32, double* evec, double* eval, double* work, int32_t* cl, int32_t* status,
-                         int steps, hipStream_t s) {
-  // X ping-pongs between the caller's evec (ws = 0) and the work-space P1 (ws = 1)
-  int cur_ws = 0;
+hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
+                         const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
+                         int32_t* status, int steps, hipStream_t s) {
+  if (max_n > kMaxN) return hipErrorInvalidValue;
+  const int nt = (max_n + kTM - 1) / kTM;
+  const int tiles = nt * nt, up_tiles = nt * (nt + 1) / 2;
+  int cur_ws = 0;  // X in the caller's evec (0) or in the work-space P1 (1); step 0 reads x32
   for (int st = 0; st < steps; ++st) {
     const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
-    if (st == 0)
-      hipLaunchKernelGGL(refine_step_kernel<float>, dim3(n_items), dim3(kBlock), 0, s, items, grids, v64, x32, 0,
-                         evec, out_ws, eval, work, cl);
-    else
-      hipLaunchKernelGGL(refine_step_kernel<double>, dim3(n_items), dim3(kBlock), 0, s, items, grids, v64,
-                         (const double*)evec, cur_ws, evec, out_ws, eval, work, cl);
+    for (int i0 = 0; i0 < n_items; i0 += 65535) {
+      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+      if (st == 0) {
+        hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, grids, v64, x32, 0,
+                           work);
+        hipLaunchKernelGGL(gemm_sg_kernel<float>, dim3(up_tiles, gy), dim3(kBlock), 0, s, items, i0, x32, 0, work);
+      } else {
+        hipLaunchKernelGGL(gemm_y_kernel<double>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, grids, v64,
+                           (const double*)evec, cur_ws, work);
+        hipLaunchKernelGGL(gemm_sg_kernel<double>, dim3(up_tiles, gy), dim3(kBlock), 0, s, items, i0,
+                           (const double*)evec, cur_ws, work);
+      }
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(refine_cluster_kernel, dim3(n_items), dim3(kBlock), 0, s, items, grids, v64, evec, out_ws,
-                       eval, work, cl, status);
+    hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
+                       status);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int i0 = 0; i0 < n_items; i0 += 65535) {
+      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+      if (st == 0)
+        hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, x32, 0, evec,
+                           out_ws, lam_pre, work, cl);
+      else
+        hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0,
+                           (const double*)evec, cur_ws, evec, out_ws, lam_pre, work, cl);
+    }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     cur_ws = out_ws;

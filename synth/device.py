@@ -22,9 +22,13 @@ def pack_host_matrices(u_elems: int, u_off, mats, dtype, device="cuda") -> torch
 
 
 def pack_coupled_yukawa(u_elems: int, u_off, nodes: np.ndarray, coeffs: np.ndarray, dtype, device="cuda",
-                        J: int = 1, chunk: int = 64) -> torch.Tensor:
-    """Items i = 0..len(coeffs)-1 of equal size with contiguous offsets."""
-    terms = configs.coupled_yukawa_terms(nodes, J)
+                        J: int = 1, chunk: int = 64, terms=None) -> torch.Tensor:
+    """Items i = 0..len(coeffs)-1 of equal size with contiguous offsets.
+
+    ``terms`` may pass precomputed ``configs.coupled_yukawa_terms(nodes, J)``.
+    """
+    if terms is None:
+        terms = configs.coupled_yukawa_terms(nodes, J)
     t = torch.from_numpy(np.stack([x.ravel() for x in terms])).to(device)
     per = t.shape[1]
     u_off = np.asarray(u_off)
