@@ -71,7 +71,8 @@ enum {
 };
 
 /* Arithmetic of the eigensolver and T contraction.
- * WPCD_MIXED: FP32 one-sided Jacobi held in LDS, then FP64 refinement of every
+ * WPCD_MIXED: FP32 one-sided Jacobi (held in LDS for n <= 200, in the batch's
+ *             device workspace above), then FP64 refinement of every
  *             eigenpair; FP32 T contraction over an FP64 resolvent table.
  * WPCD_F64:   FP64 one-sided Jacobi in device memory, FP64 T contraction.   */
 enum { WPCD_MIXED = 0, WPCD_F64 = 1 };
@@ -86,7 +87,9 @@ typedef struct {
   int32_t max_sweeps;    /* Jacobi sweep cap (default 30)                       */
   int32_t refine_steps;  /* FP64 refinement steps in WPCD_MIXED (default 2, 0..4) */
   double jacobi_tol_f32; /* one-sided Jacobi: skip a pair once |w_p.w_q| <=
-                            tol*|w_p||w_q| (FP32 path; default 2e-7)            */
+                            tol*|w_p||w_q|; a sweep whose largest rotated pair
+                            was below 8*tol ends the iteration (FP32 path;
+                            default 2e-7)                                      */
   double jacobi_tol_f64; /* same for the FP64 path (default 1e-15)              */
 } wpcd_config;
 

@@ -214,6 +214,7 @@ void wpcd_batch_destroy(wpcd_batch b) {
   hipFree(b->d_work);
   hipFree(b->d_cl);
   hipFree(b->d_lam);
+  hipFree(b->d_class);
   delete b;
 }
 
@@ -285,6 +286,20 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
     for (int i = 0; i < n_items; ++i) sitems[fill[items_host[i].sample_id]++] = i;
   }
+  // size classes of the eigensolver
+  std::vector<int32_t> cls(n_items);
+  {
+    int cnt[kNumClasses] = {0};
+    for (int i = 0; i < n_items; ++i) {
+      const int c = size_class(b->h_items[i].n);
+      cnt[c]++;
+      b->class_maxn[c] = std::max(b->class_maxn[c], b->h_items[i].n);
+    }
+    for (int c = 0; c < kNumClasses; ++c) b->class_ptr[c + 1] = b->class_ptr[c] + cnt[c];
+    int fill[kNumClasses];
+    for (int c = 0; c < kNumClasses; ++c) fill[c] = b->class_ptr[c];
+    for (int i = 0; i < n_items; ++i) cls[fill[size_class(b->h_items[i].n)]++] = i;
+  }
   std::vector<GridDev> gd(ctx->grids.size());
   for (size_t i = 0; i < gd.size(); ++i) gd[i] = ctx->grids[i].dev;
   hipError_t e = hipSuccess;
@@ -299,12 +314,14 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   alloc((void**)&b->d_work, sizeof(double) * b->work_doubles);
   alloc((void**)&b->d_cl, sizeof(int32_t) * b->eval_elems);
   alloc((void**)&b->d_lam, sizeof(double) * b->eval_elems);
+  alloc((void**)&b->d_class, sizeof(int32_t) * n_items);
   if (e == hipSuccess) e = hipMemcpy(b->d_items, b->h_items.data(), sizeof(ItemDev) * n_items, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_grids, gd.data(), sizeof(GridDev) * gd.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_sample_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_sample_items, sitems.data(), sizeof(int32_t) * sitems.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_class, cls.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     wpcd_batch_destroy(b);
     return hip_fail(e, "wpcd_batch_create");
@@ -361,15 +378,27 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
   const wpcd_config& c = b->ctx->cfg;
   if (mode == WPCD_MIXED) {
-    if (b->max_n > kMaxLdsN)
-      return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED holds n <= %d in LDS (batch has n = %d)", kMaxLdsN,
-                  b->max_n);
     if (c.refine_steps < 1)
       return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED needs refine_steps >= 1");
+    // one FP32 Jacobi launch per size class: LDS-resident up to n = kMaxLdsN,
+    // device memory above
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream,
                    [&] {
-                     return launch_jacobi_f32_lds(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, eval,
-                                                  status, c.max_sweeps, (float)c.jacobi_tol_f32, stream);
+                     hipError_t e = hipSuccess;
+                     for (int k = 0; k < kNumClasses && e == hipSuccess; ++k) {
+                       const int n_sel = b->class_ptr[k + 1] - b->class_ptr[k];
+                       const int32_t* sel = b->d_class + b->class_ptr[k];
+                       if (n_sel == 0) continue;
+                       if (k < kNumClasses - 1)
+                         e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
+                                                   b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
+                                                   stream);
+                       else
+                         e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
+                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
+                                                  c.jacobi_tol_f32, stream);
+                     }
+                     return e;
                    }),
              "wpcd_eigh: FP32 Jacobi launch");
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_REFINE, stream,
@@ -381,8 +410,9 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
   } else {
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F64, stream,
                    [&] {
-                     return launch_jacobi_f64_global(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_work, evec,
-                                                     eval, status, c.max_sweeps, c.jacobi_tol_f64, stream);
+                     return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids, v64,
+                                                 b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
+                                                 c.jacobi_tol_f64, stream);
                    }),
              "wpcd_eigh: FP64 Jacobi launch");
   }

@@ -78,8 +78,12 @@ __device__ __forceinline__ void hestenes_rotation(T al, T be, T ga, T& c, T& s) 
 // threads in lane groups of G; each group owns one column pair per step and
 // keeps it in registers (RMAX >= ceil(n/G) rows per lane).  A pair is rotated
 // while |w_p.w_q| > tol |w_p||w_q|.  rot_flag must point to max_sweeps zeroed
-// shared ints.  Returns the number of sweeps run, or max_sweeps + 1 if the last
-// allowed sweep still rotated (not converged).  Ends with a barrier.
+// shared ints; each records the largest rotated |w_p.w_q|/(|w_p||w_q|) of its
+// sweep (as the bits of a non-negative float, so integer max is float max).
+// The iteration ends after a sweep that rotated nothing or only pairs below
+// 8 tol (rounding-level rotations that would otherwise recur).  Returns the
+// number of sweeps run, or max_sweeps + 1 if the last allowed sweep still
+// rotated larger pairs (not converged).  Ends with a barrier.
 template <typename T, int BLOCK, int G, int RMAX>
 __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag) {
   const int npair = (n + 1) >> 1;
@@ -115,7 +119,8 @@ __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, i
         al = group_sum<G>(al);
         be = group_sum<G>(be);
         ga = group_sum<G>(ga);
-        if (fabs(ga) > tol * sqrt(al * be)) {
+        const T nab = sqrt(al * be);
+        if (fabs(ga) > tol * nab) {
           T c, s;
           hestenes_rotation(al, be, ga, c, s);
 #pragma unroll
@@ -126,12 +131,12 @@ __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, i
               wq[r] = s * xp[k] + c * xq[k];
             }
           }
-          if (lane == 0) rot_flag[sweep] = 1;
+          if (lane == 0) atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
         }
       }
       __syncthreads();
     }
-    if (rot_flag[sweep] == 0) return sweep + 1;
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
   }
   return max_sweeps + 1;
 }

@@ -45,5 +45,10 @@ struct wpcd_batch_s {
   double* d_work = nullptr;
   int32_t* d_cl = nullptr;
   double* d_lam = nullptr;  // Rayleigh quotients of the current refinement step
+  // items grouped by eigensolver size class (wpcd::size_class); class c holds
+  // d_class[class_ptr[c] .. class_ptr[c+1]) with largest n class_maxn[c]
+  int32_t* d_class = nullptr;
+  int class_ptr[wpcd::kNumClasses + 1] = {0};
+  int class_maxn[wpcd::kNumClasses] = {0};
 };
 

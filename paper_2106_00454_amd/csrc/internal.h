@@ -44,6 +44,10 @@ struct ItemDev {
 
 // Largest matrix the FP32 LDS eigensolver holds (n*n floats must fit 160 KiB).
 constexpr int kMaxLdsN = 200;
+// Size classes of the eigensolver launches: n <= 64, <= 128, <= 200 (LDS) and
+// larger (device memory).
+constexpr int kNumClasses = 4;
+inline int size_class(int n) { return n <= 64 ? 0 : (n <= 128 ? 1 : (n <= kMaxLdsN ? 2 : 3)); }
 // Largest item the library accepts in this build.
 constexpr int kMaxN = 1200;
 // Largest cluster handled by one Rayleigh-Ritz solve in the refinement.
@@ -52,12 +56,12 @@ constexpr int kMaxCluster = 64;
 // Kernel launchers (each returns hipSuccess or the launch error).
 hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const void* u,
                           int u_dtype, double* v64, hipStream_t s);
-hipError_t launch_jacobi_f32_lds(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
-                                 const double* v64, float* evec32, double* eval, int32_t* status, int max_sweeps,
-                                 float tol, hipStream_t s);
-hipError_t launch_jacobi_f64_global(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
-                                    const double* v64, double* work, double* evec, double* eval, int32_t* status,
-                                    int max_sweeps, double tol, hipStream_t s);
+hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
+                                 const GridDev* grids, const double* v64, float* x32, double* eval,
+                                 int32_t* status, int max_sweeps, float tol, hipStream_t s);
+hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
+                                const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
+                                double* eval, int32_t* status, int max_sweeps, double tol, hipStream_t s);
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                          const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
                          int32_t* status, int steps, hipStream_t s);

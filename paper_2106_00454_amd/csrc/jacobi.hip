@@ -11,9 +11,9 @@
 //  * jacobi_f32_lds_kernel: one work-group per item, W in LDS, FP32.  Output:
 //    eigenvalues (FP64 array, FP32 accuracy) and eigenvectors as a row-major
 //    FP32 workspace X[r*n + m], both sorted by ascending eigenvalue.
-//  * jacobi_f64_global_kernel: same iteration in FP64 with W in device memory
-//    (the plain path; any n).  Output written straight to the caller's
-//    eigenvalue and row-major eigenvector arrays.
+//  * jacobi_global_kernel: same iteration with W in device memory (any n), in
+//    FP64 for the plain path (output straight to the caller's arrays) or in
+//    FP32 for mixed-path items too large for LDS (output as above).
 #include <float.h>
 
 #include "devutil.h"
@@ -50,8 +50,15 @@ __device__ T gershgorin_shift(const T* W, int n, int ld, T* scratch) {
   return base + T(0.05) * (hi - lo);
 }
 
+// Column stride of W in LDS: the smallest ld >= n with ld = 8 (mod 64).  In a
+// round-robin step the 8 lane groups of a wavefront read 8 consecutive columns
+// (rows lane + 8t), so column starts 8 banks apart make the 8 groups cover 64
+// distinct banks: conflict-free on 64 banks, the minimal two passes on 32.
+__host__ __device__ constexpr int lds_stride(int n) { return n + ((8 - n) % 64 + 64) % 64; }
+
 template <int BLOCK, int G, int RMAX>
 __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __restrict__ items,
+                                                               const int32_t* __restrict__ sel,
                                                                const GridDev* __restrict__ grids,
                                                                const double* __restrict__ v64,
                                                                float* __restrict__ x32, double* __restrict__ eval,
@@ -63,9 +70,10 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   __shared__ float scratch[BLOCK / 64];
   __shared__ int bad;
 
-  const ItemDev it = items[blockIdx.x];
+  const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
+  const ItemDev it = items[item];
   const int n = it.n, N = it.N;
-  const int ld = n | 1;  // odd column stride spreads column starts over the LDS banks
+  const int ld = lds_stride(n);
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
   for (int i = threadIdx.x; i < 64; i += BLOCK) rot_flag[i] = 0;
@@ -118,28 +126,38 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   }
   __syncthreads();
   if (threadIdx.x == 0)
-    status[blockIdx.x] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
+    status[item] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
 }
 
-// ---------------------------------------------------------------- FP64 path
-template <int BLOCK, int G>
-__global__ __launch_bounds__(BLOCK) void jacobi_f64_global_kernel(const ItemDev* __restrict__ items,
-                                                                  const GridDev* __restrict__ grids,
-                                                                  const double* __restrict__ v64,
-                                                                  double* __restrict__ work,
-                                                                  double* __restrict__ evec,
-                                                                  double* __restrict__ eval,
-                                                                  int32_t* __restrict__ status, int max_sweeps,
-                                                                  double tol) {
+// ---------------------------------------------------------- device-memory path
+// W (n x n, column-major) lives in the item's device work-space; every pair
+// step reads its two columns twice (Gram entries, then rotation) through the
+// caches.  T = double: the plain FP64 path, eigenvalues as Rayleigh quotients
+// v^T H v / v^T v of v = w/|w| (exact for a diagonal H, free of the shift's
+// rounding), eigenvectors written straight to the caller's FP64 array.
+// T = float: the mixed path for items too large for LDS; eigenvalues |w| - sigma
+// and FP32 eigenvectors in the row-major work-space x32, as the LDS kernel.
+template <typename T, int BLOCK, int G>
+__global__ __launch_bounds__(BLOCK) void jacobi_global_kernel(const ItemDev* __restrict__ items,
+                                                              const int32_t* __restrict__ sel,
+                                                              const GridDev* __restrict__ grids,
+                                                              const double* __restrict__ v64, double* work,
+                                                              double* __restrict__ evec, float* __restrict__ x32,
+                                                              double* __restrict__ eval,
+                                                              int32_t* __restrict__ status, int max_sweeps, T tol) {
   __shared__ int rot_flag[64];
-  __shared__ double scratch[BLOCK / 64];
+  __shared__ T scratch[BLOCK / 64];
   __shared__ int bad;
-  const ItemDev it = items[blockIdx.x];
+  __shared__ int rank_of[kMaxN];
+  __shared__ double rq[kMaxN];
+  __shared__ double nrm[kMaxN];
+  const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
+  const ItemDev it = items[item];
   const int n = it.n, N = it.N;
   const int ld = n;
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
-  double* W = work + it.w_off;
+  T* W = reinterpret_cast<T*>(work + it.w_off);
   for (int i = threadIdx.x; i < 64; i += BLOCK) rot_flag[i] = 0;
   if (threadIdx.x == 0) bad = 0;
   const int64_t nn = (int64_t)n * n;
@@ -147,10 +165,10 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f64_global_kernel(const ItemDev*
     const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
     double h = V[e];
     if (r == c) h += g.e0[r % N];
-    W[e] = h;
+    W[e] = (T)h;
   }
   __syncthreads();
-  const double sigma = gershgorin_shift<double, BLOCK>(W, n, ld, scratch);
+  const T sigma = gershgorin_shift<T, BLOCK>(W, n, ld, scratch);
   for (int c = threadIdx.x; c < n; c += BLOCK) W[(int64_t)c * ld + c] += sigma;
   __syncthreads();
 
@@ -163,11 +181,11 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f64_global_kernel(const ItemDev*
       for (int pr = grp; pr < npair; pr += ngrp) {
         const int p = rr_index(pr, step, ne), q = rr_index(ne - 1 - pr, step, ne);
         if (p >= n || q >= n) continue;
-        double* wp = W + (int64_t)p * ld;
-        double* wq = W + (int64_t)q * ld;
-        double al = 0, be = 0, ga = 0;
+        T* wp = W + (int64_t)p * ld;
+        T* wq = W + (int64_t)q * ld;
+        T al = 0, be = 0, ga = 0;
         for (int r = lane; r < n; r += G) {
-          const double a = wp[r], b = wq[r];
+          const T a = wp[r], b = wq[r];
           al = fma(a, a, al);
           be = fma(b, b, be);
           ga = fma(a, b, ga);
@@ -175,53 +193,51 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f64_global_kernel(const ItemDev*
         al = group_sum<G>(al);
         be = group_sum<G>(be);
         ga = group_sum<G>(ga);
-        if (fabs(ga) > tol * sqrt(al * be)) {
-          double c, s;
+        const T nab = sqrt(al * be);
+        if (fabs(ga) > tol * nab) {
+          T c, s;
           hestenes_rotation(al, be, ga, c, s);
           for (int r = lane; r < n; r += G) {
-            const double a = wp[r], b = wq[r];
+            const T a = wp[r], b = wq[r];
             wp[r] = c * a - s * b;
             wq[r] = s * a + c * b;
           }
-          if (lane == 0) rot_flag[sweep] = 1;
+          if (lane == 0) atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
         }
       }
       __syncthreads();
     }
-    if (rot_flag[sweep] == 0) {
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) {
       sweeps = sweep + 1;
       break;
     }
   }
-  // Column norms, then eigenvalues as Rayleigh quotients w^T H w / |w|^2 of the
-  // converged columns (H = V + diag(e0), read from device memory): exact for a
-  // diagonal H and free of the shift's rounding.  Staged in the eigenvalue
-  // array (norm) and in rank_of's companion array (quotient) before sorting.
-  __shared__ int rank_of[kMaxN];
-  __shared__ double rq[kMaxN];
-  double* ev = eval + it.e_off;
+  // column norms and eigenvalue estimates
   for (int c = grp; c < n; c += ngrp) {
-    const double* col = W + (int64_t)c * ld;
-    double s2 = 0;
+    const T* col = W + (int64_t)c * ld;
+    T s2 = 0;
     for (int r = lane; r < n; r += G) s2 = fma(col[r], col[r], s2);
-    const double nc = sqrt(group_sum<G>(s2));
-    // v = w/|w| by division, so an unrotated column is an exact unit vector and
-    // the quotient v^T H v / v^T v reproduces a diagonal entry exactly
-    double q = 0, vv = 0;
-    for (int r = lane; r < n; r += G) {
-      const double* hrow = V + (int64_t)r * n;
-      double hv = 0;
-      for (int t = 0; t < n; ++t) hv = fma(hrow[t], col[t] / nc, hv);
-      const double vr = col[r] / nc;
-      hv = fma(g.e0[r % N], vr, hv);
-      q = fma(vr, hv, q);
-      vv = fma(vr, vr, vv);
+    const T nc = sqrt(group_sum<G>(s2));
+    double lam = (double)nc - (double)sigma;
+    if (sizeof(T) == 8) {
+      // v = w/|w| by division, so an unrotated column is an exact unit vector
+      double q = 0, vv = 0;
+      for (int r = lane; r < n; r += G) {
+        const double* hrow = V + (int64_t)r * n;
+        double hv = 0;
+        for (int t = 0; t < n; ++t) hv = fma(hrow[t], (double)col[t] / (double)nc, hv);
+        const double vr = (double)col[r] / (double)nc;
+        hv = fma(g.e0[r % N], vr, hv);
+        q = fma(vr, hv, q);
+        vv = fma(vr, vr, vv);
+      }
+      q = group_sum<G>(q);
+      vv = group_sum<G>(vv);
+      lam = q / vv;
     }
-    q = group_sum<G>(q);
-    vv = group_sum<G>(vv);
     if (lane == 0) {
-      ev[c] = nc;
-      rq[c] = q / vv;
+      nrm[c] = (double)nc;
+      rq[c] = lam;
     }
   }
   __syncthreads();
@@ -236,38 +252,45 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f64_global_kernel(const ItemDev*
     if (lane == 0) rank_of[c] = (int)cnt;
   }
   __syncthreads();
-  double* X = evec + it.v_off;
   for (int c = grp; c < n; c += ngrp) {
-    const double nc = ev[c];
+    const double nc = nrm[c];
     if (!(nc > 0.0) || !isfinite(nc) || !isfinite(rq[c])) {
       if (lane == 0) bad = 1;
       continue;
     }
     const int rank = rank_of[c];
-    const double* col = W + (int64_t)c * ld;
-    for (int r = lane; r < n; r += G) X[(int64_t)r * n + rank] = col[r] / nc;
+    const T* col = W + (int64_t)c * ld;
+    if (sizeof(T) == 8) {
+      double* X = evec + it.v_off;
+      for (int r = lane; r < n; r += G) X[(int64_t)r * n + rank] = (double)col[r] / nc;
+    } else {
+      float* X = x32 + it.v_off;
+      for (int r = lane; r < n; r += G) X[(int64_t)r * n + rank] = (float)col[r] / (float)nc;
+    }
   }
   __syncthreads();
+  double* ev = eval + it.e_off;
   for (int c = threadIdx.x; c < n; c += BLOCK) ev[rank_of[c]] = rq[c];
   if (threadIdx.x == 0)
-    status[blockIdx.x] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
+    status[item] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
 }
 
 }  // namespace
 
-hipError_t launch_jacobi_f32_lds(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
-                                 const double* v64, float* x32, double* eval, int32_t* status, int max_sweeps,
-                                 float tol, hipStream_t s) {
+hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
+                                 const GridDev* grids, const double* v64, float* x32, double* eval,
+                                 int32_t* status, int max_sweeps, float tol, hipStream_t s) {
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
-  const int ld = max_n | 1;
+  if (n_sel == 0) return hipSuccess;
+  const int ld = lds_stride(max_n);
   const size_t lds = (size_t)ld * max_n * sizeof(float);
   auto go = [&](auto kern, int block) -> hipError_t {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(block), lds, s, items, grids, v64, x32, eval, status, max_sweeps,
-                       tol);
+    hipLaunchKernelGGL(kern, dim3(n_sel), dim3(block), lds, s, items, sel, grids, v64, x32, eval, status,
+                       max_sweeps, tol);
     return hipGetLastError();
   };
   if (max_n <= 64) return go(jacobi_f32_lds_kernel<256, 4, 16>, 256);
@@ -275,12 +298,17 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, int n_items, int max_n, c
   return go(jacobi_f32_lds_kernel<1024, 8, 25>, 1024);
 }
 
-hipError_t launch_jacobi_f64_global(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
-                                    const double* v64, double* work, double* evec, double* eval, int32_t* status,
-                                    int max_sweeps, double tol, hipStream_t s) {
-  if (max_n > kMaxN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((jacobi_f64_global_kernel<1024, 8>), dim3(n_items), dim3(1024), 0, s, items, grids, v64, work,
-                     evec, eval, status, max_sweeps, tol);
+hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
+                                const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
+                                double* eval, int32_t* status, int max_sweeps, double tol, hipStream_t s) {
+  if (max_n > kMaxN || max_sweeps > 64) return hipErrorInvalidValue;
+  if (n_sel == 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL((jacobi_global_kernel<float, 1024, 8>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64,
+                       work, evec, x32, eval, status, max_sweeps, (float)tol);
+  else
+    hipLaunchKernelGGL((jacobi_global_kernel<double, 1024, 8>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids,
+                       v64, work, evec, x32, eval, status, max_sweeps, tol);
   return hipGetLastError();
 }
 

@@ -126,7 +126,11 @@ def test_coupled_batch_matches_oracle(ctx, coupled_setup, mode, dtype):
 # ------------------------------------------------ ragged mixed batch, odd n
 @pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
 def test_ragged_mixed_batch(ctx, mode):
-    specs = [("yam", 37, 1), ("cyuk", 20, 2), ("yuk0", 64, 1), ("cyuk", 75, 2), ("yam", 100, 1), ("cyuk", 100, 2)]
+    # n = 37, 240, 40, 64, 233, 150, 100, 128, 200: every eigensolver size class
+    # (<= 64, <= 128, <= 200 in LDS, > 200 in device memory) with its boundary
+    # sizes, interleaved so each class launch works from a scattered item list
+    specs = [("yam", 37, 1), ("cyuk", 120, 2), ("cyuk", 20, 2), ("yuk0", 64, 1), ("yam", 233, 1),
+             ("cyuk", 75, 2), ("yam", 100, 1), ("cyuk", 64, 2), ("cyuk", 100, 2)]
     items, mats, refs = [], [], []
     rng = np.random.default_rng(7)
     for sid, (kind, N, K) in enumerate(specs):
@@ -182,12 +186,12 @@ def test_argument_errors_are_reported_before_launch(ctx):
     with pytest.raises(wp.WPCDError) as e:
         ctx.grid(np.array([0.0, 1.0, 1.0, 2.0]), 8)
     assert e.value.code == wp.WPCD_ERR_INVALID
-    big = ctx.grid(grids.tan2_bounded(101), 8)
-    b = ctx.batch([(big, 2, 1, 0)])
-    bufs = b.alloc()
+    big = ctx.grid(grids.tan2_bounded(601), 2)
     with pytest.raises(wp.WPCDError) as e:
-        b.eigh(bufs["v64"], wp.MIXED, bufs["eval"], bufs["evec"], bufs["eig_status"])
+        ctx.batch([(big, 2, 1, 0)])          # n = 1202 > 1200
     assert e.value.code == wp.WPCD_ERR_UNSUPPORTED
+    b = ctx.batch([(g, 1, 0, 0)])
+    bufs = b.alloc()
     with pytest.raises(wp.WPCDError) as e:
         b.eigh(bufs["v64"], 7, bufs["eval"], bufs["evec"], bufs["eig_status"])
     assert e.value.code == wp.WPCD_ERR_INVALID
