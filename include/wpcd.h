@@ -134,10 +134,15 @@ typedef struct {
   int32_t n_ch;
   int32_t J;
   int32_t sample_id;
+  int32_t basis_id; /* -1: V from a fine-mesh potential (wpcd_project);
+                       >= 0: V = sum_t c_t B_t from a registered basis
+                       (wpcd_project_affine), which must match grid_id and
+                       n_ch.  Such items take no space in u_fine and
+                       n_terms entries in the packed coefficient array.   */
 } wpcd_item;
 
 typedef struct {
-  int64_t u_elems, v_elems, eval_elems, t_doubles, delta_elems, mix_elems;
+  int64_t u_elems, v_elems, eval_elems, t_doubles, delta_elems, mix_elems, coef_elems;
   int32_t n_items, n_samples, max_n, max_nbins;
 } wpcd_batch_layout;
 
@@ -147,15 +152,35 @@ int wpcd_batch_layout_get(wpcd_batch b, wpcd_batch_layout* out);
 /* Per-item element offsets into the packed arrays (host arrays of n_items;
  * any pointer may be NULL).                                                  */
 int wpcd_batch_offsets(wpcd_batch b, int64_t* u_off_host, int64_t* v_off_host, int64_t* eval_off_host,
-                       int64_t* t_off_host, int64_t* delta_off_host, int64_t* mix_off_host);
+                       int64_t* t_off_host, int64_t* delta_off_host, int64_t* mix_off_host,
+                       int64_t* coef_off_host);
+
+/* ---------------------------------------------------------------- bases ----
+ * wpcd_basis_register (Sec. 3.2: the packet potential matrix is linear in U):
+ * for potentials of the affine form U = sum_t c_t U_t, projects the n_terms
+ * fine-mesh terms U_t once and keeps B_t = proj(U_t) resident in the context
+ * (FP64, n_terms*n*n doubles, n = n_ch*N).  u_terms is a DEVICE array of n_terms
+ * consecutive M*M matrices (layout of u_fine above, M = n_ch*N*n_gauss) of
+ * dtype u_dtype; it is read on `stream`, and the call returns after the
+ * projection has finished (it synchronises that stream), so the caller may
+ * free u_terms afterwards.  1 <= n_terms <= 16.  Returns a basis id >= 0.     */
+int wpcd_basis_register(wpcd_ctx ctx, int grid_id, int n_ch, int n_terms, const void* u_terms, int u_dtype,
+                        hipStream_t stream, int* basis_id);
 
 /* ------------------------------------------------------------ compute calls --
  * wpcd_project (Sec. 3.2, the packet potential matrix as a double bin integral):
  *   V_(a,i),(b,j) = (dk_i dk_j)^(-1/2) sum_{alpha in i, beta in j}
  *                   w_alpha k_alpha w_beta k_beta U_(a,alpha),(b,beta)
- * from U at the grid's Gauss nodes.  u_dtype selects FP32 (accumulated in FP32)
- * or FP64 (accumulated in FP64) input; V is written as FP64.                 */
+ * from U at the grid's Gauss nodes, for every item with basis_id = -1.
+ * u_dtype selects FP32 (accumulated in FP32) or FP64 (accumulated in FP64)
+ * input; V is written as FP64.                                               */
 int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hipStream_t stream);
+/* wpcd_project_affine (Sec. 3.2, projection of an affine potential): for every
+ * item with basis_id >= 0, V = sum_t coef[c_off + t] * B_t in FP64 (items with
+ * basis_id = -1 are left untouched, as wpcd_project leaves basis items).  coef
+ * is a DEVICE array of layout.coef_elems doubles; item i's n_terms values
+ * start at its coef offset (wpcd_batch_offsets).                            */
+int wpcd_project_affine(wpcd_batch b, const double* coef, double* v64, hipStream_t stream);
 
 /* wpcd_eigh (Sec. 3.1, H = C D C^T; Sec. 3.2, step 2): eigenpairs of
  * H = diag(e, .., e) + V, eigenvalues ascending.  status[i] >= 0 is the number

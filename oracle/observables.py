@@ -131,13 +131,18 @@ def channel_loss(delta_deg: np.ndarray, eps_deg, kbar: np.ndarray, p, k_max: flo
     return total
 
 
-def sigma_tot(channels, kbar: np.ndarray, tlab_mev, k_max: float) -> np.ndarray:
+def sigma_tot(channels, kbar, tlab_mev, k_max) -> np.ndarray:
     """Total cross section in mb at the given T_lab values.
 
-    channels: iterable of (J, delta_deg (N, K), eps_deg (N,) or None).
+    channels: iterable of (J, delta_deg (N, K), eps_deg (N,) or None), all on
+    the bins with midpoints kbar and top momentum k_max, or of
+    (J, delta_deg, eps_deg, kbar_c, k_max_c) for channels on their own bins
+    (then kbar and k_max may be None).
     """
     p = tlab_to_p(tlab_mev)
     acc = np.zeros_like(p)
-    for J, delta_deg, eps_deg in channels:
-        acc = acc + (2 * J + 1) * channel_loss(np.asarray(delta_deg), eps_deg, kbar, p, k_max)
+    for ch in channels:
+        J, delta_deg, eps_deg = ch[:3]
+        kb, km = (ch[3], ch[4]) if len(ch) > 3 else (kbar, k_max)
+        acc = acc + (2 * J + 1) * channel_loss(np.asarray(delta_deg), eps_deg, kb, p, km)
     return 10.0 * np.pi / (2.0 * p * p) * acc

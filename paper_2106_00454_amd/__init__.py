@@ -35,8 +35,8 @@ DTYPE_F64 = 1
 #: every symbol declared in include/wpcd.h
 EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wpcd_grid_create",
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
-           "wpcd_batch_offsets", "wpcd_project", "wpcd_eigh", "wpcd_tmatrix", "wpcd_observables",
-           "wpcd_sigma_tot", "wpcd_profile_enable", "wpcd_stage_times")
+           "wpcd_batch_offsets", "wpcd_basis_register", "wpcd_project", "wpcd_project_affine", "wpcd_eigh",
+           "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_profile_enable", "wpcd_stage_times")
 
 STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma")
 
@@ -54,14 +54,14 @@ class _Config(ctypes.Structure):
 
 class _Item(ctypes.Structure):
     _fields_ = [("grid_id", ctypes.c_int32), ("n_ch", ctypes.c_int32), ("J", ctypes.c_int32),
-                ("sample_id", ctypes.c_int32)]
+                ("sample_id", ctypes.c_int32), ("basis_id", ctypes.c_int32)]
 
 
 class _Layout(ctypes.Structure):
     _fields_ = [("u_elems", ctypes.c_int64), ("v_elems", ctypes.c_int64), ("eval_elems", ctypes.c_int64),
                 ("t_doubles", ctypes.c_int64), ("delta_elems", ctypes.c_int64), ("mix_elems", ctypes.c_int64),
-                ("n_items", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("max_n", ctypes.c_int32),
-                ("max_nbins", ctypes.c_int32)]
+                ("coef_elems", ctypes.c_int64), ("n_items", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("max_n", ctypes.c_int32), ("max_nbins", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,8 +87,10 @@ def lib() -> ctypes.CDLL:
         "wpcd_batch_create": (i32, [vp, ctypes.POINTER(_Item), i32, ctypes.POINTER(vp)]),
         "wpcd_batch_destroy": (None, [vp]),
         "wpcd_batch_layout_get": (i32, [vp, ctypes.POINTER(_Layout)]),
-        "wpcd_batch_offsets": (i32, [vp] + [ctypes.POINTER(i64)] * 6),
+        "wpcd_batch_offsets": (i32, [vp] + [ctypes.POINTER(i64)] * 7),
+        "wpcd_basis_register": (i32, [vp, i32, i32, i32, dp, i32, vp, ctypes.POINTER(i32)]),
         "wpcd_project": (i32, [vp, dp, i32, dp, vp]),
+        "wpcd_project_affine": (i32, [vp, dp, dp, vp]),
         "wpcd_eigh": (i32, [vp, dp, i32, dp, dp, dp, vp]),
         "wpcd_tmatrix": (i32, [vp, dp, dp, dp, i32, dp, dp, vp]),
         "wpcd_observables": (i32, [vp, dp, dp, dp, dp, vp]),
@@ -189,9 +191,40 @@ class Context:
         _check(lib().wpcd_stage_times(self._h, ms, n))
         return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
 
+    def basis(self, grid: Grid, n_ch: int, terms, stream=None) -> "Basis":
+        """Register the projections of fine-mesh terms U_t (a list of host (M, M)
+        matrices, or a contiguous CUDA tensor of n_terms*M*M elements) for
+        affine potentials U = sum_t c_t U_t on `grid` with n_ch channels."""
+        import torch
+        m = n_ch * grid.n_wp * grid.n_gauss
+        if isinstance(terms, torch.Tensor):
+            u = terms
+            n_terms = u.numel() // (m * m)
+        else:
+            n_terms = len(terms)
+            u = torch.empty(n_terms * m * m, dtype=torch.float64, device=f"cuda:{self.device}")
+            for t, a in enumerate(terms):
+                a = np.asarray(a, dtype=np.float64)
+                if a.shape != (m, m):
+                    raise ValueError(f"term {t}: expected shape {(m, m)}, got {a.shape}")
+                u[t * m * m:(t + 1) * m * m].copy_(torch.from_numpy(a.ravel()))
+        dt = DTYPE_F32 if u.dtype == torch.float32 else DTYPE_F64
+        bid = ctypes.c_int()
+        _check(lib().wpcd_basis_register(self._h, grid.id, n_ch, n_terms, _ptr(u, u.dtype, n_terms * m * m, "terms"),
+                                         dt, _stream(stream), ctypes.byref(bid)))
+        return Basis(bid.value, grid, n_ch, n_terms)
+
     def batch(self, items) -> "Batch":
-        """items: iterable of (grid, n_ch, J, sample_id)."""
+        """items: iterable of (grid, n_ch, J, sample_id) or (grid, n_ch, J, sample_id, basis)."""
         return Batch(self, list(items))
+
+
+@dataclass
+class Basis:
+    id: int
+    grid: Grid
+    n_ch: int
+    n_terms: int
 
 
 class Batch:
@@ -199,19 +232,23 @@ class Batch:
         self.ctx = ctx
         arr = (_Item * len(items))()
         self.grids = []
-        for i, (g, n_ch, J, sid) in enumerate(items):
-            arr[i] = _Item(g.id, n_ch, J, sid)
+        self.items = []
+        for i, spec in enumerate(items):
+            g, n_ch, J, sid = spec[:4]
+            basis = spec[4] if len(spec) > 4 else None
+            arr[i] = _Item(g.id, n_ch, J, sid, -1 if basis is None else basis.id)
             self.grids.append(g)
-        self.items = items
+            self.items.append((g, n_ch, J, sid))
+        self.bases = [spec[4] if len(spec) > 4 else None for spec in items]
         h = ctypes.c_void_p()
         _check(lib().wpcd_batch_create(ctx._h, arr, len(items), ctypes.byref(h)))
         self._h = h
         lay = _Layout()
         _check(lib().wpcd_batch_layout_get(h, ctypes.byref(lay)))
         self.layout = {f: getattr(lay, f) for f, _ in _Layout._fields_}
-        offs = [np.zeros(len(items), dtype=np.int64) for _ in range(6)]
+        offs = [np.zeros(len(items), dtype=np.int64) for _ in range(7)]
         _check(lib().wpcd_batch_offsets(h, *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) for o in offs]))
-        self.u_off, self.v_off, self.eval_off, self.t_off, self.delta_off, self.mix_off = offs
+        self.u_off, self.v_off, self.eval_off, self.t_off, self.delta_off, self.mix_off, self.coef_off = offs
 
     def close(self):
         if getattr(self, "_h", None):
@@ -249,6 +286,13 @@ class Batch:
         _check(lib().wpcd_project(self._h, _ptr(u, u.dtype, self.layout["u_elems"], "u"), dt,
                                   _ptr(v64, torch.float64, self.layout["v_elems"], "v64"), _stream(stream)))
 
+    def project_affine(self, coef, v64, stream=None):
+        import torch
+        L = self.layout
+        cp = _ptr(coef, torch.float64, L["coef_elems"], "coef") if coef is not None else ctypes.c_void_p(0)
+        _check(lib().wpcd_project_affine(self._h, cp, _ptr(v64, torch.float64, L["v_elems"], "v64"),
+                                         _stream(stream)))
+
     def eigh(self, v64, mode, eval_, evec, status, stream=None):
         import torch
         L = self.layout
@@ -284,9 +328,14 @@ class Batch:
                                     _ptr(sigma, torch.float64, L["n_samples"] * n_tlab, "sigma"),
                                     _stream(stream)))
 
-    def run(self, u, bufs, mode, tlab=None, sigma=None, stream=None):
-        """The whole path a1..a9 for this batch on one stream."""
-        self.project(u, bufs["v64"], stream)
+    def run(self, u, bufs, mode, tlab=None, sigma=None, stream=None, coef=None):
+        """The whole path for this batch on one stream: fine-mesh items
+        projected from `u`, basis items from `coef`, then eigenpairs, T,
+        phase shifts and (with tlab) cross sections."""
+        if u is not None:
+            self.project(u, bufs["v64"], stream)
+        if coef is not None:
+            self.project_affine(coef, bufs["v64"], stream)
         self.eigh(bufs["v64"], mode, bufs["eval"], bufs["evec"], bufs["eig_status"], stream)
         self.tmatrix(bufs["v64"], bufs["eval"], bufs["evec"], mode, bufs["t"], bufs["t_status"], stream)
         self.observables(bufs["t"], bufs["delta"], bufs["mix"], bufs["s_dev"], stream)

@@ -133,6 +133,7 @@ void wpcd_destroy(wpcd_ctx ctx) {
     hipEventDestroy(p.stop);
   }
   for (auto& g : ctx->grids) hipFree(g.dbuf);
+  for (auto& bs : ctx->bases) hipFree(bs.dbuf);
   delete ctx;
 }
 
@@ -215,6 +216,7 @@ void wpcd_batch_destroy(wpcd_batch b) {
   hipFree(b->d_cl);
   hipFree(b->d_lam);
   hipFree(b->d_class);
+  hipFree(b->d_bases);
   delete b;
 }
 
@@ -243,6 +245,15 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
       delete b;
       return fail(WPCD_ERR_INVALID, "item %d: need J >= 0 (>= 1 if coupled) and sample_id >= 0", i);
     }
+    if (in.basis_id < -1 || in.basis_id >= (int)ctx->bases.size()) {
+      delete b;
+      return fail(WPCD_ERR_INVALID, "item %d: unknown basis id %d", i, in.basis_id);
+    }
+    if (in.basis_id >= 0 &&
+        (ctx->bases[in.basis_id].grid != in.grid_id || ctx->bases[in.basis_id].nch != in.n_ch)) {
+      delete b;
+      return fail(WPCD_ERR_INVALID, "item %d: basis %d was registered for another grid or n_ch", i, in.basis_id);
+    }
     const GridHost& g = ctx->grids[in.grid_id];
     const int n = in.n_ch * g.N;
     if (n > kMaxN) {
@@ -257,9 +268,16 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     d.ng = g.ng;
     d.J = in.J;
     d.sample = in.sample_id;
-    d.pad = 0;
-    const int64_t M = (int64_t)n * g.ng;
+    d.basis = in.basis_id;
+    const int64_t M = in.basis_id >= 0 ? 0 : (int64_t)n * g.ng;
     d.u_off = b->u_elems;
+    d.c_off = b->coef_elems;
+    if (in.basis_id >= 0) {
+      b->coef_elems += ctx->bases[in.basis_id].n_terms;
+      b->n_affine++;
+    } else {
+      b->n_fine++;
+    }
     d.v_off = b->v_elems;
     d.e_off = b->eval_elems;
     d.t_off = b->t_doubles;
@@ -315,6 +333,11 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   alloc((void**)&b->d_cl, sizeof(int32_t) * b->eval_elems);
   alloc((void**)&b->d_lam, sizeof(double) * b->eval_elems);
   alloc((void**)&b->d_class, sizeof(int32_t) * n_items);
+  std::vector<BasisDev> bd(ctx->bases.size());
+  for (size_t i = 0; i < bd.size(); ++i) bd[i] = BasisDev{ctx->bases[i].dbuf, ctx->bases[i].n, ctx->bases[i].n_terms};
+  alloc((void**)&b->d_bases, sizeof(BasisDev) * bd.size());
+  if (e == hipSuccess && !bd.empty())
+    e = hipMemcpy(b->d_bases, bd.data(), sizeof(BasisDev) * bd.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_items, b->h_items.data(), sizeof(ItemDev) * n_items, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_grids, gd.data(), sizeof(GridDev) * gd.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -338,6 +361,7 @@ int wpcd_batch_layout_get(wpcd_batch b, wpcd_batch_layout* out) {
   out->t_doubles = b->t_doubles;
   out->delta_elems = b->delta_elems;
   out->mix_elems = b->mix_elems;
+  out->coef_elems = b->coef_elems;
   out->n_items = b->n_items;
   out->n_samples = b->n_samples;
   out->max_n = b->max_n;
@@ -346,7 +370,7 @@ int wpcd_batch_layout_get(wpcd_batch b, wpcd_batch_layout* out) {
 }
 
 int wpcd_batch_offsets(wpcd_batch b, int64_t* u_off, int64_t* v_off, int64_t* eval_off, int64_t* t_off,
-                       int64_t* delta_off, int64_t* mix_off) {
+                       int64_t* delta_off, int64_t* mix_off, int64_t* coef_off) {
   if (!b) return fail(WPCD_ERR_INVALID, "wpcd_batch_offsets: NULL batch");
   for (int i = 0; i < b->n_items; ++i) {
     const ItemDev& d = b->h_items[i];
@@ -356,6 +380,7 @@ int wpcd_batch_offsets(wpcd_batch b, int64_t* u_off, int64_t* v_off, int64_t* ev
     if (t_off) t_off[i] = d.t_off;
     if (delta_off) delta_off[i] = d.d_off;
     if (mix_off) mix_off[i] = d.m_off;
+    if (coef_off) coef_off[i] = d.c_off;
   }
   return WPCD_OK;
 }
@@ -365,9 +390,75 @@ int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hip
   if (u_dtype != WPCD_DTYPE_F32 && u_dtype != WPCD_DTYPE_F64)
     return fail(WPCD_ERR_INVALID, "wpcd_project: unknown u_dtype %d", u_dtype);
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  if (b->n_fine == 0) return WPCD_OK;
   WPCD_HIP(timed(b->ctx, WPCD_STAGE_PROJECT, stream,
                  [&] { return launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64, stream); }),
            "wpcd_project launch");
+  return WPCD_OK;
+}
+
+int wpcd_project_affine(wpcd_batch b, const double* coef, double* v64, hipStream_t stream) {
+  if (!b || !v64 || (!coef && b->coef_elems > 0)) return fail(WPCD_ERR_INVALID, "wpcd_project_affine: NULL argument");
+  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  if (b->n_affine == 0) return WPCD_OK;
+  WPCD_HIP(timed(b->ctx, WPCD_STAGE_PROJECT, stream,
+                 [&] {
+                   return launch_project_affine(b->d_items, b->n_items, b->max_n, b->d_bases, coef, v64, stream);
+                 }),
+           "wpcd_project_affine launch");
+  return WPCD_OK;
+}
+
+int wpcd_basis_register(wpcd_ctx ctx, int grid_id, int n_ch, int n_terms, const void* u_terms, int u_dtype,
+                        hipStream_t stream, int* basis_id) {
+  if (!ctx || !u_terms || !basis_id) return fail(WPCD_ERR_INVALID, "wpcd_basis_register: NULL argument");
+  if (grid_id < 0 || grid_id >= (int)ctx->grids.size())
+    return fail(WPCD_ERR_INVALID, "wpcd_basis_register: unknown grid id %d", grid_id);
+  if (n_ch != 1 && n_ch != 2) return fail(WPCD_ERR_INVALID, "wpcd_basis_register: n_ch must be 1 or 2");
+  if (n_terms < 1 || n_terms > 16) return fail(WPCD_ERR_INVALID, "wpcd_basis_register: n_terms must be in [1, 16]");
+  if (u_dtype != WPCD_DTYPE_F32 && u_dtype != WPCD_DTYPE_F64)
+    return fail(WPCD_ERR_INVALID, "wpcd_basis_register: unknown u_dtype %d", u_dtype);
+  const GridHost& g = ctx->grids[grid_id];
+  const int n = n_ch * g.N;
+  if (n > kMaxN) return fail(WPCD_ERR_UNSUPPORTED, "wpcd_basis_register: n = %d exceeds %d", n, kMaxN);
+  WPCD_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const int64_t M = (int64_t)n * g.ng;
+  // the terms as items of a temporary batch over a one-entry grid table
+  std::vector<ItemDev> it(n_terms);
+  for (int t = 0; t < n_terms; ++t) {
+    ItemDev& d = it[t];
+    memset(&d, 0, sizeof(d));
+    d.grid = 0;
+    d.nch = n_ch;
+    d.N = g.N;
+    d.n = n;
+    d.ng = g.ng;
+    d.basis = -1;
+    d.u_off = t * M * M;
+    d.v_off = (int64_t)t * n * n;
+  }
+  BasisHost bh;
+  bh.grid = grid_id;
+  bh.nch = n_ch;
+  bh.n = n;
+  bh.n_terms = n_terms;
+  ItemDev* d_it = nullptr;
+  GridDev* d_g = nullptr;
+  hipError_t e = hipMalloc((void**)&bh.dbuf, sizeof(double) * n_terms * (size_t)n * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_it, sizeof(ItemDev) * n_terms);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_g, sizeof(GridDev));
+  if (e == hipSuccess) e = hipMemcpy(d_it, it.data(), sizeof(ItemDev) * n_terms, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_g, &g.dev, sizeof(GridDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_project(d_it, n_terms, n, d_g, u_terms, u_dtype, bh.dbuf, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  hipFree(d_it);
+  hipFree(d_g);
+  if (e != hipSuccess) {
+    hipFree(bh.dbuf);
+    return hip_fail(e, "wpcd_basis_register");
+  }
+  ctx->bases.push_back(bh);
+  *basis_id = (int)ctx->bases.size() - 1;
   return WPCD_OK;
 }
 

@@ -14,6 +14,11 @@ struct GridHost {
   GridDev dev{};
 };
 
+struct BasisHost {
+  int grid = 0, nch = 0, n = 0, n_terms = 0;
+  double* dbuf = nullptr;  // n_terms * n * n FP64
+};
+
 }  // namespace wpcd
 
 
@@ -21,6 +26,7 @@ struct wpcd_context {
   int device = 0;
   wpcd_config cfg{};
   std::vector<wpcd::GridHost> grids;
+  std::vector<wpcd::BasisHost> bases;
   // stage timers
   bool profiling = false;
   struct Pending {
@@ -40,7 +46,10 @@ struct wpcd_batch_s {
   wpcd::GridDev* d_grids = nullptr;
   int32_t* d_sample_ptr = nullptr;
   int32_t* d_sample_items = nullptr;
-  int64_t u_elems = 0, v_elems = 0, eval_elems = 0, t_doubles = 0, delta_elems = 0, mix_elems = 0, work_doubles = 0;
+  wpcd::BasisDev* d_bases = nullptr;
+  int n_fine = 0, n_affine = 0;  // items projected from u_fine / from a basis
+  int64_t u_elems = 0, v_elems = 0, eval_elems = 0, t_doubles = 0, delta_elems = 0, mix_elems = 0, work_doubles = 0,
+          coef_elems = 0;
   float* d_x32 = nullptr;
   double* d_work = nullptr;
   int32_t* d_cl = nullptr;

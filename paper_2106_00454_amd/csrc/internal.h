@@ -32,7 +32,7 @@ struct ItemDev {
   int32_t ng;      // Gauss nodes per bin
   int32_t J;
   int32_t sample;
-  int32_t pad;
+  int32_t basis;   // -1: fine-mesh potential; >= 0: index into the basis table
   int64_t u_off;   // elements into u_fine
   int64_t v_off;   // elements into v64 / evec (n*n)
   int64_t e_off;   // elements into eval (n)
@@ -40,6 +40,15 @@ struct ItemDev {
   int64_t d_off;   // elements into delta / s_dev (N*nch)
   int64_t m_off;   // elements into mix (N)
   int64_t w_off;   // elements into the per-item eigensolver workspace
+  int64_t c_off;   // elements into the affine coefficient array
+};
+
+// Device view of a resident projected basis: n_terms consecutive n*n FP64
+// matrices B_t (row-major, exactly symmetric).
+struct BasisDev {
+  const double* b;
+  int32_t n;
+  int32_t n_terms;
 };
 
 // Largest matrix the FP32 LDS eigensolver holds (n*n floats must fit 160 KiB).
@@ -56,6 +65,8 @@ constexpr int kMaxCluster = 64;
 // Kernel launchers (each returns hipSuccess or the launch error).
 hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const void* u,
                           int u_dtype, double* v64, hipStream_t s);
+hipError_t launch_project_affine(const ItemDev* items, int n_items, int max_n, const BasisDev* bases,
+                                 const double* coef, double* v64, hipStream_t s);
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
                                  int32_t* status, int max_sweeps, float tol, hipStream_t s);

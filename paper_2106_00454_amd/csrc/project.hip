@@ -48,6 +48,7 @@ __global__ __launch_bounds__(256) void project_kernel(const ItemDev* __restrict_
                                                       const GridDev* __restrict__ grids,
                                                       const T* __restrict__ u, double* __restrict__ v64) {
   const ItemDev it = items[item0 + blockIdx.y];
+  if (it.basis >= 0) return;  // projected from a resident basis instead
   const int n = it.n;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * n) return;
@@ -72,7 +73,40 @@ __global__ __launch_bounds__(256) void project_kernel(const ItemDev* __restrict_
   v64[it.v_off + (int64_t)J * n + I] = v;
 }
 
+// Affine potentials (the projection is linear in U): V = sum_t c_t B_t over
+// the item's resident basis, one thread per element of V, FP64 throughout.
+// Every B_t is exactly symmetric and the sum runs in the same order for (I,J)
+// and (J,I), so V is exactly symmetric.
+__global__ __launch_bounds__(256) void project_affine_kernel(const ItemDev* __restrict__ items, int item0,
+                                                             const BasisDev* __restrict__ bases,
+                                                             const double* __restrict__ coef,
+                                                             double* __restrict__ v64) {
+  const ItemDev it = items[item0 + blockIdx.y];
+  if (it.basis < 0) return;
+  const int64_t nn = (int64_t)it.n * it.n;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const BasisDev bs = bases[it.basis];
+  const double* c = coef + it.c_off;
+  double acc = 0.0;
+  for (int t = 0; t < bs.n_terms; ++t) acc = fma(c[t], bs.b[t * nn + e], acc);
+  v64[it.v_off + e] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_project_affine(const ItemDev* items, int n_items, int max_n, const BasisDev* bases,
+                                 const double* coef, double* v64, hipStream_t s) {
+  const int bs = 256;
+  const unsigned gx = (unsigned)(((int64_t)max_n * max_n + bs - 1) / bs);
+  for (int i0 = 0; i0 < n_items; i0 += 65535) {
+    const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+    hipLaunchKernelGGL(project_affine_kernel, dim3(gx, gy), dim3(bs), 0, s, items, i0, bases, coef, v64);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const void* u,
                           int u_dtype, double* v64, hipStream_t s) {

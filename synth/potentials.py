@@ -49,26 +49,33 @@ def legendre_q(lmax: int, zm1: np.ndarray) -> list:
     zm1 = np.asarray(zm1, dtype=np.float64)
     if np.any(zm1 <= 0):
         raise ValueError("legendre_q needs z > 1")
+    shape = zm1.shape
+    zm1 = zm1.ravel()
     z = 1.0 + zm1
     q0 = 0.5 * np.log1p(2.0 / zm1)
     if lmax == 0:
-        return [q0]
-    # decay rate of the minimal solution: Q_{l+1}/Q_l -> exp(-x)
+        return [q0.reshape(shape)]
+    # decay rate of the minimal solution: Q_{l+1}/Q_l -> exp(-x); points are
+    # processed in groups of similar x, each started deep enough for its
+    # smallest x
     x = np.arccosh(z)
-    xmin = float(np.min(x)) if x.size else 1.0
-    extra = int(np.ceil(40.0 / max(xmin, 1e-3)))
-    big_l = lmax + min(extra, 20000)
-    r = np.zeros_like(z)
-    ratios = {}
-    for l in range(big_l, 0, -1):
-        r = l / ((2 * l + 1) * z - (l + 1) * r)
-        if l <= lmax:
-            ratios[l] = r
-    out = [q0]
+    order = np.argsort(x)
+    ratios = np.empty((lmax + 1, z.size))
+    chunk = 65536
+    for c0 in range(0, z.size, chunk):
+        idx = order[c0:c0 + chunk]
+        zc = z[idx]
+        extra = int(np.ceil(40.0 / max(float(x[idx[0]]), 1e-3)))
+        r = np.zeros_like(zc)
+        for l in range(lmax + min(extra, 20000), 0, -1):
+            r = l / ((2 * l + 1) * zc - (l + 1) * r)
+            if l <= lmax:
+                ratios[l, idx] = r
+    out = [q0.reshape(shape)]
     q = q0
     for l in range(1, lmax + 1):
         q = q * ratios[l]
-        out.append(q)
+        out.append(q.reshape(shape))
     return out
 
 

@@ -3,23 +3,34 @@ import numpy as np
 import torch
 
 import paper_2106_00454_amd as wp
+from oracle import wpcd as ow
 from synth import device as sdev
 
 TLAB = np.linspace(1.0, 350.0, 30)
+DELTA_TOL = 0.01   # deg, phase shifts and mixing angles vs the oracle
+SIGMA_TOL = 0.01   # mb, total cross sections vs the oracle
 
 
-def run_items(ctx, items, u, mode, tlab=TLAB):
-    """items: list of (grid, n_ch, J, sample_id); u: packed device tensor (or list of host matrices)."""
+def run_items(ctx, items, u, mode, tlab=TLAB, coef=None):
+    """items: list of (grid, n_ch, J, sample_id[, basis]); u: packed device tensor
+    (or list of host matrices, or None for a batch of basis items); coef: host
+    list of per-item coefficient vectors of the basis items (None for others)."""
     b = ctx.batch(items)
-    if not isinstance(u, torch.Tensor):
+    if u is not None and not isinstance(u, torch.Tensor):
         u = sdev.pack_host_matrices(b.layout["u_elems"], b.u_off, u, torch.float64)
+    if coef is not None:
+        c = np.zeros(max(1, b.layout["coef_elems"]))
+        for i, ci in enumerate(coef):
+            if ci is not None:
+                c[b.coef_off[i]:b.coef_off[i] + len(ci)] = ci
+        coef = torch.tensor(c, dtype=torch.float64, device="cuda")
     bufs = b.alloc()
     sig = None
     tl = None
     if tlab is not None:
         tl = torch.tensor(tlab, dtype=torch.float64, device="cuda")
         sig = torch.full((b.layout["n_samples"] * len(tlab),), np.nan, dtype=torch.float64, device="cuda")
-    b.run(u, bufs, mode, tl, sig)
+    b.run(u, bufs, mode, tl, sig, coef=coef)
     torch.cuda.synchronize()
     host = {k: v.cpu().numpy() for k, v in bufs.items()}
     if sig is not None:
@@ -48,3 +59,34 @@ def item_view(b, host, i):
 
 def dmod180(a, b):
     return np.abs(((np.asarray(a) - np.asarray(b) + 90.0) % 180.0) - 90.0)
+
+
+def check_item(tag, it, ref, k, mode, J, want_sigma=None, got_sigma=None):
+    K = it["delta"].shape[1]
+    n = it["v"].shape[0]
+    # eigenpairs are checked against the H the GPU itself diagonalised (its V
+    # differs from the oracle's by the input/accumulation rounding of wpcd_project)
+    h = it["v"] + np.diag(np.tile(ow.h0_diagonal(k), K))
+    hmax = np.abs(h).max()
+    dv = np.linalg.norm(it["v"] - ref["v"])  # bounds the eigenvalue shift (Weyl)
+    dd = dmod180(it["delta"], ref["delta"]).max()
+    dm = np.abs(it["mix"] - ref["mix"]).max() if K == 2 else 0.0
+    de = np.abs(it["evals"] - ref["evals"]).max()
+    resid = np.abs(h @ it["evecs"] - it["evecs"] * it["evals"][None, :]).max()
+    orth = np.abs(it["evecs"].T @ it["evecs"] - np.eye(n)).max()
+    msg = f"{tag}: ddelta={dd:.3e} dmix={dm:.3e} deval={de:.3e} resid={resid:.3e} orth={orth:.3e} " \
+          f"sweeps={it['eig_status']}"
+    print(msg, flush=True)
+    assert it["eig_status"] > 0, msg
+    assert it["t_status"] == 0, msg
+    assert dd <= DELTA_TOL and dm <= DELTA_TOL, msg
+    # eigenpairs: FP64-level residual; orthogonality 1e-12 for the FP64 Jacobi,
+    # 1e-7 after two refinement steps from FP32 (the second step is quadratic in
+    # the first one's 1e-4-level corrections)
+    orth_tol = 1e-7 if mode == wp.MIXED else 1e-12
+    assert resid <= 1e-9 * hmax and orth <= orth_tol, msg
+    assert de <= 1e-9 * hmax + dv, msg
+    if want_sigma is not None:
+        ds = np.abs(got_sigma - want_sigma).max()
+        print(f"{tag}: dsigma={ds:.3e} mb", flush=True)
+        assert ds <= SIGMA_TOL, msg

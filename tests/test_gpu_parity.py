@@ -13,13 +13,9 @@ from oracle import observables as oo
 from oracle import wpcd as ow
 from synth import configs, grids, potentials
 from synth import device as sdev
-from tests.gpu_util import TLAB, dmod180, item_view, run_items
+from tests.gpu_util import DELTA_TOL, SIGMA_TOL, TLAB, check_item, dmod180, item_view, run_items
 
 pytestmark = pytest.mark.gpu
-
-DELTA_TOL = 0.01   # deg
-SIGMA_TOL = 0.01   # mb
-
 
 @pytest.fixture(scope="module")
 def ctx():
@@ -28,37 +24,6 @@ def ctx():
 
 def oracle_item(k, u_oracle_nodes, K):
     return ow.solve_channel(k, configs.N_GAUSS, u_oracle_nodes, K)
-
-
-def check_item(tag, it, ref, k, mode, J, want_sigma=None, got_sigma=None):
-    K = it["delta"].shape[1]
-    n = it["v"].shape[0]
-    # eigenpairs are checked against the H the GPU itself diagonalised (its V
-    # differs from the oracle's by the input/accumulation rounding of wpcd_project)
-    h = it["v"] + np.diag(np.tile(ow.h0_diagonal(k), K))
-    hmax = np.abs(h).max()
-    dv = np.linalg.norm(it["v"] - ref["v"])  # bounds the eigenvalue shift (Weyl)
-    dd = dmod180(it["delta"], ref["delta"]).max()
-    dm = np.abs(it["mix"] - ref["mix"]).max() if K == 2 else 0.0
-    de = np.abs(it["evals"] - ref["evals"]).max()
-    resid = np.abs(h @ it["evecs"] - it["evecs"] * it["evals"][None, :]).max()
-    orth = np.abs(it["evecs"].T @ it["evecs"] - np.eye(n)).max()
-    msg = f"{tag}: ddelta={dd:.3e} dmix={dm:.3e} deval={de:.3e} resid={resid:.3e} orth={orth:.3e} " \
-          f"sweeps={it['eig_status']}"
-    print(msg, flush=True)
-    assert it["eig_status"] > 0, msg
-    assert it["t_status"] == 0, msg
-    assert dd <= DELTA_TOL and dm <= DELTA_TOL, msg
-    # eigenpairs: FP64-level residual; orthogonality 1e-12 for the FP64 Jacobi,
-    # 1e-7 after two refinement steps from FP32 (the second step is quadratic in
-    # the first one's 1e-4-level corrections)
-    orth_tol = 1e-7 if mode == wp.MIXED else 1e-12
-    assert resid <= 1e-9 * hmax and orth <= orth_tol, msg
-    assert de <= 1e-9 * hmax + dv, msg
-    if want_sigma is not None:
-        ds = np.abs(got_sigma - want_sigma).max()
-        print(f"{tag}: dsigma={ds:.3e} mb", flush=True)
-        assert ds <= SIGMA_TOL, msg
 
 
 # ------------------------------------------------------------------ grid

@@ -329,3 +329,39 @@ def test_tensor_block_matches_direct_radial_integral():
         ref = float(mpmath.quad(f, mpmath.linspace(0, 60, 121))) * (2 / np.pi) * 6 * np.sqrt(2.0) / 3
         got = potentials.tensor_block(J, np.array([pp]), np.array([p]), 1.0, mu)[0, 0]
         assert abs(got - ref) <= 1e-9 * abs(ref)
+
+
+def test_legendre_q_array_matches_mpmath_across_depth_groups():
+    # > 65536 points so several depth groups (sorted by decay rate) are formed
+    mpmath.mp.dps = 30
+    rng = np.random.default_rng(5)
+    zm1 = np.concatenate([10.0 ** rng.uniform(-3, 5, 70000), [0.0153, 1e-3]])
+    q = potentials.legendre_q(7, zm1.reshape(2, -1))
+    for j in rng.integers(0, zm1.size, 25).tolist() + [zm1.size - 1, zm1.size - 2]:
+        z = 1 + mpmath.mpf(zm1[j])
+        for l in (0, 3, 7):
+            ref = float(mpmath.legenq(l, 0, z, type=3).real)
+            assert abs(q[l].ravel()[j] - ref) <= 1e-12 * abs(ref)
+
+
+def test_sweep_channel_set_and_sigma_with_per_channel_bins():
+    from synth import sweep
+    names = [c[0] for c in sweep.CHANNELS]
+    assert len(names) == 20 and len(set(names)) == 20
+    slj = set()
+    for _, n_ch, J, S, l in sweep.CHANNELS:
+        assert 0 <= J <= 6
+        ls = (l,) if n_ch == 1 else (l, l + 2)
+        if n_ch == 2:
+            assert S == 1 and l == J - 1
+        for ll in ls:
+            assert abs(ll - J) <= S and (S, ll, J) not in slj
+            slj.add((S, ll, J))
+    assert len(slj) == 26            # 7 singlet + 7 triplet uncoupled + 6 x 2 coupled
+    # per-channel bins: identical to the shared-bin form when the bins agree
+    kbar = np.linspace(0.05, 3.0, 40)
+    d = (20.0 * kbar)[:, None]
+    tl = np.array([1.0, 100.0, 300.0])
+    a = observables.sigma_tot([(0, d, None), (2, d, None)], kbar, tl, 4.0)
+    b = observables.sigma_tot([(0, d, None, kbar, 4.0), (2, d, None, kbar, 4.0)], None, tl, None)
+    assert np.array_equal(a, b)
