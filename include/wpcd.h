@@ -223,6 +223,78 @@ int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* m
 int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev,
                    int n_tlab, double* sigma_mb, hipStream_t stream);
 
+/* ---------------------------------------------------------------- serving --
+ * A request loop over one context (the paper's posterior-sweep use case, Sec. 1
+ * and Sec. 5: many independent parameter-vector solves).  A request is one
+ * parameter sample: a set of channels, each an affine potential over a
+ * registered basis (wpcd_basis_register) with its own coefficients, and the
+ * T_lab values of its total cross section.  Requests are queued by
+ * wpcd_submit; a worker thread owned by the server admits queued requests in
+ * arrival order while their device footprint fits the free part of a device
+ * arena of hbm_budget_bytes and an in-flight slot is free, packs them into
+ * one batch, and runs the whole path (affine projection, mixed-precision
+ * eigensolver, T, phase shifts, cross sections) on that slot's stream, so
+ * batches admitted while others run overlap on the device (continuous
+ * batching).  Each item's arithmetic does not depend on the other items of its
+ * batch.  Grids and bases stay resident; register all of them before
+ * wpcd_server_create (the server snapshots the context's tables).  The
+ * context must not be used for other compute calls while a server runs.
+ *
+ * Thread safety: wpcd_submit and wpcd_poll may be called from any host
+ * threads concurrently.                                                     */
+typedef struct wpcd_server_s* wpcd_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* device arena for in-flight batches (default 4 GiB) */
+  int32_t max_inflight;     /* concurrent batches, one stream each (1..8, default 4) */
+  int32_t max_batch_items;  /* items per batch (default 4096)                  */
+  int32_t max_queue;        /* queued requests before WPCD_ERR_BUSY (default 65536) */
+  int32_t pad;
+} wpcd_server_config;
+
+typedef struct {
+  int32_t basis_id;        /* registered basis: fixes grid and n_ch           */
+  int32_t J;               /* total angular momentum (weight 2J+1 in sigma)   */
+  const double* coef_host; /* the basis's n_terms coefficients (copied)       */
+} wpcd_req_channel;
+
+typedef struct {
+  const wpcd_req_channel* channels_host; /* copied at submit                   */
+  int32_t n_channels;                     /* 1..64                              */
+  int32_t n_tlab;                         /* 0..1024                            */
+  const double* tlab_host;                /* n_tlab T_lab values (copied)       */
+  /* outputs, host memory owned by the caller, written by the worker thread
+   * and valid once wpcd_poll has returned anything but WPCD_ERR_AGAIN:       */
+  double* sigma_host;  /* n_tlab total cross sections (mb), may be NULL if n_tlab = 0 */
+  double* delta_host;  /* optional: per channel N*n_ch phase shifts, channels concatenated */
+  double* mix_host;    /* optional: per channel N mixing angles (0 if uncoupled), concatenated */
+  int32_t* status_host; /* optional: per channel eigensolver status (sweeps or WPCD_ERR_*) */
+} wpcd_request;
+
+typedef struct {
+  int64_t submitted, completed, batches, items, peak_arena_bytes;
+  int32_t queued, inflight;
+} wpcd_server_stats;
+
+/* cfg may be NULL for defaults.  Allocates the arena and pinned staging and
+ * starts the worker thread.                                                 */
+int wpcd_server_create(wpcd_ctx ctx, const wpcd_server_config* cfg, wpcd_server* out);
+/* Stops admitting, waits for in-flight batches, joins the worker and frees
+ * everything; requests still queued are dropped (their poll would return
+ * WPCD_ERR_INVALID afterwards, as the server no longer exists).             */
+void wpcd_server_destroy(wpcd_server s);
+/* Queues a request; *ticket identifies it for wpcd_poll.  Returns
+ * WPCD_ERR_BUSY if max_queue requests are waiting, WPCD_ERR_INVALID for bad
+ * arguments (unknown basis, too many channels or energies) and
+ * WPCD_ERR_UNSUPPORTED if the request alone exceeds hbm_budget_bytes.       */
+int wpcd_submit(wpcd_server s, const wpcd_request* req, uint64_t* ticket);
+/* WPCD_ERR_AGAIN while pending; otherwise the request's outputs are written,
+ * the ticket is retired and the return value is WPCD_OK, the first failing
+ * item's code (WPCD_ERR_NOCONV / WPCD_ERR_NUMERIC), or WPCD_ERR_DEVICE if its
+ * batch failed on the device.  Unknown or retired tickets: WPCD_ERR_INVALID. */
+int wpcd_poll(wpcd_server s, uint64_t ticket);
+int wpcd_server_stats_get(wpcd_server s, wpcd_server_stats* out);
+
 /* ------------------------------------------------------------ stage timers --
  * When enabled, every compute call records a pair of HIP events on its stream
  * around each kernel group it launches (the eigensolver counts as two stages:

@@ -36,7 +36,8 @@ DTYPE_F64 = 1
 EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wpcd_grid_create",
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
            "wpcd_batch_offsets", "wpcd_basis_register", "wpcd_project", "wpcd_project_affine", "wpcd_eigh",
-           "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_profile_enable", "wpcd_stage_times")
+           "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_server_create", "wpcd_server_destroy",
+           "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times")
 
 STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma")
 
@@ -62,6 +63,27 @@ class _Layout(ctypes.Structure):
                 ("t_doubles", ctypes.c_int64), ("delta_elems", ctypes.c_int64), ("mix_elems", ctypes.c_int64),
                 ("coef_elems", ctypes.c_int64), ("n_items", ctypes.c_int32), ("n_samples", ctypes.c_int32),
                 ("max_n", ctypes.c_int32), ("max_nbins", ctypes.c_int32)]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch_items", ctypes.c_int32), ("max_queue", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _ReqChannel(ctypes.Structure):
+    _fields_ = [("basis_id", ctypes.c_int32), ("J", ctypes.c_int32), ("coef_host", ctypes.c_void_p)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("channels_host", ctypes.POINTER(_ReqChannel)), ("n_channels", ctypes.c_int32),
+                ("n_tlab", ctypes.c_int32), ("tlab_host", ctypes.c_void_p), ("sigma_host", ctypes.c_void_p),
+                ("delta_host", ctypes.c_void_p), ("mix_host", ctypes.c_void_p), ("status_host", ctypes.c_void_p)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("items", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_int64), ("queued", ctypes.c_int32),
+                ("inflight", ctypes.c_int32)]
 
 
 _lib = None
@@ -95,6 +117,11 @@ def lib() -> ctypes.CDLL:
         "wpcd_tmatrix": (i32, [vp, dp, dp, dp, i32, dp, dp, vp]),
         "wpcd_observables": (i32, [vp, dp, dp, dp, dp, vp]),
         "wpcd_sigma_tot": (i32, [vp, dp, dp, dp, i32, dp, vp]),
+        "wpcd_server_create": (i32, [vp, ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]),
+        "wpcd_server_destroy": (None, [vp]),
+        "wpcd_submit": (i32, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "wpcd_poll": (i32, [vp, ctypes.c_uint64]),
+        "wpcd_server_stats_get": (i32, [vp, ctypes.POINTER(_ServerStats)]),
         "wpcd_profile_enable": (i32, [vp, i32]),
         "wpcd_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
     }
@@ -341,3 +368,81 @@ class Batch:
         self.observables(bufs["t"], bufs["delta"], bufs["mix"], bufs["s_dev"], stream)
         if tlab is not None:
             self.sigma_tot(bufs["delta"], bufs["mix"], tlab, sigma, stream)
+
+
+# ---------------------------------------------------------------- serving
+class Ticket:
+    """A submitted request: its id and the host arrays its results go to."""
+
+    def __init__(self, tid, sigma, delta, mix, status):
+        self.id = tid
+        self.sigma = sigma
+        self.delta = delta
+        self.mix = mix
+        self.status = status
+        self.code = None          # set by Server.poll once done
+
+
+class Server:
+    """Request loop with continuous batching over a context's registered bases."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 4 << 30, max_inflight: int = 4,
+                 max_batch_items: int = 4096, max_queue: int = 65536):
+        cfg = _ServerConfig(hbm_budget_bytes, max_inflight, max_batch_items, max_queue, 0)
+        h = ctypes.c_void_p()
+        _check(lib().wpcd_server_create(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wpcd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, channels, tlab, want_phases: bool = False) -> Ticket:
+        """channels: list of (basis, J, coefficients); tlab: T_lab values (MeV)."""
+        arr = (_ReqChannel * len(channels))()
+        keep = []
+        n_delta = n_mix = 0
+        for i, (basis, J, coef) in enumerate(channels):
+            c = np.ascontiguousarray(coef, dtype=np.float64)
+            if c.size != basis.n_terms:
+                raise ValueError(f"channel {i}: {basis.n_terms} coefficients expected, got {c.size}")
+            keep.append(c)
+            arr[i] = _ReqChannel(basis.id, J, c.ctypes.data)
+            n_delta += basis.grid.n_wp * basis.n_ch
+            n_mix += basis.grid.n_wp
+        tl = np.ascontiguousarray(tlab, dtype=np.float64)
+        sigma = np.full(tl.size, np.nan)
+        status = np.zeros(len(channels), dtype=np.int32)
+        delta = np.full(n_delta, np.nan) if want_phases else None
+        mix = np.full(n_mix, np.nan) if want_phases else None
+        req = _Request(arr, len(channels), tl.size, tl.ctypes.data if tl.size else None,
+                       sigma.ctypes.data if tl.size else None, delta.ctypes.data if want_phases else None,
+                       mix.ctypes.data if want_phases else None, status.ctypes.data)
+        t = ctypes.c_uint64()
+        _check(lib().wpcd_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return Ticket(t.value, sigma, delta, mix, status)
+
+    def poll(self, ticket: Ticket) -> bool:
+        """True once the request is done (ticket.code holds its status)."""
+        if ticket.code is not None:
+            return True
+        code = lib().wpcd_poll(self._h, ticket.id)
+        if code == WPCD_ERR_AGAIN:
+            return False
+        if code == WPCD_ERR_INVALID:
+            _check(code)
+        ticket.code = code
+        return True
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().wpcd_server_stats_get(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}

@@ -14,11 +14,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwpcd.so")
-SOURCES = ["api.hip", "project.hip", "jacobi.hip", "refine.hip", "tmatrix.hip", "observables.hip"]
+SOURCES = ["api.hip", "project.hip", "jacobi.hip", "refine.hip", "tmatrix.hip", "observables.hip", "serve.cpp"]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for all device code
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-         "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wno-unused-command-line-argument"]
+         "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-pthread",
+         "-Wno-unused-command-line-argument"]
 
 
 def _hipcc() -> str:
@@ -34,7 +35,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -50,7 +51,7 @@ def build(verbose: bool = False) -> str:
     if errors:
         raise RuntimeError("HIP compilation failed:\n" + "\n".join(errors))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)

@@ -98,6 +98,10 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 
 }  // namespace
 
+namespace wpcd {
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace wpcd
+
 extern "C" {
 
 const char* wpcd_last_error(void) { return g_err.c_str(); }
@@ -547,7 +551,7 @@ int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg,
   WPCD_HIP(timed(b->ctx, WPCD_STAGE_SIGMA, stream,
                  [&] {
                    return launch_sigma(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples, b->d_grids,
-                                       delta_deg, mix_deg, tlab_mev, n_tlab, sigma_mb, stream);
+                                       delta_deg, mix_deg, tlab_mev, nullptr, n_tlab, sigma_mb, stream);
                  }),
            "wpcd_sigma_tot launch");
   return WPCD_OK;

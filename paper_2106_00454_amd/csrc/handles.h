@@ -14,6 +14,9 @@ struct GridHost {
   GridDev dev{};
 };
 
+// Records msg as this thread's wpcd_last_error() text; returns code.
+int set_error(int code, const char* msg);
+
 struct BasisHost {
   int grid = 0, nch = 0, n = 0, n_terms = 0;
   double* dbuf = nullptr;  // n_terms * n * n FP64

@@ -83,7 +83,7 @@ hipError_t launch_observables(const ItemDev* items, int n_items, int max_nbins, 
                               const double* t, double* delta, double* mix, double* s_dev, hipStream_t s);
 hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
                         int n_samples, const GridDev* grids, const double* delta, const double* mix,
-                        const double* tlab, int n_tlab, double* sigma, hipStream_t s);
+                        const double* tlab, const int32_t* tlab_off, int n_tlab, double* sigma, hipStream_t s);
 
 // Per-item device work-space (doubles) of the eigensolvers for an n x n item:
 // P1 | Y | S | G | W5 | W6 for the refinement (the FP64 Jacobi uses P1).

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(256) void observables_kernel(const ItemDev* __restr
   mix[it.m_off + k] = e;
 }
 
-// One work-group per sample; threads over the T_lab list.  Every item of the
+// One work-group per sample; threads over the T_lab list (at most
+// 4*kSigBlock energies per sample).  Every item of the
 // sample is unwrapped modulo 180 degrees from its lowest bin upwards (one
 // thread per orbital channel), the mixing angle follows the parity of the
 // shifts applied to its two phases, then each thread interpolates linearly in
@@ -62,13 +63,23 @@ __global__ __launch_bounds__(kSigBlock) void sigma_kernel(const ItemDev* __restr
                                                           const GridDev* __restrict__ grids,
                                                           const double* __restrict__ delta,
                                                           const double* __restrict__ mix,
-                                                          const double* __restrict__ tlab, int n_tlab,
+                                                          const double* __restrict__ tlab,
+                                                          const int32_t* __restrict__ tlab_off, int n_tlab,
                                                           double* __restrict__ sigma) {
   __shared__ double dl[2][kSigMaxBins];
   __shared__ double mx[kSigMaxBins];
   __shared__ int sh[2][kSigMaxBins];
   const int smp = blockIdx.x;
   const int i0 = sample_ptr[smp], i1 = sample_ptr[smp + 1];
+  // the sample's energies: its own slice of a packed list, or the shared list
+  if (tlab_off) {
+    const int j0 = tlab_off[smp];
+    n_tlab = tlab_off[smp + 1] - j0;
+    tlab += j0;
+    sigma += j0;
+  } else {
+    sigma += (int64_t)smp * n_tlab;
+  }
   // each thread owns T_lab indices j = tid, tid + kSigBlock, ...
   constexpr int kPer = 4;  // up to kPer*kSigBlock energies per sample
   double acc[kPer];
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(kSigBlock) void sigma_kernel(const ItemDev* __restr
     const int j = threadIdx.x + q * kSigBlock;
     if (j >= n_tlab) break;
     const double p = sqrt(kMnMeV * tlab[j] / 2.0) / kHbarcMeVfm;
-    sigma[(int64_t)smp * n_tlab + j] = 10.0 * kPi / (2.0 * p * p) * acc[q];
+    sigma[j] = 10.0 * kPi / (2.0 * p * p) * acc[q];
   }
 }
 
@@ -155,10 +166,10 @@ hipError_t launch_observables(const ItemDev* items, int n_items, int max_nbins, 
 
 hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
                         int n_samples, const GridDev* grids, const double* delta, const double* mix,
-                        const double* tlab, int n_tlab, double* sigma, hipStream_t s) {
+                        const double* tlab, const int32_t* tlab_off, int n_tlab, double* sigma, hipStream_t s) {
   if (n_tlab > 4 * kSigBlock) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sigma_kernel, dim3(n_samples), dim3(kSigBlock), 0, s, items, sample_ptr, sample_items, grids,
-                     delta, mix, tlab, n_tlab, sigma);
+                     delta, mix, tlab, tlab_off, n_tlab, sigma);
   return hipGetLastError();
 }
 
