@@ -95,6 +95,7 @@ def main() -> int:
     ap.add_argument("--plain-items", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jacobi-block", type=int, default=0, help="column block width of the LDS Jacobi (0: default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: items are independent and this build has no multi-GPU path "
@@ -108,7 +109,7 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    ctx = wp.Context(0)
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block)
     k = configs.grid("coupled_yukawa")
     g = ctx.grid(k, configs.N_GAUSS)
     B = args.batch

@@ -91,6 +91,11 @@ typedef struct {
                             was below 8*tol ends the iteration (FP32 path;
                             default 2e-7)                                      */
   double jacobi_tol_f64; /* same for the FP64 path (default 1e-15)              */
+  int32_t jacobi_block;  /* column block width of the LDS FP32 Jacobi: 1, 2 or 4
+                            columns per block (registers hold two blocks per
+                            lane group, so LDS traffic falls as 1/width);
+                            0 = library default                              */
+  int32_t pad;
 } wpcd_config;
 
 /* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */

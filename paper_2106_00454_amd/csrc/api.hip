@@ -114,11 +114,13 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   WPCD_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   if (hip_device < 0 || hip_device >= ndev)
     return fail(WPCD_ERR_INVALID, "wpcd_create: device %d out of range (%d devices)", hip_device, ndev);
-  wpcd_config c{30, 2, 2e-7, 1e-15};
+  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0};
   if (cfg) c = *cfg;
   if (c.max_sweeps < 1 || c.max_sweeps > 60) return fail(WPCD_ERR_INVALID, "max_sweeps must be in [1, 60]");
   if (c.refine_steps < 0 || c.refine_steps > 4) return fail(WPCD_ERR_INVALID, "refine_steps must be in [0, 4]");
   if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
+  if (c.jacobi_block != 0 && c.jacobi_block != 1 && c.jacobi_block != 2 && c.jacobi_block != 4)
+    return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2 or 4");
   WPCD_HIP(hipSetDevice(hip_device), "hipSetDevice");
   wpcd_context* ctx = new (std::nothrow) wpcd_context;
   if (!ctx) return fail(WPCD_ERR_NOMEM, "wpcd_create: host allocation");
@@ -487,7 +489,7 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                        if (k < kNumClasses - 1)
                          e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
                                                    b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
-                                                   stream);
+                                                   c.jacobi_block, stream);
                        else
                          e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
                                                   b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,

@@ -141,6 +141,142 @@ __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, i
   return max_sweeps + 1;
 }
 
+// Column-blocked variant of the same iteration for LDS-resident W: columns
+// are grouped into blocks of B (block b holds columns bB .. bB+B-1, columns
+// >= n are absent and stay zero in registers).  A sweep first rotates the
+// pairs inside every block, then runs the round-robin ordering over blocks;
+// at each block step a lane group loads the 2B columns of its two blocks into
+// registers, rotates all B*B cross pairs in B stages of B disjoint pairs
+// (x_i with y_(i+s) mod B at stage s), and stores them back.  Every pair is
+// rotated once per sweep, as in the unblocked ordering, but LDS is read and
+// written once per B*B rotations instead of once per rotation, and there is
+// one barrier per block step.  Same tolerance, stopping rule and return value
+// as onesided_jacobi_lds; RMAX >= ceil(n/G).  Ends with a barrier.
+template <typename T, int G, int RMAX>
+__device__ __forceinline__ void load_col(const T* W, int c, int n, int ld, int lane, T (&x)[RMAX]) {
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    const int r = lane + k * G;
+    x[k] = (c < n && r < n) ? W[(int64_t)c * ld + r] : T(0);
+  }
+}
+template <typename T, int G, int RMAX>
+__device__ __forceinline__ void store_col(T* W, int c, int n, int ld, int lane, const T (&x)[RMAX]) {
+  if (c >= n) return;
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    const int r = lane + k * G;
+    if (r < n) W[(int64_t)c * ld + r] = x[k];
+  }
+}
+// Rotates NP disjoint register column pairs (xs[ia(i)], ys[ib(i)]) of the
+// B-column register blocks xs and ys; the pairs are independent, so their Gram
+// entries are accumulated and reduced together.  rmax collects the largest
+// rotated |w_p.w_q|/(|w_p||w_q|).  The index maps are evaluated on unrolled
+// constants, so every array access resolves to a fixed register.
+template <typename T, int G, int RMAX, int B, int NP, class IA, class IB>
+__device__ __forceinline__ void rotate_pairs(T (&xs)[B][RMAX], T (&ys)[B][RMAX], IA ia, IB ib, T tol, T& rmax) {
+  T al[NP], be[NP], ga[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    al[i] = T(0);
+    be[i] = T(0);
+    ga[i] = T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const T a = xs[ia(i)][k], b = ys[ib(i)][k];
+      al[i] = fma(a, a, al[i]);
+      be[i] = fma(b, b, be[i]);
+      ga[i] = fma(a, b, ga[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    al[i] = group_sum<G>(al[i]);
+    be[i] = group_sum<G>(be[i]);
+    ga[i] = group_sum<G>(ga[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const T nab = sqrt(al[i] * be[i]);
+    if (fabs(ga[i]) > tol * nab) {
+      T c, s;
+      hestenes_rotation(al[i], be[i], ga[i], c, s);
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) {
+        const T a = xs[ia(i)][k], b = ys[ib(i)][k];
+        xs[ia(i)][k] = c * a - s * b;
+        ys[ib(i)][k] = s * a + c * b;
+      }
+      const T rel = fabs(ga[i]) / nab;
+      rmax = rel > rmax ? rel : rmax;
+    }
+  }
+}
+
+template <typename T, int BLOCK, int G, int RMAX, int B>
+__device__ int onesided_jacobi_blocked(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag) {
+  static_assert(B == 1 || B == 2 || B == 4, "block width");
+  const int nb = (n + B - 1) / B;
+  const int nbp = (nb + 1) >> 1;
+  const int nbe = nbp << 1;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    T rmax = T(0);
+    if constexpr (B > 1) {
+      // pairs inside each block: round robin over its B columns
+      for (int blk = grp; blk < nb; blk += ngrp) {
+        T x[B][RMAX];
+#pragma unroll
+        for (int i = 0; i < B; ++i) load_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
+        // circle ordering on B positions: pair i is (pos i, pos B-1-i); pos 0
+        // holds column 0, pos q >= 1 holds column 1 + (q - 1 + st) mod (B - 1)
+#pragma unroll
+        for (int st = 0; st < B - 1; ++st) {
+          auto col = [st](int q) { return q == 0 ? 0 : 1 + (q - 1 + st) % (B - 1); };
+          rotate_pairs<T, G, RMAX, B, B / 2>(x, x, [&](int i) { return col(i); },
+                                             [&](int i) { return col(B - 1 - i); }, tol, rmax);
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i) store_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
+      }
+      __syncthreads();
+    }
+    for (int step = 0; step < nbe - 1; ++step) {
+      for (int pr = grp; pr < nbp; pr += ngrp) {
+        const int P = rr_index(pr, step, nbe);
+        const int Q = rr_index(nbe - 1 - pr, step, nbe);
+        if (P >= nb || Q >= nb) continue;  // the padding block of odd nb
+        T x[B][RMAX], y[B][RMAX];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          load_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
+          load_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st)
+          rotate_pairs<T, G, RMAX, B, B>(x, y, [](int i) { return i; }, [st](int i) { return (i + st) % B; }, tol,
+                                         rmax);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          store_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
+          store_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
+        }
+      }
+      __syncthreads();
+    }
+    if (lane == 0 && rmax > T(0)) atomicMax(&rot_flag[sweep], __float_as_int((float)rmax));
+    __syncthreads();
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+  }
+  return max_sweeps + 1;
+}
+
 // Work-group reductions through a small shared scratch array (>= BLOCK/64 slots).
 template <int BLOCK, typename T, typename Op>
 __device__ T block_reduce(T v, T* scratch, Op op) {

@@ -56,7 +56,7 @@ __device__ T gershgorin_shift(const T* W, int n, int ld, T* scratch) {
 // distinct banks: conflict-free on 64 banks, the minimal two passes on 32.
 __host__ __device__ constexpr int lds_stride(int n) { return n + ((8 - n) % 64 + 64) % 64; }
 
-template <int BLOCK, int G, int RMAX>
+template <int BLOCK, int G, int RMAX, int B>
 __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __restrict__ items,
                                                                const int32_t* __restrict__ sel,
                                                                const GridDev* __restrict__ grids,
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   for (int c = threadIdx.x; c < n; c += BLOCK) W[c * ld + c] += sigma;
   __syncthreads();
 
-  const int sweeps = onesided_jacobi_lds<float, BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag);
+  const int sweeps = onesided_jacobi_blocked<float, BLOCK, G, RMAX, B>(W, n, ld, tol, max_sweeps, rot_flag);
 
   // column norms
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_global_kernel(const ItemDev* __r
 
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
-                                 int32_t* status, int max_sweeps, float tol, hipStream_t s) {
+                                 int32_t* status, int max_sweeps, float tol, int block_cols, hipStream_t s) {
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
@@ -293,9 +293,21 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
                        max_sweeps, tol);
     return hipGetLastError();
   };
-  if (max_n <= 64) return go(jacobi_f32_lds_kernel<256, 4, 16>, 256);
-  if (max_n <= 128) return go(jacobi_f32_lds_kernel<512, 8, 16>, 512);
-  return go(jacobi_f32_lds_kernel<1024, 8, 25>, 1024);
+  // column block width: 0 picks the default per size class
+  const int B = block_cols != 0 ? block_cols : 1;
+  if (max_n <= 64) {
+    if (B == 1) return go(jacobi_f32_lds_kernel<256, 4, 16, 1>, 256);
+    if (B == 2) return go(jacobi_f32_lds_kernel<256, 16, 4, 2>, 256);
+    return go(jacobi_f32_lds_kernel<128, 16, 4, 4>, 128);
+  }
+  if (max_n <= 128) {
+    if (B == 1) return go(jacobi_f32_lds_kernel<512, 8, 16, 1>, 512);
+    if (B == 2) return go(jacobi_f32_lds_kernel<512, 16, 8, 2>, 512);
+    return go(jacobi_f32_lds_kernel<256, 16, 8, 4>, 256);
+  }
+  if (B == 1) return go(jacobi_f32_lds_kernel<1024, 8, 25, 1>, 1024);
+  if (B == 2) return go(jacobi_f32_lds_kernel<1024, 16, 13, 2>, 1024);
+  return go(jacobi_f32_lds_kernel<512, 16, 13, 4>, 512);
 }
 
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
