@@ -7,7 +7,7 @@
 namespace wpcd {
 
 // ---------------------------------------------------------------------------
-// Sums over aligned groups of G lanes (G = 4, 8 or 16) with DPP lane swizzles.
+// Sums over aligned groups of G lanes (G = 2 ... 64) with DPP lane swizzles.
 // Every lane of a group ends with the bitwise-same total: each butterfly stage
 // adds the same two partial sums in either order, and IEEE addition is
 // commutative, so control decisions taken on the result are group-uniform.
@@ -27,22 +27,28 @@ constexpr int kQuadXor2 = 0x4E;    // quad_perm [2,3,0,1]
 constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 
+// Groups of 32 and 64 lanes add the other 16-lane rows with xor shuffles
+// (each pair of lanes again adds the same two values).
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group size");
   if (G >= 2) v += dpp_f32<kQuadXor1>(v);
   if (G >= 4) v += dpp_f32<kQuadXor2>(v);
   if (G >= 8) v += dpp_f32<kRowHalfMirror>(v);
   if (G >= 16) v += dpp_f32<kRowMirror>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group size");
   if (G >= 2) v += dpp_f64<kQuadXor1>(v);
   if (G >= 4) v += dpp_f64<kQuadXor2>(v);
   if (G >= 8) v += dpp_f64<kRowHalfMirror>(v);
   if (G >= 16) v += dpp_f64<kRowMirror>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 

@@ -86,7 +86,8 @@ hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const i
                         const double* tlab, const int32_t* tlab_off, int n_tlab, double* sigma, hipStream_t s);
 
 // Per-item device work-space (doubles) of the eigensolvers for an n x n item:
-// P1 | Y | S | G | W5 | W6 for the refinement (the FP64 Jacobi uses P1).
-inline int64_t eig_work_doubles(int n) { return 6LL * n * n; }
+// P1 | Y | S | G | W5 | W6 for the refinement; the device-memory Jacobi keeps
+// W (n*n elements) and its per-item state (<= 320 bytes) at the start.
+inline int64_t eig_work_doubles(int n) { return 6LL * n * n + 40; }
 
 }  // namespace wpcd

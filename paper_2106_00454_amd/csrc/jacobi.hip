@@ -11,9 +11,11 @@
 //  * jacobi_f32_lds_kernel: one work-group per item, W in LDS, FP32.  Output:
 //    eigenvalues (FP64 array, FP32 accuracy) and eigenvectors as a row-major
 //    FP32 workspace X[r*n + m], both sorted by ascending eigenvalue.
-//  * jacobi_global_kernel: same iteration with W in device memory (any n), in
-//    FP64 for the plain path (output straight to the caller's arrays) or in
-//    FP32 for mixed-path items too large for LDS (output as above).
+//  * gjac_* kernels: the same iteration as a block Jacobi with W in device
+//    memory (any n up to kMaxN), one launch per round-robin stage so that an
+//    item's column blocks run on many compute units; FP64 for the plain path
+//    (output straight to the caller's arrays) or FP32 for mixed-path items too
+//    large for LDS (output as above).
 #include <float.h>
 
 #include "devutil.h"
@@ -130,36 +132,55 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
 }
 
 // ---------------------------------------------------------- device-memory path
-// W (n x n, column-major) lives in the item's device work-space; every pair
-// step reads its two columns twice (Gram entries, then rotation) through the
-// caches.  T = double: the plain FP64 path, eigenvalues as Rayleigh quotients
-// v^T H v / v^T v of v = w/|w| (exact for a diagonal H, free of the shift's
-// rounding), eigenvectors written straight to the caller's FP64 array.
-// T = float: the mixed path for items too large for LDS; eigenvalues |w| - sigma
-// and FP32 eigenvectors in the row-major work-space x32, as the LDS kernel.
-template <typename T, int BLOCK, int G>
-__global__ __launch_bounds__(BLOCK) void jacobi_global_kernel(const ItemDev* __restrict__ items,
-                                                              const int32_t* __restrict__ sel,
-                                                              const GridDev* __restrict__ grids,
-                                                              const double* __restrict__ v64, double* work,
-                                                              double* __restrict__ evec, float* __restrict__ x32,
-                                                              double* __restrict__ eval,
-                                                              int32_t* __restrict__ status, int max_sweeps, T tol) {
-  __shared__ int rot_flag[64];
+// Items too large for LDS (and every item of the plain FP64 path) keep W
+// (n x n, column-major) in their device work-space and run a block Jacobi
+// over column blocks of BW columns, one kernel launch per stage of the sweep so
+// that the blocks of one item are spread over many compute units:
+//   gjac_init:   W = H + sigma I (Gershgorin sigma), per-item state cleared;
+//   gjac_block:  INTRA=true  -- one work-group per block rotates all pairs
+//                               inside it (circle ordering over BW columns);
+//                INTRA=false -- one work-group per block pair of round-robin
+//                               step `step` rotates the BW*BW cross pairs in
+//                               BW stages of BW disjoint pairs;
+//                both stage the 2*BW (or BW) columns in LDS and write them back;
+//   gjac_finish: column norms, eigenvalues, rank sort and outputs.
+// A sweep is one INTRA launch plus the round-robin steps over blocks, so every
+// column pair is rotated once per sweep.  Each launch first reads the previous
+// sweep's largest rotated |w_p.w_q|/(|w_p||w_q|) (kept per item, atomically
+// maxed as float bits) and does nothing once the item has converged, so the
+// host can enqueue all sweeps without waiting.
+template <typename T>
+struct GJacState {
+  T sigma;
+  int32_t pad[3];
+  int32_t rotmax[64];  // per sweep, float bits of the largest rotated pair
+};
+
+template <typename T>
+__device__ __forceinline__ GJacState<T>* gjac_state(double* work, const ItemDev& it) {
+  // after W (n*n elements of T), 16-byte aligned, inside the 6 n^2 doubles
+  const int64_t wbytes = ((int64_t)it.n * it.n * (int64_t)sizeof(T) + 15) & ~(int64_t)15;
+  return reinterpret_cast<GJacState<T>*>(reinterpret_cast<char*>(work + it.w_off) + wbytes);
+}
+
+template <typename T>
+__device__ __forceinline__ bool gjac_converged(const GJacState<T>* st, int sweep, T tol) {
+  return sweep > 0 && __int_as_float(__atomic_load_n(&st->rotmax[sweep - 1], __ATOMIC_RELAXED)) < 8.0f * (float)tol;
+}
+
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restrict__ items,
+                                                          const int32_t* __restrict__ sel,
+                                                          const GridDev* __restrict__ grids,
+                                                          const double* __restrict__ v64, double* work) {
   __shared__ T scratch[BLOCK / 64];
-  __shared__ int bad;
-  __shared__ int rank_of[kMaxN];
-  __shared__ double rq[kMaxN];
-  __shared__ double nrm[kMaxN];
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
   const int n = it.n, N = it.N;
-  const int ld = n;
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
   T* W = reinterpret_cast<T*>(work + it.w_off);
-  for (int i = threadIdx.x; i < 64; i += BLOCK) rot_flag[i] = 0;
-  if (threadIdx.x == 0) bad = 0;
+  GJacState<T>* st = gjac_state<T>(work, it);
   const int64_t nn = (int64_t)n * n;
   for (int64_t e = threadIdx.x; e < nn; e += BLOCK) {
     const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
@@ -167,54 +188,156 @@ __global__ __launch_bounds__(BLOCK) void jacobi_global_kernel(const ItemDev* __r
     if (r == c) h += g.e0[r % N];
     W[e] = (T)h;
   }
+  for (int i = threadIdx.x; i < 64; i += BLOCK) st->rotmax[i] = 0;
   __syncthreads();
-  const T sigma = gershgorin_shift<T, BLOCK>(W, n, ld, scratch);
-  for (int c = threadIdx.x; c < n; c += BLOCK) W[(int64_t)c * ld + c] += sigma;
-  __syncthreads();
+  const T sigma = gershgorin_shift<T, BLOCK>(W, n, n, scratch);
+  for (int c = threadIdx.x; c < n; c += BLOCK) W[(int64_t)c * n + c] += sigma;
+  if (threadIdx.x == 0) st->sigma = sigma;
+}
 
-  const int npair = (n + 1) >> 1, ne = npair << 1;
-  const int lane = threadIdx.x % G, grp = threadIdx.x / G;
-  constexpr int ngrp = BLOCK / G;
-  int sweeps = max_sweeps + 1;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int step = 0; step < ne - 1; ++step) {
-      for (int pr = grp; pr < npair; pr += ngrp) {
-        const int p = rr_index(pr, step, ne), q = rr_index(ne - 1 - pr, step, ne);
-        if (p >= n || q >= n) continue;
-        T* wp = W + (int64_t)p * ld;
-        T* wq = W + (int64_t)q * ld;
-        T al = 0, be = 0, ga = 0;
-        for (int r = lane; r < n; r += G) {
-          const T a = wp[r], b = wq[r];
-          al = fma(a, a, al);
-          be = fma(b, b, be);
-          ga = fma(a, b, ga);
-        }
-        al = group_sum<G>(al);
-        be = group_sum<G>(be);
-        ga = group_sum<G>(ga);
-        const T nab = sqrt(al * be);
-        if (fabs(ga) > tol * nab) {
-          T c, s;
-          hestenes_rotation(al, be, ga, c, s);
-          for (int r = lane; r < n; r += G) {
-            const T a = wp[r], b = wq[r];
-            wp[r] = c * a - s * b;
-            wq[r] = s * a + c * b;
-          }
-          if (lane == 0) atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
-        }
+// LDS column stride of the block kernels: the smallest ld >= n with
+// ld = G (mod 2G) for G < 64 (the 64/G lane groups of a wavefront, each
+// reading G consecutive rows of its own column, start on distinct bank
+// ranges when their columns are consecutive) and ld = 0 (mod 64) for G = 64.
+template <int G>
+__host__ __device__ constexpr int gjac_ld(int n) {
+  return G >= 64 ? n + (64 - n % 64) % 64 : n + ((G - n % (2 * G)) % (2 * G) + 2 * G) % (2 * G);
+}
+
+// Rotates the column pair (p, q) held in LDS by a lane group of G.
+template <typename T, int G, int RMAX>
+__device__ __forceinline__ void lds_pair_rotate(T* wp, T* wq, int n, int lane, T tol, T& rmax) {
+  T xp[RMAX], xq[RMAX];
+  T al = T(0), be = T(0), ga = T(0);
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    const int r = lane + k * G;
+    const T a = r < n ? wp[r] : T(0), b = r < n ? wq[r] : T(0);
+    xp[k] = a;
+    xq[k] = b;
+    al = fma(a, a, al);
+    be = fma(b, b, be);
+    ga = fma(a, b, ga);
+  }
+  al = group_sum<G>(al);
+  be = group_sum<G>(be);
+  ga = group_sum<G>(ga);
+  const T nab = sqrt(al * be);
+  if (fabs(ga) > tol * nab) {
+    T c, s;
+    hestenes_rotation(al, be, ga, c, s);
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+      const int r = lane + k * G;
+      if (r < n) {
+        wp[r] = c * xp[k] - s * xq[k];
+        wq[r] = s * xp[k] + c * xq[k];
+      }
+    }
+    const T rel = fabs(ga) / nab;
+    rmax = rel > rmax ? rel : rmax;
+  }
+}
+
+template <typename T, int BW, int G, int RMAX, bool INTRA>
+__global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __restrict__ items,
+                                                            const int32_t* __restrict__ sel, double* work,
+                                                            int sweep, int step, T tol) {
+  extern __shared__ char lds_raw[];
+  T* L = reinterpret_cast<T*>(lds_raw);
+  const int item = sel ? sel[blockIdx.y] : (int)blockIdx.y;
+  const ItemDev it = items[item];
+  const int n = it.n;
+  const int nb = (n + BW - 1) / BW, nbp = (nb + 1) >> 1, nbe = nbp << 1;
+  int blk[2];
+  int nblk;
+  if (INTRA) {
+    if ((int)blockIdx.x >= nb) return;
+    blk[0] = blockIdx.x;
+    nblk = 1;
+  } else {
+    if (step >= nbe - 1 || (int)blockIdx.x >= nbp) return;
+    blk[0] = rr_index(blockIdx.x, step, nbe);
+    blk[1] = rr_index(nbe - 1 - blockIdx.x, step, nbe);
+    if (blk[0] >= nb || blk[1] >= nb) return;  // the padding block of odd nb
+    nblk = 2;
+  }
+  T* W = reinterpret_cast<T*>(work + it.w_off);
+  GJacState<T>* st = gjac_state<T>(work, it);
+  if (gjac_converged(st, sweep, tol)) return;
+  const int ld = gjac_ld<G>(n);
+  // stage the columns (absent columns beyond n are zero and never written back)
+  for (int b = 0; b < nblk; ++b)
+    for (int j = threadIdx.y; j < BW; j += blockDim.y) {
+      const int c = blk[b] * BW + j;
+      T* dst = L + (b * BW + j) * ld;
+      for (int r = threadIdx.x; r < n; r += G) dst[r] = c < n ? W[(int64_t)c * n + r] : T(0);
+    }
+  __syncthreads();
+  const int lane = threadIdx.x, grp = threadIdx.y;
+  T rmax = T(0);
+  if (INTRA) {
+    // circle ordering over the BW columns: BW-1 stages of BW/2 pairs
+    for (int s = 0; s < BW - 1; ++s) {
+      if (grp < BW / 2) {
+        auto col = [s](int q) { return q == 0 ? 0 : 1 + (q - 1 + s) % (BW - 1); };
+        lds_pair_rotate<T, G, RMAX>(L + col(grp) * ld, L + col(BW - 1 - grp) * ld, n, lane, tol, rmax);
       }
       __syncthreads();
     }
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) {
-      sweeps = sweep + 1;
-      break;
+  } else {
+    // cross pairs: stage s pairs column i of the first block with column
+    // (i + s) mod BW of the second
+    for (int s = 0; s < BW; ++s) {
+      lds_pair_rotate<T, G, RMAX>(L + grp * ld, L + (BW + (grp + s) % BW) * ld, n, lane, tol, rmax);
+      __syncthreads();
     }
   }
-  // column norms and eigenvalue estimates
+  for (int b = 0; b < nblk; ++b)
+    for (int j = threadIdx.y; j < BW; j += blockDim.y) {
+      const int c = blk[b] * BW + j;
+      if (c >= n) continue;
+      const T* src = L + (b * BW + j) * ld;
+      for (int r = threadIdx.x; r < n; r += G) W[(int64_t)c * n + r] = src[r];
+    }
+  if (lane == 0 && rmax > T(0)) atomicMax(&st->rotmax[sweep], __float_as_int((float)rmax));
+}
+
+// Norms, eigenvalues and sorted outputs.  T = double: eigenvalues as Rayleigh
+// quotients v^T H v / v^T v of v = w/|w| (exact for a diagonal H, free of the
+// shift's rounding), eigenvectors to the caller's FP64 array.  T = float:
+// eigenvalues |w| - sigma and FP32 eigenvectors in the row-major x32.
+template <typename T, int BLOCK, int G>
+__global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __restrict__ items,
+                                                            const int32_t* __restrict__ sel,
+                                                            const GridDev* __restrict__ grids,
+                                                            const double* __restrict__ v64, double* work,
+                                                            double* __restrict__ evec, float* __restrict__ x32,
+                                                            double* __restrict__ eval, int32_t* __restrict__ status,
+                                                            int max_sweeps, T tol) {
+  __shared__ int bad;
+  __shared__ int rank_of[kMaxN];
+  __shared__ double rq[kMaxN];
+  __shared__ double nrm[kMaxN];
+  const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
+  const ItemDev it = items[item];
+  const int n = it.n, N = it.N;
+  const GridDev g = grids[it.grid];
+  const double* V = v64 + it.v_off;
+  const T* W = reinterpret_cast<const T*>(work + it.w_off);
+  const GJacState<T>* st = gjac_state<T>(work, it);
+  const T sigma = st->sigma;
+  int sweeps = max_sweeps + 1;
+  for (int s = 0; s < max_sweeps; ++s)
+    if (__int_as_float(st->rotmax[s]) < 8.0f * (float)tol) {
+      sweeps = s + 1;
+      break;
+    }
+  if (threadIdx.x == 0) bad = 0;
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
   for (int c = grp; c < n; c += ngrp) {
-    const T* col = W + (int64_t)c * ld;
+    const T* col = W + (int64_t)c * n;
     T s2 = 0;
     for (int r = lane; r < n; r += G) s2 = fma(col[r], col[r], s2);
     const T nc = sqrt(group_sum<G>(s2));
@@ -259,7 +382,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_global_kernel(const ItemDev* __r
       continue;
     }
     const int rank = rank_of[c];
-    const T* col = W + (int64_t)c * ld;
+    const T* col = W + (int64_t)c * n;
     if (sizeof(T) == 8) {
       double* X = evec + it.v_off;
       for (int r = lane; r < n; r += G) X[(int64_t)r * n + rank] = (double)col[r] / nc;
@@ -273,6 +396,35 @@ __global__ __launch_bounds__(BLOCK) void jacobi_global_kernel(const ItemDev* __r
   for (int c = threadIdx.x; c < n; c += BLOCK) ev[rank_of[c]] = rq[c];
   if (threadIdx.x == 0)
     status[item] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
+}
+
+// Host side: init, max_sweeps x (INTRA + round-robin steps), finish.
+template <typename T, int BW, int G, int RMAX>
+hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max_n, const GridDev* grids,
+                    const double* v64, double* work, double* evec, float* x32, double* eval, int32_t* status,
+                    int max_sweeps, T tol, hipStream_t s) {
+  static_assert(BW * G <= 1024, "block size");
+  if (max_n > RMAX * G) return hipErrorInvalidValue;
+  const size_t lds = (size_t)2 * BW * gjac_ld<G>(max_n) * sizeof(T);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  auto intra = gjac_block_kernel<T, BW, G, RMAX, true>;
+  auto cross = gjac_block_kernel<T, BW, G, RMAX, false>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(intra),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(cross), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  if (e != hipSuccess) return e;
+  const int nb = (max_n + BW - 1) / BW, nbp = (nb + 1) >> 1, nbe = nbp << 1;
+  hipLaunchKernelGGL((gjac_init_kernel<T, 1024>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work);
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    hipLaunchKernelGGL(intra, dim3(nb, n_sel), dim3(G, BW), lds, s, items, sel, work, sw, 0, tol);
+    for (int step = 0; step < nbe - 1; ++step)
+      hipLaunchKernelGGL(cross, dim3(nbp, n_sel), dim3(G, BW), lds, s, items, sel, work, sw, step, tol);
+  }
+  hipLaunchKernelGGL((gjac_finish_kernel<T, 1024, 16>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work,
+                     evec, x32, eval, status, max_sweeps, tol);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -315,13 +467,30 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
                                 double* eval, int32_t* status, int max_sweeps, double tol, hipStream_t s) {
   if (max_n > kMaxN || max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
-  if (mixed)
-    hipLaunchKernelGGL((jacobi_global_kernel<float, 1024, 8>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64,
-                       work, evec, x32, eval, status, max_sweeps, (float)tol);
-  else
-    hipLaunchKernelGGL((jacobi_global_kernel<double, 1024, 8>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids,
-                       v64, work, evec, x32, eval, status, max_sweeps, tol);
-  return hipGetLastError();
+  // block width: two blocks of the largest item fill at most 160 KiB of LDS;
+  // lane groups of G rows x RMAX rows per lane cover n
+  if (mixed) {
+    const float t = (float)tol;
+    if (max_n <= 304)
+      return gjac_run<float, 64, 16, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+                                         max_sweeps, t, s);
+    if (max_n <= 608)
+      return gjac_run<float, 32, 32, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+                                         max_sweeps, t, s);
+    return gjac_run<float, 16, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+                                       max_sweeps, t, s);
+  }
+  if (max_n <= 144)
+    return gjac_run<double, 64, 16, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+                                       max_sweeps, tol, s);
+  if (max_n <= 288)
+    return gjac_run<double, 32, 32, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+                                       max_sweeps, tol, s);
+  if (max_n <= 640)
+    return gjac_run<double, 16, 64, 10>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+                                        max_sweeps, tol, s);
+  return gjac_run<double, 8, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status, max_sweeps,
+                                     tol, s);
 }
 
 }  // namespace wpcd

@@ -51,7 +51,7 @@ struct Req {
 size_t item_bytes(const ReqChannel& c) {
   const size_t n = c.n, N = c.N, K = c.nch;
   return sizeof(ItemDev) + 3 * sizeof(int32_t) + 8 * c.n_terms +              // descriptors, class, sitems, coef
-         n * n * (8 + 8 + 4 + 8 * 6) +                                        // v64, evec, x32, work
+         n * n * (8 + 8 + 4) + 8 * eig_work_doubles((int)n) +                // v64, evec, x32, work
          n * (4 + 8 + 8) +                                                    // cl, lam, eval
          8 * (2 * N * K * K + N * K + N + N * K) + 2 * sizeof(int32_t);      // t, delta, mix, s_dev, statuses
 }
@@ -113,13 +113,14 @@ int sfail(int code, const char* msg) { return set_error(code, msg); }
 
 Layout plan(const std::vector<Req*>& take, int64_t& n_items) {
   Layout L{};
-  int64_t ni = 0, nc = 0, nt = 0, vv = 0, ne = 0, td = 0, de = 0, me = 0;
+  int64_t ni = 0, nc = 0, nt = 0, vv = 0, ne = 0, td = 0, de = 0, me = 0, wd = 0;
   for (Req* r : take) {
     nt += r->tlab.size();
     for (auto& c : r->ch) {
       ni++;
       nc += c.n_terms;
       vv += (int64_t)c.n * c.n;
+      wd += eig_work_doubles(c.n);
       ne += c.n;
       td += 2LL * c.N * c.nch * c.nch;
       de += (int64_t)c.N * c.nch;
@@ -150,7 +151,7 @@ Layout plan(const std::vector<Req*>& take, int64_t& n_items) {
   L.v64 = put(8 * vv);
   L.evec = put(8 * vv);
   L.x32 = put(4 * vv);
-  L.work = put(8 * 6 * vv);
+  L.work = put(8 * wd);
   L.cl = put(4 * ne);
   L.lam = put(8 * ne);
   L.eval = put(8 * ne);

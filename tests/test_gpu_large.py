@@ -1,0 +1,55 @@
+"""Large-mesh coupled items beyond LDS (n = 2 N_WP = 600) against the FP64 oracle.
+
+The eigenpairs of such items come from the device-memory FP32 Jacobi plus the
+FP64 refinement (WPCD_MIXED) or the device-memory FP64 Jacobi (WPCD_F64); the
+potential is the coupled Yukawa + tensor form of the sweep's 3S1-3D1 and
+3D3-3G3 channels, projected from registered affine bases.  Bars: phase shifts
+and mixing angles within 0.01 deg, sigma over both channels within 0.01 mb.
+"""
+import numpy as np
+import pytest
+
+import paper_2106_00454_amd as wp
+from oracle import observables as oo
+from oracle import wpcd as ow
+from synth import sweep
+from tests.gpu_util import SIGMA_TOL, check_item, item_view, run_items
+
+pytestmark = pytest.mark.gpu
+
+N_WP = 300
+CHANNELS = (14, 16)     # 3S1-3D1 (J = 1), 3D3-3G3 (J = 3)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    ctx = wp.Context(0)
+    k = sweep.grid_bounds(N_WP)
+    g = ctx.grid(k, sweep.N_GAUSS)
+    xo, _ = ow.gauss_nodes(k, sweep.N_GAUSS)
+    lib_terms, or_terms = sweep.TermCache(), sweep.TermCache()
+    specs, coefs, refs = [], [], []
+    for c in CHANNELS:
+        bs = ctx.basis(g, 2, lib_terms.terms(("lib", N_WP), g.nodes, c))
+        specs.append((g, 2, sweep.CHANNELS[c][2], 0, bs))
+        coefs.append(sweep.coefficients(3, c))
+        u = sum(ci * t for ci, t in zip(sweep.coefficients(3, c), or_terms.terms(("or", N_WP), xo, c)))
+        refs.append(ow.solve_channel(k, sweep.N_GAUSS, u, 2))
+    return ctx, k, specs, coefs, refs
+
+
+@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
+def test_large_mesh_matches_oracle(setup, mode):
+    ctx, k, specs, coefs, refs = setup
+    b, host = run_items(ctx, specs, None, mode, tlab=sweep.TLAB, coef=coefs)
+    assert b.layout["max_n"] == 2 * N_WP
+    _, kbar, _ = ow.bins(k)
+    chans = []
+    for i, (c, ref) in enumerate(zip(CHANNELS, refs)):
+        it = item_view(b, host, i)
+        J = sweep.CHANNELS[c][2]
+        check_item(f"large mode={mode} {sweep.CHANNELS[c][0]} n={2 * N_WP}", it, ref, k, mode, J)
+        chans.append((J, ref["delta"], ref["mix"]))
+    ds = np.abs(host["sigma"][0] - oo.sigma_tot(chans, kbar, sweep.TLAB, k[-1])).max()
+    print(f"large mode={mode}: dsigma={ds:.3e} mb", flush=True)
+    assert ds <= SIGMA_TOL
