@@ -85,6 +85,177 @@ def cpu_baseline(seconds: float) -> dict:
                       f"one single-threaded process per core, {wall:.1f} s wall"}
 
 
+# ------------------------------------------------------- other workloads
+def _jacobi_flops(ns, sweeps):
+    """One-sided Jacobi work: per sweep n(n-1)/2 pair rotations of 12 n flops."""
+    ns = np.asarray(ns, dtype=np.float64)
+    return float(np.sum(np.asarray(sweeps, dtype=np.float64) * ns * (ns - 1) / 2 * 12 * ns))
+
+
+def _register_bases(ctx, cache, n_wps, channels):
+    from synth import sweep
+    grids = {N: ctx.grid(sweep.grid_bounds(N), sweep.N_GAUSS) for N in n_wps}
+    bases = {}
+    for N in n_wps:
+        for c in channels:
+            bases[(c, N)] = ctx.basis(grids[N], sweep.CHANNELS[c][1], cache.terms(("lib", N), grids[N].nodes, c))
+    return grids, bases
+
+
+def _affine_batch_run(args, ctx, specs, coefs, tlab, label):
+    """Stage an affine batch, warm up, time args.steps passes; returns the common JSON fields."""
+    import torch
+    import paper_2106_00454_amd as wp
+    b = ctx.batch(specs)
+    c = np.zeros(max(1, b.layout["coef_elems"]))
+    for i, ci in enumerate(coefs):
+        c[b.coef_off[i]:b.coef_off[i] + len(ci)] = ci
+    coef = torch.tensor(c, dtype=torch.float64, device="cuda")
+    bufs = b.alloc()
+    tl = torch.tensor(tlab, dtype=torch.float64, device="cuda")
+    sigma = torch.empty(b.layout["n_samples"] * len(tlab), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        b.run(None, bufs, wp.MIXED, tl, sigma, coef=coef)
+    torch.cuda.synchronize()
+    st_e = bufs["eig_status"].cpu().numpy()
+    st_t = bufs["t_status"].cpu().numpy()
+    if (st_e <= 0).any() or (st_t != 0).any():
+        log(f"{label}: item failures: eig {int((st_e <= 0).sum())} tmatrix {int((st_t != 0).sum())}")
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run(None, bufs, wp.MIXED, tl, sigma, coef=coef)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.profile(False)
+    ns = [sp[1] * sp[0].n_wp for sp in specs]
+    value = len(specs) * args.steps / wall
+    log(f"{label}: {value:.0f} channel-solves/s, {wall / args.steps * 1e3:.2f} ms/step")
+    avg = {k: (ms / cnt if cnt else 0.0) for k, (ms, cnt) in stages.items()}
+    jac = _jacobi_flops(ns, np.maximum(st_e, 0)) / (stages["jacobi_f32"][0] / args.steps * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": jac, "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": jac / PEAK_FP32_VALU,
+            "traffic": None, "kernel": "jacobi_f32 (all size classes)",
+            "avg_stage_ms": stages["jacobi_f32"][0] / args.steps}
+    return {"value": value, "unit": "channel-solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "jacobi_sweeps_mean": float(st_e[st_e > 0].mean()) if (st_e > 0).any() else None,
+            "stages_ms_per_step": {k: ms / args.steps for k, (ms, cnt) in stages.items() if cnt},
+            "stage_avg_launch_ms": {k: v for k, v in avg.items() if v}, "roofline": roof, "cpu_baseline": None}
+
+
+def run_sweep(args) -> dict:
+    """J <= 6 batched sweep: args.samples x 20 channels, N_WP from {50, 100, 150}, affine bases."""
+    import paper_2106_00454_amd as wp
+    from synth import sweep
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block)
+    t0 = time.perf_counter()
+    _, bases = _register_bases(ctx, sweep.TermCache(), sweep.N_WP_CHOICES, range(len(sweep.CHANNELS)))
+    log(f"sweep: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
+    items = sweep.items(args.samples)
+    specs = [(bases[(c, N)].grid, sweep.CHANNELS[c][1], sweep.CHANNELS[c][2], s, bases[(c, N)])
+             for s, c, N in items]
+    coefs = [sweep.coefficients(s, c) for s, c, N in items]
+    out = _affine_batch_run(args, ctx, specs, coefs, sweep.TLAB, "sweep")
+    out["metric"] = "channel-solves/sec (J<=6 sweep, 20 channels, N_WP in {50,100,150}, sigma_tot per sample)"
+    out["config"] = {"workload": f"batched sweep: {args.samples} samples x 20 channels (J<=6), N_WP uniform in "
+                                 "{50,100,150}, affine Yukawa+tensor bases, sigma_tot at 30 T_lab per sample",
+                     "items_per_step": len(specs)}
+    return out
+
+
+def run_large(args) -> dict:
+    """Large mesh: 64 samples x 6 coupled channels (J = 1..6) at N_WP = args.large_nwp."""
+    import paper_2106_00454_amd as wp
+    from synth import sweep
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block)
+    coupled = [c for c in range(len(sweep.CHANNELS)) if sweep.CHANNELS[c][1] == 2]
+    N = args.large_nwp
+    t0 = time.perf_counter()
+    _, bases = _register_bases(ctx, sweep.TermCache(), (N,), coupled)
+    log(f"large: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
+    specs, coefs = [], []
+    for s in range(64):
+        for c in coupled:
+            specs.append((bases[(c, N)].grid, 2, sweep.CHANNELS[c][2], s, bases[(c, N)]))
+            coefs.append(sweep.coefficients(s, c))
+    out = _affine_batch_run(args, ctx, specs, coefs, sweep.TLAB, "large")
+    out["metric"] = f"channel-solves/sec (coupled, N_WP={N}, device-memory eigensolver)"
+    out["config"] = {"workload": f"large mesh: 64 samples x 6 coupled channels (J=1..6), N_WP={N} "
+                                 f"({2 * N}x{2 * N} H), affine bases", "items_per_step": len(specs)}
+    return out
+
+
+def run_serve(args) -> dict:
+    """Poisson arrivals of parameter-vector requests with random channel subsets."""
+    import paper_2106_00454_amd as wp
+    from synth import sweep
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block)
+    n_wps = (50, 100, 150, 200)
+    t0 = time.perf_counter()
+    _, bases = _register_bases(ctx, sweep.TermCache(), n_wps, range(len(sweep.CHANNELS)))
+    log(f"serve: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
+    srv = wp.Server(ctx, hbm_budget_bytes=16 << 30, max_inflight=4, max_batch_items=2048)
+    rng = np.random.default_rng(np.random.SeedSequence([20210601 + 4, 0]))
+    warm = 5.0
+    n_req = int((args.duration + warm) * args.rate * 1.2) + 10
+    gaps = rng.exponential(1.0 / args.rate, n_req)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < args.duration + warm]
+    reqs = []
+    for r in range(arrivals.size):
+        k = int(rng.integers(1, 21))
+        chans = rng.choice(20, size=k, replace=False)
+        N = int(rng.choice(n_wps))
+        reqs.append([(bases[(int(c), N)], sweep.CHANNELS[int(c)][2], sweep.coefficients(r, int(c))) for c in chans])
+    log(f"serve: {len(reqs)} requests generated")
+    lat, t_done, outstanding = [], [], []
+    n_items = 0
+    start = time.perf_counter()
+    nxt = 0
+    while nxt < len(reqs) or outstanding:
+        now = time.perf_counter() - start
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            tk = srv.submit(reqs[nxt], sweep.TLAB)
+            outstanding.append((tk, arrivals[nxt], len(reqs[nxt])))
+            nxt += 1
+        still = []
+        for tk, ta, nc in outstanding:
+            if srv.poll(tk):
+                tnow = time.perf_counter() - start
+                if ta >= warm:
+                    lat.append((tnow - ta) * 1e3)
+                    t_done.append(tnow)
+                    n_items += nc
+                if tk.code != 0:
+                    log(f"serve: request failed with code {tk.code}")
+            else:
+                still.append((tk, ta, nc))
+        outstanding = still
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    span = max(t_done) - warm if t_done else float("nan")
+    out = {
+        "metric": "serving: p50/p99 latency (ms) and channel-solves/s under Poisson arrivals",
+        "value": float(np.percentile(lat, 99)), "unit": "ms (p99 latency)", "n_gpus": 1, "steps": len(lat),
+        "warmup": int(np.sum(arrivals < warm)), "ms_per_step": float(np.mean(lat)), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {args.rate:.0f} req/s for {args.duration:.0f} s after "
+                               f"{warm:.0f} s warm-up; each request 1-20 random channels of the J<=6 set, "
+                               "N_WP uniform in {50,100,150,200}, sigma_tot at 30 T_lab"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "throughput": {"requests_per_s": len(lat) / span, "channel_solves_per_s": n_items / span},
+        "server": st, "roofline": None, "cpu_baseline": None,
+    }
+    log(f"serve: p50 {out['latency_ms']['p50']:.2f} ms p99 {out['latency_ms']['p99']:.2f} ms, "
+        f"{out['throughput']['channel_solves_per_s']:.0f} channel-solves/s, {st['batches']} batches")
+    return out
+
+
 # ----------------------------------------------------------------- GPU path
 def main() -> int:
     ap = argparse.ArgumentParser()
@@ -96,11 +267,22 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jacobi-block", type=int, default=0, help="column block width of the LDS Jacobi (0: default)")
+    ap.add_argument("--workload", choices=("coupled", "sweep", "large", "serve"), default="coupled",
+                    help="coupled: the headline line; sweep / large / serve: the other workloads")
+    ap.add_argument("--samples", type=int, default=512, help="sweep: parameter samples per step")
+    ap.add_argument("--large-nwp", type=int, default=300, help="large: N_WP of the coupled items")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals after warm-up")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: items are independent and this build has no multi-GPU path "
               "(sharding by parameter sample is described in DESIGN.md); run with --gpus 1", flush=True)
         return 2
+
+    if args.workload != "coupled":
+        out = {"sweep": run_sweep, "large": run_large, "serve": run_serve}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return 0
 
     import torch
     import paper_2106_00454_amd as wp

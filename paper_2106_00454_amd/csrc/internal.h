@@ -59,8 +59,6 @@ constexpr int kNumClasses = 4;
 inline int size_class(int n) { return n <= 64 ? 0 : (n <= 128 ? 1 : (n <= kMaxLdsN ? 2 : 3)); }
 // Largest item the library accepts in this build.
 constexpr int kMaxN = 1200;
-// Largest cluster handled by one Rayleigh-Ritz solve in the refinement.
-constexpr int kMaxCluster = 64;
 
 // Kernel launchers (each returns hipSuccess or the launch error).
 hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const void* u,
@@ -86,8 +84,8 @@ hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const i
                         const double* tlab, const int32_t* tlab_off, int n_tlab, double* sigma, hipStream_t s);
 
 // Per-item device work-space (doubles) of the eigensolvers for an n x n item:
-// P1 | Y | S | G | W5 | W6 for the refinement; the device-memory Jacobi keeps
-// W (n*n elements) and its per-item state (<= 320 bytes) at the start.
-inline int64_t eig_work_doubles(int n) { return 6LL * n * n + 40; }
+// P1 | Y | S | G | W5 | W6 | W7 for the refinement; the device-memory Jacobi
+// keeps W (n*n elements) and its per-item state (<= 320 bytes) at the start.
+inline int64_t eig_work_doubles(int n) { return 7LL * n * n + 40; }
 
 }  // namespace wpcd

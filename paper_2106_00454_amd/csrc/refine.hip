@@ -8,13 +8,14 @@
 //   X <- X (I + E).
 // The first-order update is only accurate where |E_ij| is small.  A pair is
 // called close when c |S_ij + lam_j R_ij| >= |lam_j - lam_i| (or the same with
-// lam_i in the numerator), c = 1000, i.e. when its predicted correction would
-// reach 1e-3; close pairs take E_ij = R_ij/2 (orthogonalisation only) and every
-// maximal index range spanned by close pairs (a chain) is solved exactly by
-// Rayleigh-Ritz: with P = (I + E)[:, chain], X P spans the refined chain
-// subspace and (X P)^T A (X P) = P^T S P, whose eigenvectors Q (FP64 one-sided
-// Jacobi, all chains at once as one block-diagonal matrix) rotate the chain:
-// the update becomes X <- X M with M = I + E except M[:, chain] = P Q.
+// lam_i in the numerator), i.e. when its predicted correction would reach 1/c,
+// with c = 1000 in the first step and 10x more in each later one.  Close
+// pairs take E_ij = R_ij/2 (orthogonalisation only) and every maximal index
+// range spanned by close pairs (a chain) is solved exactly by Rayleigh-Ritz:
+// with P = (I + E)[:, chain], X P spans the refined chain subspace and
+// (X P)^T A (X P) = P^T S P, whose eigenvectors Q (FP64 one-sided Jacobi)
+// rotate the chain: the update becomes X <- X M with M = I + E except
+// M[:, chain] = P Q.
 // This replaces the published cluster threshold (a Frobenius-norm bound that
 // is far too coarse for an FP32 starting point and lets badly conditioned
 // Newton updates through) by a direct bound on the size of each update.
@@ -39,8 +40,14 @@ constexpr int kBlock = 256;    // 4 wavefronts
 constexpr int kTM = 64;        // output tile edge
 constexpr int kTK = 32;        // reduction chunk
 constexpr int kLdT = kTM + 4;  // LDS stride of a staged operand tile (doubles)
-constexpr int kMaxChain = 64;  // columns in Rayleigh-Ritz chains per item
-constexpr double kCloseC = 1000.0;
+constexpr int kMaxChain = 64;  // columns of one LDS Rayleigh-Ritz batch
+constexpr int kMaxBig = 24;    // longer chains per item, solved in device memory
+constexpr int kBigRows = 19;   // rows per lane of their Jacobi (64 * 19 >= kMaxN)
+// Closeness constant of refinement step st: c = kCloseC0 * 10^st.  The first
+// step starts from FP32 vectors and admits Newton updates up to 1e-3; later
+// steps start from much better vectors and take only updates up to 10^-(3+st),
+// whose second-order remainders are below FP64 orthogonality.
+constexpr double kCloseC0 = 1000.0;
 
 // --------------------------------------------------------------- GEMM tiles
 // acc = sum_k A(m0+i, k) B(k, c0+j) over one 64 x 64 tile; fa(i,k) gives A,
@@ -175,20 +182,20 @@ struct RowMajorT {  // A operand M^T or B operand M (fb(j,k) = M[k][j])
 
 // Newton correction E(k,j) for k != j (R_kj/2 for a close pair), R_jj/2 on the diagonal
 __device__ __forceinline__ double newton_e(const double* S, const double* G, const double* lam, int n, int k,
-                                           int j) {
+                                           int j, double closec) {
   const double g = G[(int64_t)k * n + j];
   if (j == k) return 0.5 * (1.0 - g);
   const double r = -g;
   const double d = fabs(lam[j] - lam[k]);
   const double s = S[(int64_t)k * n + j];
   const double num = s + lam[j] * r;
-  if (kCloseC * fabs(num) >= d || kCloseC * fabs(s + lam[k] * r) >= d) return 0.5 * r;
+  if (closec * fabs(num) >= d || closec * fabs(s + lam[k] * r) >= d) return 0.5 * r;
   return num / (lam[j] - lam[k]);
 }
 
-// Per-item work-space (doubles): P1 | Y | S | G | W5 | W6, each n*n.
+// Per-item work-space (doubles): P1 | Y | S | G | W5 | W6 | W7, each n*n.
 struct WS {
-  double *P1, *Y, *S, *G, *W5, *W6;
+  double *P1, *Y, *S, *G, *W5, *W6, *W7;
   __device__ WS(double* work, const ItemDev& it) {
     const int64_t nn = (int64_t)it.n * it.n;
     P1 = work + it.w_off;
@@ -197,6 +204,7 @@ struct WS {
     G = S + nn;
     W5 = G + nn;
     W6 = W5 + nn;
+    W7 = W6 + nn;
   }
 };
 
@@ -266,7 +274,7 @@ template <typename XT>
 __global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restrict__ items, int item0,
                                                          const XT* xin, int xin_ws, double* evec, int xout_ws,
                                                          const double* __restrict__ lam_pre, double* work,
-                                                         const int32_t* __restrict__ cl) {
+                                                         const int32_t* __restrict__ cl, double closec) {
   __shared__ double As[kTK * kLdT];
   __shared__ double Bs[kTK * kLdT];
   __shared__ double lam[kMaxN];
@@ -295,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restri
   auto fb = [&](int j, int k) -> double {  // M(k, j)
     const int q = cpos[j];
     if (q >= 0) return MC[(int64_t)k * T + q];
-    return (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j);
+    return (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j, closec);
   };
   d4 acc[2][2];
   gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajor<XT>{X, n}, fb, acc);
@@ -304,18 +312,21 @@ __global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restri
 
 // ------------------------------------------------------------ chain kernel
 // One work-group per item: Rayleigh quotients, close pairs and chains, and the
-// Rayleigh-Ritz rotation of every chain.  Chains are processed in batches of
-// whole chains with at most kMaxChain columns; for a batch with columns
-// cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb), P^T S P -> LDS (kept
-// block-diagonal, one block per chain), one-sided Jacobi, Q -> LDS, and P Q ->
-// columns [pos, pos + Tb) of the n x Ttot matrix in W6.  Writes the quotients
+// Rayleigh-Ritz rotation of every chain.  Chains of up to kMaxChain columns
+// are processed in batches of whole chains with at most kMaxChain columns;
+// for a batch with columns cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb),
+// P^T S P -> LDS (kept block-diagonal, one block per chain), one-sided Jacobi,
+// Q -> LDS, and P Q -> columns [pos, pos + Tb) of the n x Ttot matrix in W6.
+// Longer chains (dense parts of the spectrum of large items) are solved one
+// at a time in device memory: P -> W5, S P -> Y, P^T S P -> W7 (m x m), FP64
+// one-sided Jacobi on W7, the sorted Q -> Y, P Q -> W6.  Writes the quotients
 // to lam_pre, the refined eigenvalues to eval, and cl[j] = position of column
 // j among all chain columns, or -1.
 __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __restrict__ items,
                                                               double* __restrict__ lam_pre,
                                                               double* __restrict__ eval, double* work,
                                                               int32_t* __restrict__ cl,
-                                                              int32_t* __restrict__ status) {
+                                                              int32_t* __restrict__ status, double closec) {
   constexpr int ldw = kMaxChain | 1;
   __shared__ double As[kTK * kLdT];
   __shared__ double Bs[kTK * kLdT];
@@ -330,7 +341,10 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
   __shared__ int cols[kMaxChain];
   __shared__ int blk[kMaxChain];
   __shared__ int rot_flag[64];
-  __shared__ int s_Ttot, s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail;
+  __shared__ double bnrm[kMaxN];
+  __shared__ short big_start[kMaxBig], big_len[kMaxBig], big_pos[kMaxBig];
+  __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
+  __shared__ int s_Ttot, s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail, s_nbig;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
   const WS ws(work, it);
@@ -348,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
         const double r = -G[(int64_t)p * n + q];
         const double s = S[(int64_t)p * n + q];
         const double d = fabs(lam[q] - lam[p]);
-        if (kCloseC * fabs(s + lam[q] * r) >= d || kCloseC * fabs(s + lam[p] * r) >= d) rq = q;
+        if (closec * fabs(s + lam[q] * r) >= d || closec * fabs(s + lam[p] * r) >= d) rq = q;
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
@@ -362,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
   __syncthreads();
   // chains = unions of overlapping [p, reach[p]] with at least two columns
   if (threadIdx.x == 0) {
-    int T = 0, fail = 0, i = 0, nch = 0;
+    int T = 0, fail = 0, i = 0, nch = 0, nbig = 0;
     int32_t* c = cl + it.e_off;
     while (i < n) {
       int j = reach[i], q = i;
@@ -377,14 +391,26 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
         ch_len[nch] = (short)m;
         ++nch;
         T += m;
+      } else if (m > kMaxChain && nbig < kMaxBig) {
+        big_start[nbig] = (short)i;
+        big_len[nbig] = (short)m;
+        ++nbig;
       } else {
-        if (m > kMaxChain) fail = 1;  // one chain larger than a Rayleigh-Ritz batch
+        if (m > kMaxChain) fail = 1;  // more long chains than the list holds
         for (int t = 0; t < m; ++t) c[i + t] = -1;
       }
       i = j + 1;
     }
+    // the short chains' columns come first in the chain matrix (in the order
+    // their batches are processed), the long chains' after them
+    for (int b = 0; b < nbig; ++b) {
+      big_pos[b] = (short)T;
+      for (int t = 0; t < big_len[b]; ++t) c[big_start[b] + t] = T + t;
+      T += big_len[b];
+    }
     s_Ttot = T;
     s_nch = nch;
+    s_nbig = nbig;
     s_fail = fail;
     s_c1 = 0;
     s_pos = 0;
@@ -421,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     for (int64_t e = threadIdx.x; e < (int64_t)n * Tb; e += kBlock) {
       const int k = (int)(e / Tb), t = (int)(e - (int64_t)k * Tb);
       const int j = cols[t];
-      P[e] = (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j);
+      P[e] = (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j, closec);
     }
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm) {
@@ -476,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
         rank += (lq < lj || (lq == lj && q < j)) ? 1 : 0;
       }
       for (int r = 0; r < Tb; ++r) Qs[r * kMaxChain + rank] = W[j * ldw + r] / nrm[j];
-      lam[cols[rank]] = lj;
+      eval[it.e_off + cols[rank]] = lj;
     }
     __syncthreads();
     // P Q -> chain columns [pos, pos + Tb) of MC
@@ -489,7 +515,96 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     if (threadIdx.x == 0) s_pos = pos + Tb;
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += kBlock) eval[it.e_off + i] = lam[i];
+  // long chains, one at a time in device memory
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* C = ws.W7;
+  double* Q = ws.Y;
+  for (int b = 0; b < s_nbig; ++b) {
+    const int i0 = big_start[b], m = big_len[b], pos = big_pos[b];
+    const int mt = (m + kTM - 1) / kTM;
+    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += kBlock) {
+      const int k = (int)(e / m), t = (int)(e - (int64_t)k * m);
+      P[e] = (k == i0 + t ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, i0 + t, closec);
+    }
+    __syncthreads();
+    for (int tm = 0; tm < nt; ++tm)
+      for (int tc = 0; tc < mt; ++tc) {
+        gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, m, n, RowMajor<double>{S, n},
+                               RowMajorT<double>{P, m}, acc);
+        tile_store(tm * kTM, tc * kTM, n, m, acc, [&](int r, int cc, double v) { SP[(int64_t)r * m + cc] = v; });
+      }
+    __syncthreads();
+    for (int tm = 0; tm < mt; ++tm)
+      for (int tc = tm; tc < mt; ++tc) {
+        gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, m, m, n, RowMajorT<double>{P, m},
+                                RowMajorT<double>{SP, m}, acc);
+        tile_store(tm * kTM, tc * kTM, m, m, acc, [&](int r, int cc, double v) {
+          if (r > cc) return;  // symmetric: one writer per pair
+          C[(int64_t)cc * m + r] = v;
+          C[(int64_t)r * m + cc] = v;
+        });
+      }
+    if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
+    __syncthreads();
+    // Gershgorin shift: one wavefront per column
+    double lo = DBL_MAX, hi = -DBL_MAX;
+    for (int q = wave; q < m; q += kBlock / 64) {
+      double sacc = 0.0;
+      for (int r = lane; r < m; r += 64) sacc += (r == q) ? 0.0 : fabs(C[(int64_t)q * m + r]);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
+      const double d = C[(int64_t)q * m + q];
+      lo = fmin(lo, d - sacc);
+      hi = fmax(hi, d + sacc);
+    }
+    if (lane == 0) {
+      s_lo[wave] = lo;
+      s_hi[wave] = hi;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      lo = fmin(lo, s_lo[w]);
+      hi = fmax(hi, s_hi[w]);
+    }
+    const double sh = (lo < 0.0 ? -lo : 0.0) + 0.05 * (hi - lo) + DBL_MIN;
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += kBlock) C[(int64_t)j * m + j] += sh;
+    __syncthreads();
+    const int swb = onesided_jacobi_lds<double, kBlock, 64, kBigRows>(C, m, m, 1e-15, 40, rot_flag);
+    if (swb > 40 && threadIdx.x == 0) s_fail = 1;
+    for (int j = wave; j < m; j += kBlock / 64) {
+      double s2 = 0.0;
+      for (int r = lane; r < m; r += 64) s2 = fma(C[(int64_t)j * m + r], C[(int64_t)j * m + r], s2);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+      if (lane == 0) bnrm[j] = sqrt(s2);
+    }
+    __syncthreads();
+    // sorted Q (Q[r][rank] = w_j[r]/|w_j|) -> Y; eigenvalue |w_j| - shift
+    for (int j = wave; j < m; j += kBlock / 64) {
+      const double lj = bnrm[j];
+      int cnt = 0;
+      for (int q = lane; q < m; q += 64) cnt += (bnrm[q] < lj || (bnrm[q] == lj && q < j)) ? 1 : 0;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+      for (int r = lane; r < m; r += 64) Q[(int64_t)r * m + cnt] = C[(int64_t)j * m + r] / lj;
+      if (lane == 0) eval[it.e_off + i0 + cnt] = lj - sh;
+    }
+    __syncthreads();
+    for (int tm = 0; tm < nt; ++tm)
+      for (int tc = 0; tc < mt; ++tc) {
+        gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, m, m, RowMajor<double>{P, m},
+                               RowMajorT<double>{Q, m}, acc);
+        tile_store(tm * kTM, tc * kTM, n, m, acc,
+                   [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
+      }
+    __syncthreads();
+  }
+  const int32_t* cpos = cl + it.e_off;
+  for (int i = threadIdx.x; i < n; i += kBlock)
+    if (cpos[i] < 0) eval[it.e_off + i] = lam[i];
   if (threadIdx.x == 0 && s_fail && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
@@ -556,6 +671,8 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
   int cur_ws = 0;  // X in the caller's evec (0) or in the work-space P1 (1); step 0 reads x32
   for (int st = 0; st < steps; ++st) {
     const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
+    double closec = kCloseC0;
+    for (int q = 0; q < st; ++q) closec *= 10.0;
     for (int i0 = 0; i0 < n_items; i0 += 65535) {
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       if (st == 0) {
@@ -572,17 +689,17 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
-                       status);
+                       status, closec);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (int i0 = 0; i0 < n_items; i0 += 65535) {
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       if (st == 0)
         hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, x32, 0, evec,
-                           out_ws, lam_pre, work, cl);
+                           out_ws, lam_pre, work, cl, closec);
       else
         hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0,
-                           (const double*)evec, cur_ws, evec, out_ws, lam_pre, work, cl);
+                           (const double*)evec, cur_ws, evec, out_ws, lam_pre, work, cl, closec);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
