@@ -98,6 +98,10 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2106_00454_amd.build` "
                            "(there is no CPU fallback)")
+    # torch first: its HIP runtime (same soname as the system one) must be the
+    # one the process loads, so that torch's device memory and streams and the
+    # library's kernels share one runtime
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
     sig = {

@@ -178,10 +178,12 @@ __device__ __forceinline__ void store_col(T* W, int c, int n, int ld, int lane, 
 // Rotates NP disjoint register column pairs (xs[ia(i)], ys[ib(i)]) of the
 // B-column register blocks xs and ys; the pairs are independent, so their Gram
 // entries are accumulated and reduced together.  rmax collects the largest
-// rotated |w_p.w_q|/(|w_p||w_q|).  The index maps are evaluated on unrolled
+// rotated |w_p.w_q|/(|w_p||w_q|); dx/dy mark the columns that changed (only
+// those are stored back).  The index maps are evaluated on unrolled
 // constants, so every array access resolves to a fixed register.
 template <typename T, int G, int RMAX, int B, int NP, class IA, class IB>
-__device__ __forceinline__ void rotate_pairs(T (&xs)[B][RMAX], T (&ys)[B][RMAX], IA ia, IB ib, T tol, T& rmax) {
+__device__ __forceinline__ void rotate_pairs(T (&xs)[B][RMAX], T (&ys)[B][RMAX], bool (&dx)[B], bool (&dy)[B], IA ia,
+                                             IB ib, T tol, T& rmax) {
   T al[NP], be[NP], ga[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
@@ -219,6 +221,8 @@ __device__ __forceinline__ void rotate_pairs(T (&xs)[B][RMAX], T (&ys)[B][RMAX],
       }
       const T rel = fabs(ga[i]) / nab;
       rmax = rel > rmax ? rel : rmax;
+      dx[ia(i)] = true;
+      dy[ib(i)] = true;
     }
   }
 }
@@ -238,18 +242,23 @@ __device__ int onesided_jacobi_blocked(T* W, int n, int ld, T tol, int max_sweep
       // pairs inside each block: round robin over its B columns
       for (int blk = grp; blk < nb; blk += ngrp) {
         T x[B][RMAX];
+        bool dx[B];
 #pragma unroll
-        for (int i = 0; i < B; ++i) load_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
+        for (int i = 0; i < B; ++i) {
+          load_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
+          dx[i] = false;
+        }
         // circle ordering on B positions: pair i is (pos i, pos B-1-i); pos 0
         // holds column 0, pos q >= 1 holds column 1 + (q - 1 + st) mod (B - 1)
 #pragma unroll
         for (int st = 0; st < B - 1; ++st) {
           auto col = [st](int q) { return q == 0 ? 0 : 1 + (q - 1 + st) % (B - 1); };
-          rotate_pairs<T, G, RMAX, B, B / 2>(x, x, [&](int i) { return col(i); },
+          rotate_pairs<T, G, RMAX, B, B / 2>(x, x, dx, dx, [&](int i) { return col(i); },
                                              [&](int i) { return col(B - 1 - i); }, tol, rmax);
         }
 #pragma unroll
-        for (int i = 0; i < B; ++i) store_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
+        for (int i = 0; i < B; ++i)
+          if (dx[i]) store_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
       }
       __syncthreads();
     }
@@ -259,19 +268,22 @@ __device__ int onesided_jacobi_blocked(T* W, int n, int ld, T tol, int max_sweep
         const int Q = rr_index(nbe - 1 - pr, step, nbe);
         if (P >= nb || Q >= nb) continue;  // the padding block of odd nb
         T x[B][RMAX], y[B][RMAX];
+        bool dx[B], dy[B];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           load_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
           load_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
+          dx[i] = false;
+          dy[i] = false;
         }
 #pragma unroll
         for (int st = 0; st < B; ++st)
-          rotate_pairs<T, G, RMAX, B, B>(x, y, [](int i) { return i; }, [st](int i) { return (i + st) % B; }, tol,
-                                         rmax);
+          rotate_pairs<T, G, RMAX, B, B>(x, y, dx, dy, [](int i) { return i; }, [st](int i) { return (i + st) % B; },
+                                         tol, rmax);
 #pragma unroll
         for (int i = 0; i < B; ++i) {
-          store_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
-          store_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
+          if (dx[i]) store_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
+          if (dy[i]) store_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
         }
       }
       __syncthreads();

@@ -93,7 +93,11 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   for (int c = threadIdx.x; c < n; c += BLOCK) W[c * ld + c] += sigma;
   __syncthreads();
 
-  const int sweeps = onesided_jacobi_blocked<float, BLOCK, G, RMAX, B>(W, n, ld, tol, max_sweeps, rot_flag);
+  int sweeps;
+  if constexpr (B == 1)
+    sweeps = onesided_jacobi_lds<float, BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag);
+  else
+    sweeps = onesided_jacobi_blocked<float, BLOCK, G, RMAX, B>(W, n, ld, tol, max_sweeps, rot_flag);
 
   // column norms
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
@@ -245,6 +249,7 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
                                                             int sweep, int step, T tol) {
   extern __shared__ char lds_raw[];
   T* L = reinterpret_cast<T*>(lds_raw);
+  __shared__ int any_rot;
   const int item = sel ? sel[blockIdx.y] : (int)blockIdx.y;
   const ItemDev it = items[item];
   const int n = it.n;
@@ -273,6 +278,7 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
       T* dst = L + (b * BW + j) * ld;
       for (int r = threadIdx.x; r < n; r += G) dst[r] = c < n ? W[(int64_t)c * n + r] : T(0);
     }
+  if (threadIdx.x == 0 && threadIdx.y == 0) any_rot = 0;
   __syncthreads();
   const int lane = threadIdx.x, grp = threadIdx.y;
   T rmax = T(0);
@@ -293,6 +299,9 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
       __syncthreads();
     }
   }
+  if (lane == 0 && rmax > T(0)) any_rot = 1;
+  __syncthreads();
+  if (!any_rot) return;  // nothing changed: W is already current
   for (int b = 0; b < nblk; ++b)
     for (int j = threadIdx.y; j < BW; j += blockDim.y) {
       const int c = blk[b] * BW + j;
@@ -406,7 +415,7 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
   static_assert(BW * G <= 1024, "block size");
   if (max_n > RMAX * G) return hipErrorInvalidValue;
   const size_t lds = (size_t)2 * BW * gjac_ld<G>(max_n) * sizeof(T);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds + 256 > 160 * 1024) return hipErrorInvalidValue;  // 256 B of static LDS (flags)
   auto intra = gjac_block_kernel<T, BW, G, RMAX, true>;
   auto cross = gjac_block_kernel<T, BW, G, RMAX, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(intra),
@@ -486,8 +495,8 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
   if (max_n <= 288)
     return gjac_run<double, 32, 32, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
                                        max_sweeps, tol, s);
-  if (max_n <= 640)
-    return gjac_run<double, 16, 64, 10>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
+  if (max_n <= 576)
+    return gjac_run<double, 16, 64, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
                                         max_sweeps, tol, s);
   return gjac_run<double, 8, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status, max_sweeps,
                                      tol, s);
