@@ -91,10 +91,12 @@ typedef struct {
                             was below 8*tol ends the iteration (FP32 path;
                             default 2e-7)                                      */
   double jacobi_tol_f64; /* same for the FP64 path (default 1e-15)              */
-  int32_t jacobi_block;  /* column block width of the LDS FP32 Jacobi: 1, 2 or 4
-                            columns per block (registers hold two blocks per
-                            lane group, so LDS traffic falls as 1/width);
-                            0 = library default                              */
+  int32_t jacobi_block;  /* variant of the LDS FP32 Jacobi: 0 (default) one
+                            column pair per lane group with tracked column
+                            norms (one dot product per pair); 1 the same with
+                            three dot products per pair; 2 or 4 column blocks
+                            of that width held in registers (two blocks per
+                            lane group, LDS traffic falling as 1/width)      */
   int32_t pad;
 } wpcd_config;
 

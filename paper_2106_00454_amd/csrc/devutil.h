@@ -147,6 +147,82 @@ __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, i
   return max_sweeps + 1;
 }
 
+// The same iteration with tracked column norms: nrm2 (n shared values) holds
+// |w_c|^2, recomputed exactly at the start of every sweep and updated after a
+// rotation by the exact identities |w_p'|^2 = |w_p|^2 - t w_p.w_q and
+// |w_q'|^2 = |w_q|^2 + t w_p.w_q (t = s/c), so a pair step computes one dot
+// product instead of three.  Same tolerance, stopping rule and return value.
+template <typename T, int BLOCK, int G, int RMAX>
+__device__ int onesided_jacobi_lds_tracked(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag, T* nrm2) {
+  const int npair = (n + 1) >> 1;
+  const int ne = npair << 1;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int c = grp; c < n; c += ngrp) {
+      const T* col = W + (int64_t)c * ld;
+      T s2 = T(0);
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) {
+        const int r = lane + k * G;
+        if (r < n) s2 = fma(col[r], col[r], s2);
+      }
+      s2 = group_sum<G>(s2);
+      if (lane == 0) nrm2[c] = s2;
+    }
+    __syncthreads();
+    for (int step = 0; step < ne - 1; ++step) {
+      for (int pr = grp; pr < npair; pr += ngrp) {
+        const int p = rr_index(pr, step, ne);
+        const int q = rr_index(ne - 1 - pr, step, ne);
+        if (p >= n || q >= n) continue;  // the padding index of odd n
+        T* wp = W + (int64_t)p * ld;
+        T* wq = W + (int64_t)q * ld;
+        T xp[RMAX], xq[RMAX];
+        T ga = T(0);
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) {
+          const int r = lane + k * G;
+          T a = T(0), b = T(0);
+          if (r < n) {
+            a = wp[r];
+            b = wq[r];
+          }
+          xp[k] = a;
+          xq[k] = b;
+          ga = fma(a, b, ga);
+        }
+        ga = group_sum<G>(ga);
+        const T al = nrm2[p], be = nrm2[q];
+        const T nab = sqrt(al * be);
+        if (fabs(ga) > tol * nab) {
+          const T zeta = (be - al) / (T(2) * ga);
+          const T t = copysign(T(1), zeta) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+          const T c = T(1) / sqrt(T(1) + t * t);
+          const T s = c * t;
+#pragma unroll
+          for (int k = 0; k < RMAX; ++k) {
+            const int r = lane + k * G;
+            if (r < n) {
+              wp[r] = c * xp[k] - s * xq[k];
+              wq[r] = s * xp[k] + c * xq[k];
+            }
+          }
+          if (lane == 0) {
+            nrm2[p] = al - t * ga;
+            nrm2[q] = be + t * ga;
+            atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+  }
+  return max_sweeps + 1;
+}
+
 // Column-blocked variant of the same iteration for LDS-resident W: columns
 // are grouped into blocks of B (block b holds columns bB .. bB+B-1, columns
 // >= n are absent and stay zero in registers).  A sweep first rotates the

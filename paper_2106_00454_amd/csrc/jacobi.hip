@@ -94,10 +94,13 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   __syncthreads();
 
   int sweeps;
-  if constexpr (B == 1)
+  if constexpr (B == 0)  // unblocked, tracked column norms (nrm doubles as |w|^2 during the sweeps)
+    sweeps = onesided_jacobi_lds_tracked<float, BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag, nrm);
+  else if constexpr (B == 1)
     sweeps = onesided_jacobi_lds<float, BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag);
   else
     sweeps = onesided_jacobi_blocked<float, BLOCK, G, RMAX, B>(W, n, ld, tol, max_sweeps, rot_flag);
+  __syncthreads();
 
   // column norms
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
@@ -454,18 +457,22 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
                        max_sweeps, tol);
     return hipGetLastError();
   };
-  // column block width: 0 picks the default per size class
-  const int B = block_cols != 0 ? block_cols : 1;
+  // 0 (default): unblocked iteration with tracked column norms; 1: unblocked
+  // with three dot products per pair; 2, 4: column blocks of that width
+  const int B = block_cols;
   if (max_n <= 64) {
+    if (B == 0) return go(jacobi_f32_lds_kernel<256, 4, 16, 0>, 256);
     if (B == 1) return go(jacobi_f32_lds_kernel<256, 4, 16, 1>, 256);
     if (B == 2) return go(jacobi_f32_lds_kernel<256, 16, 4, 2>, 256);
     return go(jacobi_f32_lds_kernel<128, 16, 4, 4>, 128);
   }
   if (max_n <= 128) {
+    if (B == 0) return go(jacobi_f32_lds_kernel<512, 8, 16, 0>, 512);
     if (B == 1) return go(jacobi_f32_lds_kernel<512, 8, 16, 1>, 512);
     if (B == 2) return go(jacobi_f32_lds_kernel<512, 16, 8, 2>, 512);
     return go(jacobi_f32_lds_kernel<256, 16, 8, 4>, 256);
   }
+  if (B == 0) return go(jacobi_f32_lds_kernel<1024, 8, 25, 0>, 1024);
   if (B == 1) return go(jacobi_f32_lds_kernel<1024, 8, 25, 1>, 1024);
   if (B == 2) return go(jacobi_f32_lds_kernel<1024, 16, 13, 2>, 1024);
   return go(jacobi_f32_lds_kernel<512, 16, 13, 4>, 512);

@@ -23,8 +23,9 @@
 // Kernels per step: Y = A X, {S, G} = X^T {Y, X} and X M are dense FP64
 // contractions on the matrix cores (v_mfma_f64_16x16x4f64), one work-group per
 // 64 x 64 output tile of one item (S and G: upper tiles only, mirrored);
-// refine_chain_kernel (one work-group per item) forms the Rayleigh quotients,
-// the chains and the Rayleigh-Ritz rotations.  A final kernel sorts the
+// refine_reach_kernel (16 rows per work-group) forms the Rayleigh quotients
+// and the close pairs, refine_chain_kernel (one work-group per item) the
+// chains and their Rayleigh-Ritz rotations.  A final kernel sorts the
 // eigenpairs by eigenvalue and writes them to the caller's arrays.
 #include <float.h>
 
@@ -310,6 +311,110 @@ __global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restri
   tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
 }
 
+// ------------------------------------------------------------ reach kernel
+// Rayleigh quotients lam_i = S_ii/G_ii (-> lam_pre) and, per row p, the
+// largest q > p with (p, q) close (else p; -> cl, read back by the chain
+// kernel).  Grid: x = blocks of kReachRows rows, y = item; one wavefront per
+// row with lanes over q (coalesced reads of rows of S and G).
+constexpr int kReachRows = 16;
+__global__ __launch_bounds__(64 * kReachRows) void refine_reach_kernel(const ItemDev* __restrict__ items,
+                                                                       double* __restrict__ lam_pre,
+                                                                       const double* work, int32_t* __restrict__ cl,
+                                                                       double closec) {
+  __shared__ double lam[kMaxN];
+  const ItemDev it = items[blockIdx.y];
+  const int n = it.n;
+  if ((int)blockIdx.x * kReachRows >= n) return;
+  const WS ws(const_cast<double*>(work), it);
+  const double* S = ws.S;
+  const double* G = ws.G;
+  for (int i = threadIdx.x; i < n; i += 64 * kReachRows) lam[i] = S[(int64_t)i * n + i] / G[(int64_t)i * n + i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, p = blockIdx.x * kReachRows + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const double lp = lam[p];
+  int rq = p;
+  for (int q = p + 1 + lane; q < n; q += 64) {
+    const double r = -G[(int64_t)p * n + q];
+    const double sv = S[(int64_t)p * n + q];
+    const double d = fabs(lam[q] - lp);
+    if (closec * fabs(sv + lam[q] * r) >= d || closec * fabs(sv + lp * r) >= d) rq = q;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(rq, off, 64);
+    rq = o > rq ? o : rq;
+  }
+  if (lane == 0) {
+    cl[it.e_off + p] = rq;
+    lam_pre[it.e_off + p] = lp;
+  }
+}
+
+// One-sided Jacobi on the block-diagonal W of a Rayleigh-Ritz batch (Tb
+// columns, leading dimension ldw): its chains are independent, so each chain
+// runs its own round-robin ordering over its own rows only, and all chains
+// advance together -- a sweep has max(ne_c) - 1 barrier-separated steps
+// instead of Tb - 1.  bstart/blen: the batch's chains (batch-local first
+// column, length), nb of them; poff[c] = sum of (len+1)/2 over earlier chains.
+// Same tolerance semantics and return value as onesided_jacobi_lds.
+template <int BLOCK, int G, int RMAX>
+__device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short* blen, const short* poff, int nb,
+                            double tol, int max_sweeps, int* rot_flag) {
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
+  int ne_max = 0;
+  for (int c = 0; c < nb; ++c) ne_max = max(ne_max, (blen[c] + 1) & ~1);
+  const int ptot = poff[nb];
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int step = 0; step < ne_max - 1; ++step) {
+      for (int idx = grp; idx < ptot; idx += ngrp) {
+        int c = 0;
+        while (poff[c + 1] <= idx) ++c;
+        const int m = blen[c], ne = (m + 1) & ~1, b0 = bstart[c];
+        if (step >= ne - 1) continue;
+        const int pr = idx - poff[c];
+        const int p = rr_index(pr, step, ne), q = rr_index(ne - 1 - pr, step, ne);
+        if (p >= m || q >= m) continue;
+        double* wp = W + (b0 + p) * ldw + b0;
+        double* wq = W + (b0 + q) * ldw + b0;
+        double xp[RMAX], xq[RMAX];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) {
+          const int r = lane + k * G;
+          const double a = r < m ? wp[r] : 0.0, b = r < m ? wq[r] : 0.0;
+          xp[k] = a;
+          xq[k] = b;
+          al = fma(a, a, al);
+          be = fma(b, b, be);
+          ga = fma(a, b, ga);
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        ga = group_sum<G>(ga);
+        const double nab = sqrt(al * be);
+        if (fabs(ga) > tol * nab) {
+          double cs, sn;
+          hestenes_rotation(al, be, ga, cs, sn);
+#pragma unroll
+          for (int k = 0; k < RMAX; ++k) {
+            const int r = lane + k * G;
+            if (r < m) {
+              wp[r] = cs * xp[k] - sn * xq[k];
+              wq[r] = sn * xp[k] + cs * xq[k];
+            }
+          }
+          if (lane == 0) atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
+        }
+      }
+      __syncthreads();
+    }
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+  }
+  return max_sweeps + 1;
+}
+
 // ------------------------------------------------------------ chain kernel
 // One work-group per item: Rayleigh quotients, close pairs and chains, and the
 // Rayleigh-Ritz rotation of every chain.  Chains of up to kMaxChain columns
@@ -344,40 +449,24 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
   __shared__ double bnrm[kMaxN];
   __shared__ short big_start[kMaxBig], big_len[kMaxBig], big_pos[kMaxBig];
   __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
-  __shared__ int s_Ttot, s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail, s_nbig;
+  __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
+  __shared__ int s_Ttot, s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail, s_nbig, s_nbt;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
   const WS ws(work, it);
   const double* S = ws.S;
   const double* G = ws.G;
-  for (int i = threadIdx.x; i < n; i += kBlock) lam[i] = S[(int64_t)i * n + i] / G[(int64_t)i * n + i];
-  __syncthreads();
-  // reach[p] = largest q > p with (p, q) close, else p: one wavefront per row p,
-  // lanes over q (coalesced row reads), then a wavefront max
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int p = wave; p < n; p += kBlock / 64) {
-      int rq = p;
-      for (int q = p + 1 + lane; q < n; q += 64) {
-        const double r = -G[(int64_t)p * n + q];
-        const double s = S[(int64_t)p * n + q];
-        const double d = fabs(lam[q] - lam[p]);
-        if (closec * fabs(s + lam[q] * r) >= d || closec * fabs(s + lam[p] * r) >= d) rq = q;
-      }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const int o = __shfl_xor(rq, off, 64);
-        rq = o > rq ? o : rq;
-      }
-      if (lane == 0) reach[p] = rq;
-    }
-    for (int p = threadIdx.x; p < n; p += kBlock) lam_pre[it.e_off + p] = lam[p];
+  // Rayleigh quotients and reach[p] from refine_reach_kernel (reach staged in cl)
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    lam[i] = lam_pre[it.e_off + i];
+    reach[i] = cl[it.e_off + i];
   }
   __syncthreads();
-  // chains = unions of overlapping [p, reach[p]] with at least two columns
+  // chains = unions of overlapping [p, reach[p]] with at least two columns;
+  // one thread walks the reach list in LDS and overwrites it in place with
+  // each column's chain position (or -1), then all threads copy it to cl
   if (threadIdx.x == 0) {
     int T = 0, fail = 0, i = 0, nch = 0, nbig = 0;
-    int32_t* c = cl + it.e_off;
     while (i < n) {
       int j = reach[i], q = i;
       while (q <= j) {
@@ -386,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
       }
       const int m = j - i + 1;
       if (m >= 2 && m <= kMaxChain) {
-        for (int t = 0; t < m; ++t) c[i + t] = T + t;
+        for (int t = 0; t < m; ++t) reach[i + t] = T + t;
         ch_start[nch] = (short)i;
         ch_len[nch] = (short)m;
         ++nch;
@@ -397,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
         ++nbig;
       } else {
         if (m > kMaxChain) fail = 1;  // more long chains than the list holds
-        for (int t = 0; t < m; ++t) c[i + t] = -1;
+        for (int t = 0; t < m; ++t) reach[i + t] = -1;
       }
       i = j + 1;
     }
@@ -405,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     // their batches are processed), the long chains' after them
     for (int b = 0; b < nbig; ++b) {
       big_pos[b] = (short)T;
-      for (int t = 0; t < big_len[b]; ++t) c[big_start[b] + t] = T + t;
+      for (int t = 0; t < big_len[b]; ++t) reach[big_start[b] + t] = T + t;
       T += big_len[b];
     }
     s_Ttot = T;
@@ -416,6 +505,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     s_pos = 0;
   }
   __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) cl[it.e_off + i] = reach[i];
   const int Ttot = s_Ttot;
   const int nch = s_nch;
   const int nt = (n + kTM - 1) / kTM;
@@ -427,18 +517,24 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     // next batch: chains [c0, c1) with at most kMaxChain columns in total
     if (threadIdx.x == 0) {
       const int c0 = s_c1;
-      int c1 = c0, Tb = 0;
+      int c1 = c0, Tb = 0, nbt = 0;
+      bt_poff[0] = 0;
       while (c1 < nch && Tb + ch_len[c1] <= kMaxChain) {
         for (int t = 0; t < ch_len[c1]; ++t) {
           cols[Tb + t] = ch_start[c1] + t;
           blk[Tb + t] = Tb;
         }
+        bt_start[nbt] = (short)Tb;
+        bt_len[nbt] = ch_len[c1];
+        bt_poff[nbt + 1] = (short)(bt_poff[nbt] + (ch_len[c1] + 1) / 2);
+        ++nbt;
         Tb += ch_len[c1];
         ++c1;
       }
       s_c0 = c0;
       s_c1 = c1;
       s_Tb = Tb;
+      s_nbt = nbt;
     }
     __syncthreads();
     const int Tb = s_Tb;
@@ -484,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     __syncthreads();
     for (int j = threadIdx.x; j < Tb; j += kBlock) W[j * ldw + j] += shift[j];
     __syncthreads();
-    const int sw = onesided_jacobi_lds<double, kBlock, 8, 8>(W, Tb, ldw, 1e-15, 40, rot_flag);
+    const int sw = chain_jacobi<kBlock, 8, 8>(W, ldw, bt_start, bt_len, bt_poff, s_nbt, 1e-15, 40, rot_flag);
     if (sw > 40 && threadIdx.x == 0) s_fail = 1;
     for (int j = threadIdx.x; j < Tb; j += kBlock) {
       double s2 = 0.0;
@@ -602,9 +698,8 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
       }
     __syncthreads();
   }
-  const int32_t* cpos = cl + it.e_off;
   for (int i = threadIdx.x; i < n; i += kBlock)
-    if (cpos[i] < 0) eval[it.e_off + i] = lam[i];
+    if (reach[i] < 0) eval[it.e_off + i] = lam[i];
   if (threadIdx.x == 0 && s_fail && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
@@ -688,6 +783,11 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
+    for (int i0 = 0; i0 < n_items; i0 += 65535) {
+      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+      hipLaunchKernelGGL(refine_reach_kernel, dim3((max_n + kReachRows - 1) / kReachRows, gy),
+                         dim3(64 * kReachRows), 0, s, items + i0, lam_pre, work, cl, closec);
+    }
     hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
                        status, closec);
     err = hipGetLastError();
