@@ -97,7 +97,10 @@ typedef struct {
                             three dot products per pair; 2 or 4 column blocks
                             of that width held in registers (two blocks per
                             lane group, LDS traffic falling as 1/width)      */
-  int32_t pad;
+  int32_t refine_close_log10; /* closeness constant of the first refinement
+                            step, c = 10^k (pairs whose first-order update
+                            would exceed 1/c are solved by Rayleigh-Ritz);
+                            later steps use 10x more each; 0 = default 3    */
 } wpcd_config;
 
 /* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */

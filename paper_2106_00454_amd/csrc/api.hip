@@ -116,11 +116,14 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
     return fail(WPCD_ERR_INVALID, "wpcd_create: device %d out of range (%d devices)", hip_device, ndev);
   wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0};
   if (cfg) c = *cfg;
+  if (c.refine_close_log10 == 0) c.refine_close_log10 = 3;
   if (c.max_sweeps < 1 || c.max_sweeps > 60) return fail(WPCD_ERR_INVALID, "max_sweeps must be in [1, 60]");
   if (c.refine_steps < 0 || c.refine_steps > 4) return fail(WPCD_ERR_INVALID, "refine_steps must be in [0, 4]");
   if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
   if (c.jacobi_block != 0 && c.jacobi_block != 1 && c.jacobi_block != 2 && c.jacobi_block != 4)
     return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2 or 4");
+  if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
+    return fail(WPCD_ERR_INVALID, "refine_close_log10 must be in [1, 8] (0 = default)");
   WPCD_HIP(hipSetDevice(hip_device), "hipSetDevice");
   wpcd_context* ctx = new (std::nothrow) wpcd_context;
   if (!ctx) return fail(WPCD_ERR_NOMEM, "wpcd_create: host allocation");
@@ -501,7 +504,8 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_REFINE, stream,
                    [&] {
                      return launch_refine(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, evec, eval,
-                                          b->d_lam, b->d_work, b->d_cl, status, c.refine_steps, stream);
+                                          b->d_lam, b->d_work, b->d_cl, status, c.refine_steps,
+                                          c.refine_close_log10, stream);
                    }),
              "wpcd_eigh: FP64 refinement launch");
   } else {

@@ -147,13 +147,28 @@ __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, i
   return max_sweeps + 1;
 }
 
-// The same iteration with tracked column norms: nrm2 (n shared values) holds
+// rr_index for 0 <= pos < ne and 0 <= step < ne - 1, without a division.
+__device__ __forceinline__ int rr_index_nodiv(int pos, int step, int ne) {
+  if (pos == 0) return 0;
+  int v = pos - 1 + step;
+  if (v >= ne - 1) v -= ne - 1;
+  return 1 + v;
+}
+
+// The same iteration with tracked column norms: nrm2 (n shared floats) holds
 // |w_c|^2, recomputed exactly at the start of every sweep and updated after a
 // rotation by the exact identities |w_p'|^2 = |w_p|^2 - t w_p.w_q and
 // |w_q'|^2 = |w_q|^2 + t w_p.w_q (t = s/c), so a pair step computes one dot
-// product instead of three.  Same tolerance, stopping rule and return value.
-template <typename T, int BLOCK, int G, int RMAX>
-__device__ int onesided_jacobi_lds_tracked(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag, T* nrm2) {
+// product instead of three.  FP32 only; the caller guarantees ld >= RMAX*G
+// and zero rows n .. RMAX*G-1 in every column, so no row is guarded (the zero
+// rows stay zero under rotations).  The rotation is formed with the hardware
+// reciprocal and square-root instructions (about 1 ulp): only the angle
+// depends on them; c and s are normalised by construction to 1 ulp, as with
+// correctly rounded operations.  Same tolerance, stopping rule and return
+// value as onesided_jacobi_lds.
+template <int BLOCK, int G, int RMAX>
+__device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
+                                           float* nrm2) {
   const int npair = (n + 1) >> 1;
   const int ne = npair << 1;
   const int lane = threadIdx.x % G;
@@ -161,64 +176,53 @@ __device__ int onesided_jacobi_lds_tracked(T* W, int n, int ld, T tol, int max_s
   constexpr int ngrp = BLOCK / G;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int c = grp; c < n; c += ngrp) {
-      const T* col = W + (int64_t)c * ld;
-      T s2 = T(0);
+      const float* col = W + c * ld + lane;
+      float s2 = 0.f;
 #pragma unroll
-      for (int k = 0; k < RMAX; ++k) {
-        const int r = lane + k * G;
-        if (r < n) s2 = fma(col[r], col[r], s2);
-      }
+      for (int k = 0; k < RMAX; ++k) s2 = fmaf(col[k * G], col[k * G], s2);
       s2 = group_sum<G>(s2);
       if (lane == 0) nrm2[c] = s2;
     }
     __syncthreads();
     for (int step = 0; step < ne - 1; ++step) {
       for (int pr = grp; pr < npair; pr += ngrp) {
-        const int p = rr_index(pr, step, ne);
-        const int q = rr_index(ne - 1 - pr, step, ne);
+        const int p = rr_index_nodiv(pr, step, ne);
+        const int q = rr_index_nodiv(ne - 1 - pr, step, ne);
         if (p >= n || q >= n) continue;  // the padding index of odd n
-        T* wp = W + (int64_t)p * ld;
-        T* wq = W + (int64_t)q * ld;
-        T xp[RMAX], xq[RMAX];
-        T ga = T(0);
+        float* wp = W + p * ld + lane;
+        float* wq = W + q * ld + lane;
+        float xp[RMAX], xq[RMAX];
+        float ga = 0.f;
 #pragma unroll
         for (int k = 0; k < RMAX; ++k) {
-          const int r = lane + k * G;
-          T a = T(0), b = T(0);
-          if (r < n) {
-            a = wp[r];
-            b = wq[r];
-          }
-          xp[k] = a;
-          xq[k] = b;
-          ga = fma(a, b, ga);
+          xp[k] = wp[k * G];
+          xq[k] = wq[k * G];
+          ga = fmaf(xp[k], xq[k], ga);
         }
         ga = group_sum<G>(ga);
-        const T al = nrm2[p], be = nrm2[q];
-        const T nab = sqrt(al * be);
-        if (fabs(ga) > tol * nab) {
-          const T zeta = (be - al) / (T(2) * ga);
-          const T t = copysign(T(1), zeta) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
-          const T c = T(1) / sqrt(T(1) + t * t);
-          const T s = c * t;
+        const float al = nrm2[p], be = nrm2[q];
+        const float nab = __builtin_amdgcn_sqrtf(al * be);
+        if (fabsf(ga) > tol * nab) {
+          const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
+          const float t = copysignf(1.f, zeta) *
+                          __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.f)));
+          const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          const float s = c * t;
 #pragma unroll
           for (int k = 0; k < RMAX; ++k) {
-            const int r = lane + k * G;
-            if (r < n) {
-              wp[r] = c * xp[k] - s * xq[k];
-              wq[r] = s * xp[k] + c * xq[k];
-            }
+            wp[k * G] = c * xp[k] - s * xq[k];
+            wq[k * G] = s * xp[k] + c * xq[k];
           }
           if (lane == 0) {
             nrm2[p] = al - t * ga;
             nrm2[q] = be + t * ga;
-            atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
+            atomicMax(&rot_flag[sweep], __float_as_int(fabsf(ga) * __builtin_amdgcn_rcpf(nab)));
           }
         }
       }
       __syncthreads();
     }
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * tol) return sweep + 1;
   }
   return max_sweeps + 1;
 }

@@ -73,7 +73,7 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
                                 double* eval, int32_t* status, int max_sweeps, double tol, hipStream_t s);
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                          const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
-                         int32_t* status, int steps, hipStream_t s);
+                         int32_t* status, int steps, int close_log10, hipStream_t s);
 hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                           const double* eval, const double* evec, int mode, double* t, int32_t* status,
                           hipStream_t s);

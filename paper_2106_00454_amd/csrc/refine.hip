@@ -44,11 +44,11 @@ constexpr int kLdT = kTM + 4;  // LDS stride of a staged operand tile (doubles)
 constexpr int kMaxChain = 64;  // columns of one LDS Rayleigh-Ritz batch
 constexpr int kMaxBig = 24;    // longer chains per item, solved in device memory
 constexpr int kBigRows = 19;   // rows per lane of their Jacobi (64 * 19 >= kMaxN)
-// Closeness constant of refinement step st: c = kCloseC0 * 10^st.  The first
-// step starts from FP32 vectors and admits Newton updates up to 1e-3; later
-// steps start from much better vectors and take only updates up to 10^-(3+st),
-// whose second-order remainders are below FP64 orthogonality.
-constexpr double kCloseC0 = 1000.0;
+// Closeness constant of refinement step st: c = 10^(close_log10 + st) (by
+// default 1e3 in the first step, which starts from FP32 vectors and admits
+// Newton updates up to 1e-3; later steps start from much better vectors and
+// take only smaller updates, whose second-order remainders are below FP64
+// orthogonality).
 
 // --------------------------------------------------------------- GEMM tiles
 // acc = sum_k A(m0+i, k) B(k, c0+j) over one 64 x 64 tile; fa(i,k) gives A,
@@ -759,15 +759,15 @@ __global__ __launch_bounds__(kBlock) void refine_finish_kernel(const ItemDev* __
 
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                          const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
-                         int32_t* status, int steps, hipStream_t s) {
+                         int32_t* status, int steps, int close_log10, hipStream_t s) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
   const int nt = (max_n + kTM - 1) / kTM;
   const int tiles = nt * nt, up_tiles = nt * (nt + 1) / 2;
   int cur_ws = 0;  // X in the caller's evec (0) or in the work-space P1 (1); step 0 reads x32
   for (int st = 0; st < steps; ++st) {
     const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
-    double closec = kCloseC0;
-    for (int q = 0; q < st; ++q) closec *= 10.0;
+    double closec = 1.0;
+    for (int q = 0; q < close_log10 + st; ++q) closec *= 10.0;
     for (int i0 = 0; i0 < n_items; i0 += 65535) {
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       if (st == 0) {
