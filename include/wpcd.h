@@ -91,12 +91,13 @@ typedef struct {
                             was below 8*tol ends the iteration (FP32 path;
                             default 2e-7)                                      */
   double jacobi_tol_f64; /* same for the FP64 path (default 1e-15)              */
-  int32_t jacobi_block;  /* variant of the LDS FP32 Jacobi: 0 (default) one
-                            column pair per lane group with tracked column
-                            norms (one dot product per pair); 1 the same with
-                            three dot products per pair; 2 or 4 column blocks
-                            of that width held in registers (two blocks per
-                            lane group, LDS traffic falling as 1/width)      */
+  int32_t jacobi_block;  /* variant of the LDS FP32 Jacobi: 0 (default) column
+                            blocks of 2 held in registers, two blocks per lane
+                            group and 4 rotations per block step, with tracked
+                            column norms (one dot product per pair); 1 one
+                            column pair per lane group, three dot products per
+                            pair; 2 one pair per group, tracked norms; 4 blocks
+                            of 4 columns, tracked norms                     */
   int32_t refine_close_log10; /* closeness constant of the first refinement
                             step, c = 10^k (pairs whose first-order update
                             would exceed 1/c are solved by Rayleigh-Ritz);
@@ -325,6 +326,12 @@ enum {
 };
 int wpcd_profile_enable(wpcd_ctx ctx, int on);
 int wpcd_stage_times(wpcd_ctx ctx, double* ms_host, int64_t* launches_host);
+/* Work done by the LDS FP32 Jacobi (default variant) while the stage timers
+ * were on, since they were last enabled: counts_host[0] = rotations applied,
+ * [1] = column-pair visits (one dot product each), [2] = column-norm
+ * evaluations (sum over items of sweeps * n^2 multiply-adds).  Synchronises
+ * the device.  Used to state the kernel's algorithmic FLOP count.          */
+int wpcd_jacobi_counts(wpcd_ctx ctx, int64_t* counts_host);
 
 #ifdef __cplusplus
 }

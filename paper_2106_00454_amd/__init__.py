@@ -37,7 +37,8 @@ EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wp
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
            "wpcd_batch_offsets", "wpcd_basis_register", "wpcd_project", "wpcd_project_affine", "wpcd_eigh",
            "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_server_create", "wpcd_server_destroy",
-           "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times")
+           "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times",
+           "wpcd_jacobi_counts")
 
 STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma")
 
@@ -129,6 +130,7 @@ def lib() -> ctypes.CDLL:
         "wpcd_server_stats_get": (i32, [vp, ctypes.POINTER(_ServerStats)]),
         "wpcd_profile_enable": (i32, [vp, i32]),
         "wpcd_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        "wpcd_jacobi_counts": (i32, [vp, ctypes.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -223,6 +225,12 @@ class Context:
         n = (ctypes.c_int64 * len(STAGES))()
         _check(lib().wpcd_stage_times(self._h, ms, n))
         return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
+
+    def jacobi_counts(self) -> dict:
+        """LDS Jacobi work since profile(True): rotations, pair visits, norm multiply-adds."""
+        c = (ctypes.c_int64 * 3)()
+        _check(lib().wpcd_jacobi_counts(self._h, c))
+        return {"rotations": c[0], "pair_visits": c[1], "norm_madds": c[2]}
 
     def basis(self, grid: Grid, n_ch: int, terms, stream=None) -> "Basis":
         """Register the projections of fine-mesh terms U_t (a list of host (M, M)

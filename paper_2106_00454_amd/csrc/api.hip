@@ -129,6 +129,12 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   if (!ctx) return fail(WPCD_ERR_NOMEM, "wpcd_create: host allocation");
   ctx->device = hip_device;
   ctx->cfg = c;
+  hipError_t e = hipMalloc((void**)&ctx->d_counters, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(ctx->d_counters, 0, 4 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    wpcd_destroy(ctx);
+    return hip_fail(e, "wpcd_create: counters");
+  }
   *out = ctx;
   return WPCD_OK;
 }
@@ -143,6 +149,7 @@ void wpcd_destroy(wpcd_ctx ctx) {
   }
   for (auto& g : ctx->grids) hipFree(g.dbuf);
   for (auto& bs : ctx->bases) hipFree(bs.dbuf);
+  hipFree(ctx->d_counters);
   delete ctx;
 }
 
@@ -492,7 +499,8 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                        if (k < kNumClasses - 1)
                          e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
                                                    b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
-                                                   c.jacobi_block, stream);
+                                                   c.jacobi_block, b->ctx->profiling ? b->ctx->d_counters : nullptr,
+                                                   stream);
                        else
                          e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
                                                   b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
@@ -576,7 +584,18 @@ int wpcd_profile_enable(wpcd_ctx ctx, int on) {
     ctx->stage_ms[i] = 0.0;
     ctx->stage_launches[i] = 0;
   }
+  WPCD_HIP(hipMemset(ctx->d_counters, 0, 4 * sizeof(unsigned long long)), "wpcd_profile_enable: counters");
   ctx->profiling = on != 0;
+  return WPCD_OK;
+}
+
+int wpcd_jacobi_counts(wpcd_ctx ctx, int64_t* counts_host) {
+  if (!ctx || !counts_host) return fail(WPCD_ERR_INVALID, "wpcd_jacobi_counts: NULL argument");
+  WPCD_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  WPCD_HIP(hipDeviceSynchronize(), "wpcd_jacobi_counts: synchronise");
+  unsigned long long h[4];
+  WPCD_HIP(hipMemcpy(h, ctx->d_counters, sizeof(h), hipMemcpyDeviceToHost), "wpcd_jacobi_counts: copy");
+  for (int i = 0; i < 3; ++i) counts_host[i] = (int64_t)h[i];
   return WPCD_OK;
 }
 

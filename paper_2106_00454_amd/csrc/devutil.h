@@ -165,10 +165,11 @@ __device__ __forceinline__ int rr_index_nodiv(int pos, int step, int ne) {
 // reciprocal and square-root instructions (about 1 ulp): only the angle
 // depends on them; c and s are normalised by construction to 1 ulp, as with
 // correctly rounded operations.  Same tolerance, stopping rule and return
-// value as onesided_jacobi_lds.
+// value as onesided_jacobi_lds; nrot (lane 0 of each group) counts the
+// rotations the group applied.
 template <int BLOCK, int G, int RMAX>
 __device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
-                                           float* nrm2) {
+                                           float* nrm2, int& nrot) {
   const int npair = (n + 1) >> 1;
   const int ne = npair << 1;
   const int lane = threadIdx.x % G;
@@ -217,6 +218,7 @@ __device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, i
             nrm2[p] = al - t * ga;
             nrm2[q] = be + t * ga;
             atomicMax(&rot_flag[sweep], __float_as_int(fabsf(ga) * __builtin_amdgcn_rcpf(nab)));
+            ++nrot;
           }
         }
       }
@@ -227,89 +229,90 @@ __device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, i
   return max_sweeps + 1;
 }
 
-// Column-blocked variant of the same iteration for LDS-resident W: columns
-// are grouped into blocks of B (block b holds columns bB .. bB+B-1, columns
-// >= n are absent and stay zero in registers).  A sweep first rotates the
-// pairs inside every block, then runs the round-robin ordering over blocks;
-// at each block step a lane group loads the 2B columns of its two blocks into
-// registers, rotates all B*B cross pairs in B stages of B disjoint pairs
-// (x_i with y_(i+s) mod B at stage s), and stores them back.  Every pair is
-// rotated once per sweep, as in the unblocked ordering, but LDS is read and
-// written once per B*B rotations instead of once per rotation, and there is
-// one barrier per block step.  Same tolerance, stopping rule and return value
-// as onesided_jacobi_lds; RMAX >= ceil(n/G).  Ends with a barrier.
-template <typename T, int G, int RMAX>
-__device__ __forceinline__ void load_col(const T* W, int c, int n, int ld, int lane, T (&x)[RMAX]) {
+// Column-blocked iteration with tracked norms (FP32, LDS-resident W): the
+// ordering of onesided_jacobi_blocked (pairs inside each block of B columns,
+// then a round robin over blocks whose block-pair steps rotate the B*B cross
+// pairs in B stages), the rotation arithmetic of onesided_jacobi_lds_tracked.
+// A lane group holds its 2B columns and their squared norms in registers for
+// the whole block step, so one barrier and one LDS round trip serve B*B
+// rotations.  Rows: lane + k*G for k < RMAX; only the last k is guarded
+// (rows >= n are skipped).  nrm2 holds the squared norms between steps.
+template <int G, int RMAX, int NP, class IA, class IB, int B>
+__device__ __forceinline__ void rotate_tracked(float (&xs)[B][RMAX], float (&ys)[B][RMAX], float (&ns)[B],
+                                               float (&ms)[B], bool (&dx)[B], bool (&dy)[B], IA ia, IB ib,
+                                               float tol, float& rmax, int& nrot) {
+  float ga[NP];
 #pragma unroll
-  for (int k = 0; k < RMAX; ++k) {
-    const int r = lane + k * G;
-    x[k] = (c < n && r < n) ? W[(int64_t)c * ld + r] : T(0);
-  }
-}
-template <typename T, int G, int RMAX>
-__device__ __forceinline__ void store_col(T* W, int c, int n, int ld, int lane, const T (&x)[RMAX]) {
-  if (c >= n) return;
+  for (int i = 0; i < NP; ++i) ga[i] = 0.f;
 #pragma unroll
-  for (int k = 0; k < RMAX; ++k) {
-    const int r = lane + k * G;
-    if (r < n) W[(int64_t)c * ld + r] = x[k];
-  }
-}
-// Rotates NP disjoint register column pairs (xs[ia(i)], ys[ib(i)]) of the
-// B-column register blocks xs and ys; the pairs are independent, so their Gram
-// entries are accumulated and reduced together.  rmax collects the largest
-// rotated |w_p.w_q|/(|w_p||w_q|); dx/dy mark the columns that changed (only
-// those are stored back).  The index maps are evaluated on unrolled
-// constants, so every array access resolves to a fixed register.
-template <typename T, int G, int RMAX, int B, int NP, class IA, class IB>
-__device__ __forceinline__ void rotate_pairs(T (&xs)[B][RMAX], T (&ys)[B][RMAX], bool (&dx)[B], bool (&dy)[B], IA ia,
-                                             IB ib, T tol, T& rmax) {
-  T al[NP], be[NP], ga[NP];
+  for (int k = 0; k < RMAX; ++k)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) ga[i] = fmaf(xs[ia(i)][k], ys[ib(i)][k], ga[i]);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) ga[i] = group_sum<G>(ga[i]);
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    al[i] = T(0);
-    be[i] = T(0);
-    ga[i] = T(0);
-  }
-#pragma unroll
-  for (int k = 0; k < RMAX; ++k) {
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const T a = xs[ia(i)][k], b = ys[ib(i)][k];
-      al[i] = fma(a, a, al[i]);
-      be[i] = fma(b, b, be[i]);
-      ga[i] = fma(a, b, ga[i]);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    al[i] = group_sum<G>(al[i]);
-    be[i] = group_sum<G>(be[i]);
-    ga[i] = group_sum<G>(ga[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    const T nab = sqrt(al[i] * be[i]);
-    if (fabs(ga[i]) > tol * nab) {
-      T c, s;
-      hestenes_rotation(al[i], be[i], ga[i], c, s);
+    const float al = ns[ia(i)], be = ms[ib(i)];
+    const float nab = __builtin_amdgcn_sqrtf(al * be);
+    if (fabsf(ga[i]) > tol * nab) {
+      const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga[i]);
+      const float t = copysignf(1.f, zeta) *
+                      __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.f)));
+      const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+      const float s = c * t;
 #pragma unroll
       for (int k = 0; k < RMAX; ++k) {
-        const T a = xs[ia(i)][k], b = ys[ib(i)][k];
+        const float a = xs[ia(i)][k], b = ys[ib(i)][k];
         xs[ia(i)][k] = c * a - s * b;
         ys[ib(i)][k] = s * a + c * b;
       }
-      const T rel = fabs(ga[i]) / nab;
+      ns[ia(i)] = al - t * ga[i];
+      ms[ib(i)] = be + t * ga[i];
+      const float rel = fabsf(ga[i]) * __builtin_amdgcn_rcpf(nab);
       rmax = rel > rmax ? rel : rmax;
       dx[ia(i)] = true;
       dy[ib(i)] = true;
+      if (threadIdx.x % G == 0) ++nrot;
     }
   }
 }
 
-template <typename T, int BLOCK, int G, int RMAX, int B>
-__device__ int onesided_jacobi_blocked(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag) {
-  static_assert(B == 1 || B == 2 || B == 4, "block width");
+template <int G, int RMAX, int B>
+__device__ __forceinline__ void load_block(const float* W, float* nrm2, int blk, int n, int ld, int lane,
+                                           float (&x)[B][RMAX], float (&nx)[B]) {
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const int c = blk * B + i;
+    const bool live = c < n;
+    const float* col = W + (live ? c : 0) * ld + lane;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+      const bool ok = live && (k < RMAX - 1 || lane + k * G < n);
+      x[i][k] = ok ? col[k * G] : 0.f;
+    }
+    nx[i] = live ? nrm2[c] : 0.f;
+  }
+}
+
+template <int G, int RMAX, int B>
+__device__ __forceinline__ void store_block(float* W, float* nrm2, int blk, int n, int ld, int lane,
+                                            const float (&x)[B][RMAX], const float (&nx)[B], const bool (&d)[B]) {
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const int c = blk * B + i;
+    if (c >= n || !d[i]) continue;
+    float* col = W + c * ld + lane;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+      if (k < RMAX - 1 || lane + k * G < n) col[k * G] = x[i][k];
+    if (lane == 0) nrm2[c] = nx[i];
+  }
+}
+
+template <int BLOCK, int G, int RMAX, int B>
+__device__ int onesided_jacobi_blocked_tracked(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
+                                               float* nrm2, int& nrot) {
+  static_assert(B == 2 || B == 4, "block width");
   const int nb = (n + B - 1) / B;
   const int nbp = (nb + 1) >> 1;
   const int nbe = nbp << 1;
@@ -317,60 +320,60 @@ __device__ int onesided_jacobi_blocked(T* W, int n, int ld, T tol, int max_sweep
   const int grp = threadIdx.x / G;
   constexpr int ngrp = BLOCK / G;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    T rmax = T(0);
-    if constexpr (B > 1) {
-      // pairs inside each block: round robin over its B columns
-      for (int blk = grp; blk < nb; blk += ngrp) {
-        T x[B][RMAX];
-        bool dx[B];
+    float rmax = 0.f;
+    // exact squared norms at the start of the sweep
+    for (int c = grp; c < n; c += ngrp) {
+      const float* col = W + c * ld + lane;
+      float s2 = 0.f;
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
-          load_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
-          dx[i] = false;
-        }
-        // circle ordering on B positions: pair i is (pos i, pos B-1-i); pos 0
-        // holds column 0, pos q >= 1 holds column 1 + (q - 1 + st) mod (B - 1)
-#pragma unroll
-        for (int st = 0; st < B - 1; ++st) {
-          auto col = [st](int q) { return q == 0 ? 0 : 1 + (q - 1 + st) % (B - 1); };
-          rotate_pairs<T, G, RMAX, B, B / 2>(x, x, dx, dx, [&](int i) { return col(i); },
-                                             [&](int i) { return col(B - 1 - i); }, tol, rmax);
-        }
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-          if (dx[i]) store_col<T, G, RMAX>(W, blk * B + i, n, ld, lane, x[i]);
-      }
-      __syncthreads();
+      for (int k = 0; k < RMAX; ++k)
+        if (k < RMAX - 1 || lane + k * G < n) s2 = fmaf(col[k * G], col[k * G], s2);
+      s2 = group_sum<G>(s2);
+      if (lane == 0) nrm2[c] = s2;
     }
+    __syncthreads();
+    // pairs inside each block
+    for (int blk = grp; blk < nb; blk += ngrp) {
+      float x[B][RMAX], nx[B];
+      bool dx[B];
+      load_block<G, RMAX, B>(W, nrm2, blk, n, ld, lane, x, nx);
+#pragma unroll
+      for (int i = 0; i < B; ++i) dx[i] = false;
+#pragma unroll
+      for (int st = 0; st < B - 1; ++st) {
+        auto col = [st](int q) { return q == 0 ? 0 : 1 + (q - 1 + st) % (B - 1); };
+        rotate_tracked<G, RMAX, B / 2>(x, x, nx, nx, dx, dx, [&](int i) { return col(i); },
+                                       [&](int i) { return col(B - 1 - i); }, tol, rmax, nrot);
+      }
+      store_block<G, RMAX, B>(W, nrm2, blk, n, ld, lane, x, nx, dx);
+    }
+    __syncthreads();
     for (int step = 0; step < nbe - 1; ++step) {
       for (int pr = grp; pr < nbp; pr += ngrp) {
-        const int P = rr_index(pr, step, nbe);
-        const int Q = rr_index(nbe - 1 - pr, step, nbe);
+        const int P = rr_index_nodiv(pr, step, nbe);
+        const int Q = rr_index_nodiv(nbe - 1 - pr, step, nbe);
         if (P >= nb || Q >= nb) continue;  // the padding block of odd nb
-        T x[B][RMAX], y[B][RMAX];
+        float x[B][RMAX], y[B][RMAX], nx[B], ny[B];
         bool dx[B], dy[B];
+        load_block<G, RMAX, B>(W, nrm2, P, n, ld, lane, x, nx);
+        load_block<G, RMAX, B>(W, nrm2, Q, n, ld, lane, y, ny);
 #pragma unroll
         for (int i = 0; i < B; ++i) {
-          load_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
-          load_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
           dx[i] = false;
           dy[i] = false;
         }
 #pragma unroll
         for (int st = 0; st < B; ++st)
-          rotate_pairs<T, G, RMAX, B, B>(x, y, dx, dy, [](int i) { return i; }, [st](int i) { return (i + st) % B; },
-                                         tol, rmax);
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-          if (dx[i]) store_col<T, G, RMAX>(W, P * B + i, n, ld, lane, x[i]);
-          if (dy[i]) store_col<T, G, RMAX>(W, Q * B + i, n, ld, lane, y[i]);
-        }
+          rotate_tracked<G, RMAX, B>(x, y, nx, ny, dx, dy, [](int i) { return i; },
+                                     [st](int i) { return (i + st) % B; }, tol, rmax, nrot);
+        store_block<G, RMAX, B>(W, nrm2, P, n, ld, lane, x, nx, dx);
+        store_block<G, RMAX, B>(W, nrm2, Q, n, ld, lane, y, ny, dy);
       }
       __syncthreads();
     }
-    if (lane == 0 && rmax > T(0)) atomicMax(&rot_flag[sweep], __float_as_int((float)rmax));
+    if (lane == 0 && rmax > 0.f) atomicMax(&rot_flag[sweep], __float_as_int(rmax));
     __syncthreads();
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * tol) return sweep + 1;
   }
   return max_sweeps + 1;
 }

@@ -39,6 +39,7 @@ struct wpcd_context {
   std::vector<Pending> pending;
   double stage_ms[WPCD_N_STAGES] = {0};
   int64_t stage_launches[WPCD_N_STAGES] = {0};
+  unsigned long long* d_counters = nullptr;  // LDS Jacobi work counters (while profiling)
 };
 
 struct wpcd_batch_s {

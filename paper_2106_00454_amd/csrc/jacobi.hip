@@ -65,11 +65,13 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
                                                                const double* __restrict__ v64,
                                                                float* __restrict__ x32, double* __restrict__ eval,
                                                                int32_t* __restrict__ status, int max_sweeps,
-                                                               float tol) {
+                                                               float tol, unsigned long long* counters) {
   extern __shared__ float W[];
+  __shared__ int s_nrot;
   __shared__ float nrm[kMaxLdsN];
-  __shared__ float diag[B == 0 ? kMaxLdsN : 1];
-  __shared__ int perm[B == 0 ? kMaxLdsN : 1];
+  constexpr bool kSorted = B == 0 || B == 5 || B == 6;  // variants with sorted columns, tracked norms
+  __shared__ float diag[kSorted ? kMaxLdsN : 1];
+  __shared__ int perm[kSorted ? kMaxLdsN : 1];
   __shared__ int rot_flag[64];
   __shared__ float scratch[BLOCK / 64];
   __shared__ int bad;
@@ -77,8 +79,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
   const int n = it.n, N = it.N;
-  // variant 0 reads RMAX*G rows per column unguarded: rows n .. RMAX*G-1 are zero
-  const int rows = B == 0 ? max(n, RMAX * G) : n;
+  // variant 0 reads RMAX*G rows per column unguarded, variants 5 and 6 guard
+  // only their last row chunk: the rows up to there (n .. rows-1) are zero
+  const int rows = B == 0 ? max(n, RMAX * G) : ((B == 5 || B == 6) ? max(n, (RMAX - 1) * G) : n);
   const int ld = lds_stride(rows);
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   if (threadIdx.x == 0) bad = 0;
   // H = V + diag(e0) (V symmetric: row-major V is also column-major), rounded to FP32
   float sigma;
-  if constexpr (B == 0) {
+  if constexpr (kSorted) {
     // Variant 0 stores the columns of B = H + sigma I in descending order of
     // their norms (column j of W is column perm[j] of B; rows keep their
     // order, so each column is still an image of a basis vector): the
@@ -160,12 +163,17 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   }
 
   int sweeps;
-  if constexpr (B == 0)  // unblocked, tracked column norms (nrm doubles as |w|^2 during the sweeps)
-    sweeps = onesided_jacobi_lds_tracked<BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag, nrm);
-  else if constexpr (B == 1)
+  int nrot = 0;
+  if (threadIdx.x == 0) s_nrot = 0;
+  // (nrm holds |w|^2 during the sweeps of the tracked variants)
+  if constexpr (B == 0)  // unblocked, tracked column norms
+    sweeps = onesided_jacobi_lds_tracked<BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+  else if constexpr (B == 5)  // blocks of 2 columns, tracked norms
+    sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 2>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+  else if constexpr (B == 6)  // blocks of 4 columns, tracked norms
+    sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 4>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+  else  // unblocked, three dot products per pair
     sweeps = onesided_jacobi_lds<float, BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag);
-  else
-    sweeps = onesided_jacobi_blocked<float, BLOCK, G, RMAX, B>(W, n, ld, tol, max_sweeps, rot_flag);
   __syncthreads();
 
   // column norms
@@ -202,6 +210,16 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   __syncthreads();
   if (threadIdx.x == 0)
     status[item] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
+  if (counters) {  // work counters for the roofline: rotations, pair visits, sweeps
+    if (nrot) atomicAdd(&s_nrot, nrot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int sw = sweeps > max_sweeps ? max_sweeps : sweeps;
+      atomicAdd(&counters[0], (unsigned long long)s_nrot);
+      atomicAdd(&counters[1], (unsigned long long)sw * (unsigned long long)(n * (n - 1) / 2));
+      atomicAdd(&counters[2], (unsigned long long)sw * (unsigned long long)n * (unsigned long long)n);
+    }
+  }
 }
 
 // ---------------------------------------------------------- device-memory path
@@ -509,7 +527,8 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
 
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
-                                 int32_t* status, int max_sweeps, float tol, int block_cols, hipStream_t s) {
+                                 int32_t* status, int max_sweeps, float tol, int block_cols,
+                                 unsigned long long* counters, hipStream_t s) {
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
@@ -519,28 +538,32 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_sel), dim3(block), lds, s, items, sel, grids, v64, x32, eval, status,
-                       max_sweeps, tol);
+                       max_sweeps, tol, counters);
     return hipGetLastError();
   };
-  // 0 (default): unblocked iteration with tracked column norms; 1: unblocked
-  // with three dot products per pair; 2, 4: column blocks of that width
-  const int B = block_cols;
+  // configuration value -> kernel variant: 0 (default) blocks of 2 columns
+  // with tracked norms, 1 unblocked with three dot products per pair, 2
+  // unblocked with tracked norms, 4 blocks of 4 columns with tracked norms
+  const int B = block_cols == 0 ? 5 : (block_cols == 1 ? 1 : (block_cols == 2 ? 0 : 6));
   if (max_n <= 64) {
     if (B == 0) return go(jacobi_f32_lds_kernel<256, 4, 16, 0>, 256, 64);
+    if (B == 5) return go(jacobi_f32_lds_kernel<256, 16, 4, 5>, 256, 48);
+    if (B == 6) return go(jacobi_f32_lds_kernel<256, 32, 2, 6>, 256, 32);
     if (B == 1) return go(jacobi_f32_lds_kernel<256, 4, 16, 1>, 256, 0);
-    if (B == 2) return go(jacobi_f32_lds_kernel<256, 16, 4, 2>, 256, 0);
-    return go(jacobi_f32_lds_kernel<128, 16, 4, 4>, 128, 0);
+    return hipErrorInvalidValue;
   }
   if (max_n <= 128) {
     if (B == 0) return go(jacobi_f32_lds_kernel<512, 8, 16, 0>, 512, 128);
+    if (B == 5) return go(jacobi_f32_lds_kernel<512, 16, 8, 5>, 512, 112);
+    if (B == 6) return go(jacobi_f32_lds_kernel<512, 32, 4, 6>, 512, 96);
     if (B == 1) return go(jacobi_f32_lds_kernel<512, 8, 16, 1>, 512, 0);
-    if (B == 2) return go(jacobi_f32_lds_kernel<512, 16, 8, 2>, 512, 0);
-    return go(jacobi_f32_lds_kernel<256, 16, 8, 4>, 256, 0);
+    return hipErrorInvalidValue;
   }
   if (B == 0) return go(jacobi_f32_lds_kernel<1024, 8, 25, 0>, 1024, 200);
+  if (B == 5) return go(jacobi_f32_lds_kernel<1024, 16, 13, 5>, 1024, 192);
+  if (B == 6) return go(jacobi_f32_lds_kernel<1024, 32, 7, 6>, 1024, 192);
   if (B == 1) return go(jacobi_f32_lds_kernel<1024, 8, 25, 1>, 1024, 0);
-  if (B == 2) return go(jacobi_f32_lds_kernel<1024, 16, 13, 2>, 1024, 0);
-  return go(jacobi_f32_lds_kernel<512, 16, 13, 4>, 512, 0);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
