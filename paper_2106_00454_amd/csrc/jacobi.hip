@@ -272,17 +272,58 @@ __global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restr
   const double* V = v64 + it.v_off;
   T* W = reinterpret_cast<T*>(work + it.w_off);
   GJacState<T>* st = gjac_state<T>(work, it);
+  // Columns of B = H + sigma I in descending order of their norms, as in the
+  // LDS kernel (column j of W is column perm[j] of B): first pass over V for
+  // the Gershgorin bounds and |H e_c|^2, H_cc; second pass writes W.
+  __shared__ T key[kMaxN];
+  __shared__ T dg[kMaxN];
+  __shared__ int perm[kMaxN];
+  constexpr int G = 16;
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+  T lo = T(DBL_MAX), hi = T(-DBL_MAX);
+  for (int c = grp; c < n; c += BLOCK / G) {
+    T off = 0, h2 = 0, d = 0;
+    for (int r = lane; r < n; r += G) {
+      double h = V[(int64_t)c * n + r];
+      if (r == c) h += g.e0[r % N];
+      const T ht = (T)h;
+      h2 = fma(ht, ht, h2);
+      if (r == c) d = ht;
+      else off += fabs(ht);
+    }
+    off = group_sum<G>(off);
+    h2 = group_sum<G>(h2);
+    d = group_sum<G>(d);
+    lo = fmin(lo, d - off);
+    hi = fmax(hi, d + off);
+    if (lane == 0) {
+      key[c] = h2;
+      dg[c] = d;
+    }
+  }
+  lo = block_reduce<BLOCK>(lo, scratch, MinOp<T>());
+  hi = block_reduce<BLOCK>(hi, scratch, MaxOp<T>());
+  const T sigma = (lo < T(0) ? -lo : T(0)) + T(0.05) * (hi - lo);
+  for (int c = threadIdx.x; c < n; c += BLOCK) key[c] = key[c] + sigma * (T(2) * dg[c] + sigma);
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += BLOCK) {
+    const T kc = key[c];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += (key[q] > kc || (key[q] == kc && q < c)) ? 1 : 0;
+    perm[rank] = c;
+  }
+  __syncthreads();
   const int64_t nn = (int64_t)n * n;
   for (int64_t e = threadIdx.x; e < nn; e += BLOCK) {
-    const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
-    double h = V[e];
+    const int j = (int)(e / n), r = (int)(e - (int64_t)j * n);
+    const int c = perm[j];
+    double h = V[(int64_t)c * n + r];
     if (r == c) h += g.e0[r % N];
-    W[e] = (T)h;
+    T w = (T)h;
+    if (r == c) w += sigma;
+    W[e] = w;
   }
   for (int i = threadIdx.x; i < 64; i += BLOCK) st->rotmax[i] = 0;
-  __syncthreads();
-  const T sigma = gershgorin_shift<T, BLOCK>(W, n, n, scratch);
-  for (int c = threadIdx.x; c < n; c += BLOCK) W[(int64_t)c * n + c] += sigma;
   if (threadIdx.x == 0) st->sigma = sigma;
 }
 
@@ -295,28 +336,29 @@ __host__ __device__ constexpr int gjac_ld(int n) {
   return G >= 64 ? n + (64 - n % 64) % 64 : n + ((G - n % (2 * G)) % (2 * G) + 2 * G) % (2 * G);
 }
 
-// Rotates the column pair (p, q) held in LDS by a lane group of G.
+// Rotates the column pair (p, q) held in LDS by a lane group of G, with the
+// squared norms np, nq of the staged columns tracked in LDS (one dot product
+// per pair; |w_p'|^2 = |w_p|^2 - t w_p.w_q, |w_q'|^2 = |w_q|^2 + t w_p.w_q).
 template <typename T, int G, int RMAX>
-__device__ __forceinline__ void lds_pair_rotate(T* wp, T* wq, int n, int lane, T tol, T& rmax) {
+__device__ __forceinline__ void lds_pair_rotate(T* wp, T* wq, T* np, T* nq, int n, int lane, T tol, T& rmax) {
   T xp[RMAX], xq[RMAX];
-  T al = T(0), be = T(0), ga = T(0);
+  T ga = T(0);
 #pragma unroll
   for (int k = 0; k < RMAX; ++k) {
     const int r = lane + k * G;
     const T a = r < n ? wp[r] : T(0), b = r < n ? wq[r] : T(0);
     xp[k] = a;
     xq[k] = b;
-    al = fma(a, a, al);
-    be = fma(b, b, be);
     ga = fma(a, b, ga);
   }
-  al = group_sum<G>(al);
-  be = group_sum<G>(be);
   ga = group_sum<G>(ga);
+  const T al = *np, be = *nq;
   const T nab = sqrt(al * be);
   if (fabs(ga) > tol * nab) {
-    T c, s;
-    hestenes_rotation(al, be, ga, c, s);
+    const T zeta = (be - al) / (T(2) * ga);
+    const T t = copysign(T(1), zeta) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+    const T c = T(1) / sqrt(T(1) + t * t);
+    const T s = c * t;
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
       const int r = lane + k * G;
@@ -324,6 +366,10 @@ __device__ __forceinline__ void lds_pair_rotate(T* wp, T* wq, int n, int lane, T
         wp[r] = c * xp[k] - s * xq[k];
         wq[r] = s * xp[k] + c * xq[k];
       }
+    }
+    if (lane == 0) {
+      *np = al - t * ga;
+      *nq = be + t * ga;
     }
     const T rel = fabs(ga) / nab;
     rmax = rel > rmax ? rel : rmax;
@@ -368,13 +414,24 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
   if (threadIdx.x == 0 && threadIdx.y == 0) any_rot = 0;
   __syncthreads();
   const int lane = threadIdx.x, grp = threadIdx.y;
+  // exact squared norms of the staged columns (tracked through the stages)
+  __shared__ T cn[2 * BW];
+  for (int j = grp; j < nblk * BW; j += BW) {
+    const T* col = L + j * ld;
+    T s2 = T(0);
+    for (int r = lane; r < n; r += G) s2 = fma(col[r], col[r], s2);
+    s2 = group_sum<G>(s2);
+    if (lane == 0) cn[j] = s2;
+  }
+  __syncthreads();
   T rmax = T(0);
   if (INTRA) {
     // circle ordering over the BW columns: BW-1 stages of BW/2 pairs
     for (int s = 0; s < BW - 1; ++s) {
       if (grp < BW / 2) {
         auto col = [s](int q) { return q == 0 ? 0 : 1 + (q - 1 + s) % (BW - 1); };
-        lds_pair_rotate<T, G, RMAX>(L + col(grp) * ld, L + col(BW - 1 - grp) * ld, n, lane, tol, rmax);
+        const int a = col(grp), b = col(BW - 1 - grp);
+        lds_pair_rotate<T, G, RMAX>(L + a * ld, L + b * ld, cn + a, cn + b, n, lane, tol, rmax);
       }
       __syncthreads();
     }
@@ -382,7 +439,8 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
     // cross pairs: stage s pairs column i of the first block with column
     // (i + s) mod BW of the second
     for (int s = 0; s < BW; ++s) {
-      lds_pair_rotate<T, G, RMAX>(L + grp * ld, L + (BW + (grp + s) % BW) * ld, n, lane, tol, rmax);
+      const int b = BW + (grp + s) % BW;
+      lds_pair_rotate<T, G, RMAX>(L + grp * ld, L + b * ld, cn + grp, cn + b, n, lane, tol, rmax);
       __syncthreads();
     }
   }
@@ -502,7 +560,7 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
   static_assert(BW * G <= 1024, "block size");
   if (max_n > RMAX * G) return hipErrorInvalidValue;
   const size_t lds = (size_t)2 * BW * gjac_ld<G>(max_n) * sizeof(T);
-  if (lds + 256 > 160 * 1024) return hipErrorInvalidValue;  // 256 B of static LDS (flags)
+  if (lds + 1024 > 160 * 1024) return hipErrorInvalidValue;  // static LDS: flag, staged-column norms
   auto intra = gjac_block_kernel<T, BW, G, RMAX, true>;
   auto cross = gjac_block_kernel<T, BW, G, RMAX, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(intra),
