@@ -269,26 +269,20 @@ __global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restri
   });
 }
 
-// X' = X M, M = I + E except chain columns (cl[j] >= 0), which are column cl[j]
-// of P Q (n x T in W6).  lam_pre holds the Rayleigh quotients E was built from.
-template <typename XT>
-__global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restrict__ items, int item0,
-                                                         const XT* xin, int xin_ws, double* evec, int xout_ws,
-                                                         const double* __restrict__ lam_pre, double* work,
-                                                         const int32_t* __restrict__ cl, double closec) {
-  __shared__ double As[kTK * kLdT];
-  __shared__ double Bs[kTK * kLdT];
+// M = I + E except chain columns (cl[j] >= 0), which are column cl[j] of
+// P Q (n x T in W6), written row-major to W5.  lam_pre holds the Rayleigh
+// quotients E was built from.  Grid: x = blocks of 64 rows, y = item.
+__global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restrict__ items, int item0,
+                                                        const double* __restrict__ lam_pre, double* work,
+                                                        const int32_t* __restrict__ cl, double closec) {
   __shared__ double lam[kMaxN];
   __shared__ int cpos[kMaxN];
   __shared__ int s_T;
   const ItemDev it = items[item0 + blockIdx.y];
   const int n = it.n;
-  const int nt = (n + kTM - 1) / kTM;
-  if ((int)blockIdx.x >= nt * nt) return;
-  const int tm = blockIdx.x / nt, tc = blockIdx.x % nt;
+  const int r0 = blockIdx.x * kTM;
+  if (r0 >= n) return;
   const WS ws(work, it);
-  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
-  double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
   if (threadIdx.x == 0) s_T = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += kBlock) {
@@ -298,16 +292,32 @@ __global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restri
   }
   __syncthreads();
   const int T = s_T;
-  const double* S = ws.S;
-  const double* G = ws.G;
-  const double* MC = ws.W6;
-  auto fb = [&](int j, int k) -> double {  // M(k, j)
+  const int r1 = min(n, r0 + kTM);
+  for (int64_t e = threadIdx.x; e < (int64_t)(r1 - r0) * n; e += kBlock) {
+    const int k = r0 + (int)(e / n), j = (int)(e % n);
     const int q = cpos[j];
-    if (q >= 0) return MC[(int64_t)k * T + q];
-    return (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j, closec);
-  };
+    ws.W5[(int64_t)k * n + j] =
+        q >= 0 ? ws.W6[(int64_t)k * T + q] : (k == j ? 1.0 : 0.0) + newton_e(ws.S, ws.G, lam, n, k, j, closec);
+  }
+}
+
+// X' = X M with M from form_m_kernel (W5).
+template <typename XT>
+__global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restrict__ items, int item0,
+                                                         const XT* xin, int xin_ws, double* evec, int xout_ws,
+                                                         double* work) {
+  __shared__ double As[kTK * kLdT];
+  __shared__ double Bs[kTK * kLdT];
+  const ItemDev it = items[item0 + blockIdx.y];
+  const int n = it.n;
+  const int nt = (n + kTM - 1) / kTM;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int tm = blockIdx.x / nt, tc = blockIdx.x % nt;
+  const WS ws(work, it);
+  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
+  double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
   d4 acc[2][2];
-  gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajor<XT>{X, n}, fb, acc);
+  gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajor<XT>{X, n}, RowMajorT<double>{ws.W5, n}, acc);
   tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
 }
 
@@ -794,12 +804,13 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
     if (err != hipSuccess) return err;
     for (int i0 = 0; i0 < n_items; i0 += 65535) {
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+      hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work, cl, closec);
       if (st == 0)
         hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, x32, 0, evec,
-                           out_ws, lam_pre, work, cl, closec);
+                           out_ws, work);
       else
         hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0,
-                           (const double*)evec, cur_ws, evec, out_ws, lam_pre, work, cl, closec);
+                           (const double*)evec, cur_ws, evec, out_ws, work);
     }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
