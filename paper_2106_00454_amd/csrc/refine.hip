@@ -32,6 +32,8 @@
 #include "devutil.h"
 #include "internal.h"
 
+#include <type_traits>
+
 namespace wpcd {
 namespace {
 
@@ -40,7 +42,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kBlock = 256;    // 4 wavefronts
 constexpr int kTM = 64;        // output tile edge
 constexpr int kTK = 32;        // reduction chunk
-constexpr int kLdT = kTM + 4;  // LDS stride of a staged operand tile (doubles)
+constexpr int kTileLds = kTK * kTM;  // doubles of one staged operand tile
+constexpr int kXcd = 8;        // XCDs; workgroups are dispatched to them round-robin
 constexpr int kMaxChain = 64;  // columns of one LDS Rayleigh-Ritz batch
 constexpr int kMaxBig = 24;    // longer chains per item, solved in device memory
 constexpr int kBigRows = 19;   // rows per lane of their Jacobi (64 * 19 >= kMaxN)
@@ -50,94 +53,211 @@ constexpr int kBigRows = 19;   // rows per lane of their Jacobi (64 * 19 >= kMax
 // take only smaller updates, whose second-order remainders are below FP64
 // orthogonality).
 
+// One-dimensional grid of (item, tile) pairs in which every tile of an item
+// lands on the same XCD (block b runs on XCD b mod 8), so that the item's
+// operand panels are fetched into one L2 and re-read there by its other
+// tiles.  The grid holds tiles * round_up(n_items, 8) blocks.
+__device__ __forceinline__ bool xcd_item_tile(int tiles, int n_items, int& item, int& tile) {
+  const int b = blockIdx.x;
+  const int s = b / kXcd;
+  item = (s / tiles) * kXcd + b % kXcd;
+  tile = s % tiles;
+  return item < n_items;
+}
+inline unsigned xcd_grid(int tiles, int n_items) {
+  return (unsigned)tiles * (unsigned)((n_items + kXcd - 1) / kXcd * kXcd);
+}
+
 // --------------------------------------------------------------- GEMM tiles
-// acc = sum_k A(m0+i, k) B(k, c0+j) over one 64 x 64 tile; fa(i,k) gives A,
-// fb(j,k) gives B(k,j) (both take (output index, reduction index)).  AKC/BKC:
-// whether the operand's source is contiguous along k (chooses the thread map
-// of the global loads).  Operands are zero outside rows/cols/K.  The next
-// chunk is loaded into registers while the current one is multiplied.
+// acc = sum_k A(m0+i, k) B(k, c0+j) over one 64 x 64 tile; A and B are
+// operand views (below) giving A(i, k) and B(k, j) as op(i, k) / op(j, k).
+// Operands are zero outside rows/cols/K.  The next 32-deep chunk is loaded
+// into registers while the current one is multiplied; the loaded values are
+// not touched until they are staged, so the loads stay in flight across the
+// MFMAs of the current chunk.
 // v_mfma_f64_16x16x4f64: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
 // D[i][j] in lane j + 16*(i % 4), register i / 4.
-template <bool KC, class F>
-__device__ __forceinline__ void fetch(double (&r)[8], int r0, int k0, int n_i, int n_k, const F& f) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (KC) {  // i = tid/8 + 32h, k = 4*(tid%8) + j
-      const int i = (tid >> 3) + 32 * h, kb = (tid & 7) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kb + j;
-        r[4 * h + j] = (r0 + i < n_i && k0 + k < n_k) ? f(r0 + i, k0 + k) : 0.0;
-      }
-    } else {  // k = tid/16 + 16h, i = 4*(tid%16) + j
-      const int k = (tid >> 4) + 16 * h, ib = (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int i = ib + j;
-        r[4 * h + j] = (r0 + i < n_i && k0 + k < n_k) ? f(r0 + i, k0 + k) : 0.0;
-      }
-    }
+// Staging: thread t loads i = t % 64 and four consecutive k of one operand
+// chunk (64 lanes along i per load: coalesced for sources contiguous in i,
+// 32-byte row segments otherwise).  LDS layout: element (i, k) at
+// T[k * 64 + (i ^ 16 (k & 1))].  A 64-bit LDS access is served per half
+// wavefront (32 lanes over 64 four-byte banks): the stores (fixed k, 64 lanes
+// over i) and the MFMA operand reads (16 lanes over i at k and at k + 1 in
+// one half-wave, moved to opposite 16-double halves by the swizzle) then
+// touch every bank once.
+
+// ------------------------------------------------------------ operand views
+// Dense matrix in device memory, element (i, k) at p[i * si + k * sk], read
+// with raw buffer loads: an offset at or beyond the buffer's byte size reads
+// zero, which pads rows >= n_i and k >= n_k without masking the data.
+constexpr unsigned kOob = 0x40000000u;  // beyond every operand (< 12 MB each), no 32-bit wrap when added twice
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Mat {
+  using raw_t = typename std::conditional<sizeof(T) == 8, u32x2, unsigned>::type;
+  __amdgpu_buffer_rsrc_t r;
+  int si, sk;
+  __device__ Mat(const T* p, int64_t elems, int si_, int sk_) : si(si_), sk(sk_) {
+    // word 3 = 0x00020000: raw (untyped) buffer access on gfx9 targets
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)(elems * (int64_t)sizeof(T)),
+                                          0x00020000);
   }
+  __device__ raw_t load(unsigned voff) const {
+    if constexpr (sizeof(T) == 8)
+      return __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+    else
+      return __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
+  }
+  __device__ static double cvt(raw_t x) { return (double)__builtin_bit_cast(T, x); }
+};
+// A operand M^T or B operand M of an n x n row-major M (op(i, k) = M[k][i]: contiguous in i)
+template <typename T>
+__device__ Mat<T> col_view(const T* M, int rows_k, int ld) { return Mat<T>(M, (int64_t)rows_k * ld, 1, ld); }
+// A operand M or B operand M^T (op(i, k) = M[i][k]: contiguous in k)
+template <typename T>
+__device__ Mat<T> row_view(const T* M, int rows_i, int ld) { return Mat<T>(M, (int64_t)rows_i * ld, ld, 1); }
+
+// Any callable op(i, k) (staged values in LDS); out-of-range reads are clamped and zeroed.
+template <class F>
+struct Fn {
+  using raw_t = double;
+  F f;
+  __device__ static double cvt(double x) { return x; }
+};
+template <class F>
+__device__ Fn<F> fn_view(const F& f) { return Fn<F>{f}; }
+
+template <typename T>
+__device__ __forceinline__ void fetch(typename Mat<T>::raw_t (&r)[8], const Mat<T>& op, int r0, int k0, int n_i,
+                                      int n_k) {
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = r0 + (tid & 63);
+  const unsigned base = i < n_i ? (unsigned)(i * op.si) * (unsigned)sizeof(T) : kOob;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + 4 * (wave + 4 * h) + j;  // wave-uniform
+      const unsigned ko = k < n_k ? (unsigned)(k * op.sk) * (unsigned)sizeof(T) : kOob;
+      r[4 * h + j] = op.load(base + ko);
+    }
 }
-template <bool KC>
-__device__ __forceinline__ void stash(double* T, const double (&r)[8]) {
+template <class F>
+__device__ __forceinline__ void fetch(double (&r)[8], const Fn<F>& op, int r0, int k0, int n_i, int n_k) {
   const int tid = threadIdx.x;
+  const int i = r0 + (tid & 63);
+  const bool iv = i < n_i;
+  const int ic = iv ? i : n_i - 1;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (KC) {
-      const int i = (tid >> 3) + 32 * h, kb = (tid & 7) * 4;
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) T[(kb + j) * kLdT + i] = r[4 * h + j];
-    } else {
-      const int k = (tid >> 4) + 16 * h, ib = (tid & 15) * 4;
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + 4 * ((tid >> 6) + 4 * h) + j;
+      const double x = op.f(ic, k < n_k ? k : n_k - 1);
+      r[4 * h + j] = (iv && k < n_k) ? x : 0.0;
+    }
+}
+template <class Op>
+__device__ __forceinline__ void stash(double* T, const typename Op::raw_t (&r)[8]) {
+  const int tid = threadIdx.x;
+  const int i = tid & 63;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) T[k * kLdT + ib + j] = r[4 * h + j];
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * ((tid >> 6) + 4 * h) + j;
+      T[k * kTM + (i ^ ((k & 1) << 4))] = Op::cvt(r[4 * h + j]);
+    }
+}
+
+// The K loop for a wave whose live 16 x 16 sub-blocks are bi < NI, bj < NJ
+// (NI = NJ = 0: the wave only helps staging).  NB = 1 or 2 B operands share
+// the A operand (Bs holds NB staged tiles).
+template <int NI, int NJ, int NB, class OA, class OB0, class OB1>
+__device__ __forceinline__ void gemm_loop(double* As, double* Bs, int m0, int c0, int rows, int cols, int K,
+                                          const OA& oa, const OB0& ob0, const OB1& ob1, d4 (&acc)[NB][2][2]) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  typename OA::raw_t ra[8];
+  typename OB0::raw_t rb0[8];
+  typename OB1::raw_t rb1[8];
+  fetch(ra, oa, m0, 0, rows, K);
+  fetch(rb0, ob0, c0, 0, cols, K);
+  if constexpr (NB > 1) fetch(rb1, ob1, c0, 0, cols, K);
+  // this lane's read offsets for sub-block 0 / 1 at k = 4q + lane / 16: the
+  // swizzle only depends on k & 1 = (lane / 16) & 1
+  const int kk = lane >> 4, sw = (kk & 1) << 4;
+  const int pa[2] = {kk * kTM + ((wr + (lane & 15)) ^ sw), kk * kTM + ((wr + 16 + (lane & 15)) ^ sw)};
+  const int pb[2] = {kk * kTM + ((wc + (lane & 15)) ^ sw), kk * kTM + ((wc + 16 + (lane & 15)) ^ sw)};
+  auto quad = [&](int q) {
+    const int o = q * 4 * kTM;
+    double a[2], b[NB][2];
+#pragma unroll
+    for (int bi = 0; bi < NI; ++bi) a[bi] = As[o + pa[bi]];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int bj = 0; bj < NJ; ++bj) b[nb][bj] = Bs[nb * kTileLds + o + pb[bj]];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int bi = 0; bi < NI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NJ; ++bj)
+          acc[nb][bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[nb][bj], acc[nb][bi][bj], 0, 0, 0);
+  };
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+    __syncthreads();  // previous chunk fully consumed
+    stash<OA>(As, ra);
+    stash<OB0>(Bs, rb0);
+    if constexpr (NB > 1) stash<OB1>(Bs + kTileLds, rb1);
+    __syncthreads();
+    if (k0 + kTK < K) {
+      fetch(ra, oa, m0, k0 + kTK, rows, K);
+      fetch(rb0, ob0, c0, k0 + kTK, cols, K);
+      if constexpr (NB > 1) fetch(rb1, ob1, c0, k0 + kTK, cols, K);
+    }
+    if constexpr (NI > 0 && NJ > 0) {
+      if (K - k0 >= kTK) {
+#pragma unroll
+        for (int q = 0; q < kTK / 4; ++q) quad(q);
+      } else {
+        const int qend = (K - k0 + 3) >> 2;
+        for (int q = 0; q < qend; ++q) quad(q);
+      }
     }
   }
 }
 
-template <bool AKC, bool BKC, class FA, class FB>
-__device__ void gemm_tile(double* As, double* Bs, int m0, int c0, int rows, int cols, int K, const FA& fa,
-                          const FB& fb, d4 (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+template <int NB, class OA, class OB0, class OB1>
+__device__ void gemm_core(double* As, double* Bs, int m0, int c0, int rows, int cols, int K, const OA& oa,
+                          const OB0& ob0, const OB1& ob1, d4 (&acc)[NB][2][2]) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
-  bool live[2][2];
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) live[bi][bj] = (m0 + wr + bi * 16 < rows) && (c0 + wc + bj * 16 < cols);
-  double ra[8], rb[8];
-  fetch<AKC>(ra, m0, 0, rows, K, fa);
-  fetch<BKC>(rb, c0, 0, cols, K, fb);
-  for (int k0 = 0; k0 < K; k0 += kTK) {
-    __syncthreads();  // previous chunk fully consumed
-    stash<AKC>(As, ra);
-    stash<BKC>(Bs, rb);
-    __syncthreads();
-    if (k0 + kTK < K) {
-      fetch<AKC>(ra, m0, k0 + kTK, rows, K, fa);
-      fetch<BKC>(rb, c0, k0 + kTK, cols, K, fb);
-    }
-    const int kend = (K - k0) < kTK ? ((K - k0 + 3) & ~3) : kTK;
-    for (int ks = 0; ks < kend; ks += 4) {
-      const int kr = ks + (lane >> 4);
-      double a[2], b[2];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) a[bi] = As[kr * kLdT + wr + bi * 16 + (lane & 15)];
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) b[bj] = Bs[kr * kLdT + wc + bj * 16 + (lane & 15)];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-          if (live[bi][bj]) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-    }
-  }
+      for (int bj = 0; bj < 2; ++bj) acc[nb][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ni = (m0 + wr < rows) + (m0 + wr + 16 < rows);
+  const int nj = (c0 + wc < cols) + (c0 + wc + 16 < cols);
+  if (ni == 2 && nj == 2)
+    gemm_loop<2, 2, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+  else if (ni == 2 && nj == 1)
+    gemm_loop<2, 1, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+  else if (ni == 1 && nj == 2)
+    gemm_loop<1, 2, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+  else if (ni == 1 && nj == 1)
+    gemm_loop<1, 1, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+  else
+    gemm_loop<0, 0, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+}
+
+template <class OA, class OB>
+__device__ __forceinline__ void gemm_tile(double* As, double* Bs, int m0, int c0, int rows, int cols, int K,
+                                          const OA& oa, const OB& ob, d4 (&acc)[2][2]) {
+  gemm_core<1>(As, Bs, m0, c0, rows, cols, K, oa, ob, ob, reinterpret_cast<d4(&)[1][2][2]>(acc));
 }
 
 template <class G>
@@ -156,30 +276,6 @@ __device__ __forceinline__ void tile_store(int m0, int c0, int rows, int cols, c
       }
     }
 }
-
-// ------------------------------------------------------------ operand views
-struct HOp {  // A = V + diag(e0 per channel copy), symmetric
-  const double* V;
-  const double* e0;
-  int n, N;
-  __device__ double operator()(int i, int k) const {
-    double h = V[(int64_t)i * n + k];
-    if (i == k) h += e0[i % N];
-    return h;
-  }
-};
-template <typename XT>
-struct RowMajor {  // A operand M (fa(i,k) = M[i][k]) or B operand M^T
-  const XT* p;
-  int ld;
-  __device__ double operator()(int r, int c) const { return (double)p[(int64_t)r * ld + c]; }
-};
-template <typename XT>
-struct RowMajorT {  // A operand M^T or B operand M (fb(j,k) = M[k][j])
-  const XT* p;
-  int ld;
-  __device__ double operator()(int i, int k) const { return (double)p[(int64_t)k * ld + i]; }
-};
 
 // Newton correction E(k,j) for k != j (R_kj/2 for a close pair), R_jj/2 on the diagonal
 __device__ __forceinline__ double newton_e(const double* S, const double* G, const double* lam, int n, int k,
@@ -210,39 +306,50 @@ struct WS {
 };
 
 // ------------------------------------------------------------ step kernels
-// grid: x = tile (tm * nt + tc), y = item
+// One-dimensional grids over (item, tile) from xcd_item_tile.
+#define WPCD_LDS_TILES(NB)     \
+  __shared__ double As[kTileLds]; \
+  __shared__ double Bs[(NB) * kTileLds]
+
+// Y = H X = V X + H0 X (H0 diagonal)
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void gemm_y_kernel(const ItemDev* __restrict__ items, int item0,
+__global__ __launch_bounds__(kBlock, 3) void gemm_y_kernel(const ItemDev* __restrict__ items, int n_items,
                                                         const GridDev* __restrict__ grids,
                                                         const double* __restrict__ v64, const XT* xin, int xin_ws,
-                                                        double* work) {
-  __shared__ double As[kTK * kLdT];
-  __shared__ double Bs[kTK * kLdT];
-  const ItemDev it = items[item0 + blockIdx.y];
+                                                        double* work, int tiles) {
+  WPCD_LDS_TILES(1);
+  int item, tile;
+  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
+  const ItemDev it = items[item];
   const int n = it.n;
   const int nt = (n + kTM - 1) / kTM;
-  if ((int)blockIdx.x >= nt * nt) return;
-  const int tm = blockIdx.x / nt, tc = blockIdx.x % nt;
+  if (tile >= nt * nt) return;
+  const int tm = tile / nt, tc = tile % nt;
   const GridDev g = grids[it.grid];
   const WS ws(work, it);
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
   d4 acc[2][2];
-  gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, HOp{v64 + it.v_off, g.e0, n, it.N},
-                         RowMajorT<XT>{X, n}, acc);
+  // V is symmetric: its rows are read as columns (contiguous along the tile's rows)
+  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(v64 + it.v_off, n, n), col_view(X, n, n), acc);
   double* Y = ws.Y;
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Y[(int64_t)r * n + c] = v; });
+  const int N = it.N;
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+    Y[(int64_t)r * n + c] = fma(g.e0[r % N], (double)X[(int64_t)r * n + c], v);  // + H0 X
+  });
 }
 
-// S = X^T Y and G = X^T X on the upper tiles (tm <= tc), mirrored on store
+// S = X^T Y and G = X^T X in one pass over the shared operand X^T, on the
+// upper tiles (tm <= tc), mirrored on store
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restrict__ items, int item0,
-                                                         const XT* xin, int xin_ws, double* work) {
-  __shared__ double As[kTK * kLdT];
-  __shared__ double Bs[kTK * kLdT];
-  const ItemDev it = items[item0 + blockIdx.y];
+__global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restrict__ items, int n_items,
+                                                         const XT* xin, int xin_ws, double* work, int tiles) {
+  WPCD_LDS_TILES(2);
+  int item, t;
+  if (!xcd_item_tile(tiles, n_items, item, t)) return;
+  const ItemDev it = items[item];
   const int n = it.n;
   const int nt = (n + kTM - 1) / kTM;
-  int t = blockIdx.x, tm = 0;
+  int tm = 0;
   while (tm < nt && t >= nt - tm) {
     t -= nt - tm;
     ++tm;
@@ -251,18 +358,17 @@ __global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restri
   const int tc = tm + t;
   const WS ws(work, it);
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
-  d4 acc[2][2];
+  d4 acc[2][2][2];
+  gemm_core<2>(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(X, n, n), col_view<double>(ws.Y, n, n),
+               col_view(X, n, n), acc);
   double* S = ws.S;
   double* G = ws.G;
-  gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajorT<XT>{X, n}, RowMajorT<double>{ws.Y, n},
-                          acc);
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+  tile_store(tm * kTM, tc * kTM, n, n, acc[0], [&](int r, int c, double v) {
     if (r > c) return;  // one writer per symmetric pair
     S[(int64_t)r * n + c] = v;
     S[(int64_t)c * n + r] = v;
   });
-  gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajorT<XT>{X, n}, RowMajorT<XT>{X, n}, acc);
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+  tile_store(tm * kTM, tc * kTM, n, n, acc[1], [&](int r, int c, double v) {
     if (r > c) return;
     G[(int64_t)r * n + c] = v;
     G[(int64_t)c * n + r] = v;
@@ -303,21 +409,22 @@ __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restric
 
 // X' = X M with M from form_m_kernel (W5).
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void gemm_xm_kernel(const ItemDev* __restrict__ items, int item0,
+__global__ __launch_bounds__(kBlock, 3) void gemm_xm_kernel(const ItemDev* __restrict__ items, int n_items,
                                                          const XT* xin, int xin_ws, double* evec, int xout_ws,
-                                                         double* work) {
-  __shared__ double As[kTK * kLdT];
-  __shared__ double Bs[kTK * kLdT];
-  const ItemDev it = items[item0 + blockIdx.y];
+                                                         double* work, int tiles) {
+  WPCD_LDS_TILES(1);
+  int item, tile;
+  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
+  const ItemDev it = items[item];
   const int n = it.n;
   const int nt = (n + kTM - 1) / kTM;
-  if ((int)blockIdx.x >= nt * nt) return;
-  const int tm = blockIdx.x / nt, tc = blockIdx.x % nt;
+  if (tile >= nt * nt) return;
+  const int tm = tile / nt, tc = tile % nt;
   const WS ws(work, it);
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
   double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
   d4 acc[2][2];
-  gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, n, n, RowMajor<XT>{X, n}, RowMajorT<double>{ws.W5, n}, acc);
+  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, row_view(X, n, n), col_view<double>(ws.W5, n, n), acc);
   tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
 }
 
@@ -443,8 +550,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
                                                               int32_t* __restrict__ cl,
                                                               int32_t* __restrict__ status, double closec) {
   constexpr int ldw = kMaxChain | 1;
-  __shared__ double As[kTK * kLdT];
-  __shared__ double Bs[kTK * kLdT];
+  WPCD_LDS_TILES(1);
   __shared__ double lam[kMaxN];
   __shared__ int reach[kMaxN];
   __shared__ short ch_start[kMaxN / 2];
@@ -557,11 +663,11 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     }
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile<true, false>(As, Bs, tm * kTM, 0, n, Tb, n, RowMajor<double>{S, n}, RowMajorT<double>{P, Tb}, acc);
+      gemm_tile(As, Bs, tm * kTM, 0, n, Tb, n, col_view(S, n, n), col_view<double>(P, n, Tb), acc);
       tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { SP[(int64_t)r * Tb + cc] = v; });
     }
     __syncthreads();
-    gemm_tile<false, false>(As, Bs, 0, 0, Tb, Tb, n, RowMajorT<double>{P, Tb}, RowMajorT<double>{SP, Tb}, acc);
+    gemm_tile(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(SP, n, Tb), acc);
     tile_store(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
       if (r > cc) return;  // symmetric: one writer per pair
       const double w = (blk[r] == blk[cc]) ? v : 0.0;
@@ -614,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     // P Q -> chain columns [pos, pos + Tb) of MC
     auto qb = [&](int j, int k) { return Qs[k * kMaxChain + j]; };  // B(k, j) = Q[k][j]
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile<true, false>(As, Bs, tm * kTM, 0, n, Tb, Tb, RowMajor<double>{P, Tb}, qb, acc);
+      gemm_tile(As, Bs, tm * kTM, 0, n, Tb, Tb, row_view<double>(P, n, Tb), fn_view(qb), acc);
       tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
     }
     __syncthreads();
@@ -635,15 +741,13 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm)
       for (int tc = 0; tc < mt; ++tc) {
-        gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, m, n, RowMajor<double>{S, n},
-                               RowMajorT<double>{P, m}, acc);
+        gemm_tile(As, Bs, tm * kTM, tc * kTM, n, m, n, col_view(S, n, n), col_view<double>(P, n, m), acc);
         tile_store(tm * kTM, tc * kTM, n, m, acc, [&](int r, int cc, double v) { SP[(int64_t)r * m + cc] = v; });
       }
     __syncthreads();
     for (int tm = 0; tm < mt; ++tm)
       for (int tc = tm; tc < mt; ++tc) {
-        gemm_tile<false, false>(As, Bs, tm * kTM, tc * kTM, m, m, n, RowMajorT<double>{P, m},
-                                RowMajorT<double>{SP, m}, acc);
+        gemm_tile(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc);
         tile_store(tm * kTM, tc * kTM, m, m, acc, [&](int r, int cc, double v) {
           if (r > cc) return;  // symmetric: one writer per pair
           C[(int64_t)cc * m + r] = v;
@@ -701,8 +805,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm)
       for (int tc = 0; tc < mt; ++tc) {
-        gemm_tile<true, false>(As, Bs, tm * kTM, tc * kTM, n, m, m, RowMajor<double>{P, m},
-                               RowMajorT<double>{Q, m}, acc);
+        gemm_tile(As, Bs, tm * kTM, tc * kTM, n, m, m, row_view<double>(P, n, m), col_view<double>(Q, m, m), acc);
         tile_store(tm * kTM, tc * kTM, n, m, acc,
                    [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
       }
@@ -778,18 +881,16 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
     const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
     double closec = 1.0;
     for (int q = 0; q < close_log10 + st; ++q) closec *= 10.0;
-    for (int i0 = 0; i0 < n_items; i0 += 65535) {
-      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
-      if (st == 0) {
-        hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, grids, v64, x32, 0,
-                           work);
-        hipLaunchKernelGGL(gemm_sg_kernel<float>, dim3(up_tiles, gy), dim3(kBlock), 0, s, items, i0, x32, 0, work);
-      } else {
-        hipLaunchKernelGGL(gemm_y_kernel<double>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, grids, v64,
-                           (const double*)evec, cur_ws, work);
-        hipLaunchKernelGGL(gemm_sg_kernel<double>, dim3(up_tiles, gy), dim3(kBlock), 0, s, items, i0,
-                           (const double*)evec, cur_ws, work);
-      }
+    if (st == 0) {
+      hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+                         grids, v64, x32, 0, work, tiles);
+      hipLaunchKernelGGL(gemm_sg_kernel<float>, dim3(xcd_grid(up_tiles, n_items)), dim3(kBlock), 0, s, items,
+                         n_items, x32, 0, work, up_tiles);
+    } else {
+      hipLaunchKernelGGL(gemm_y_kernel<double>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+                         grids, v64, (const double*)evec, cur_ws, work, tiles);
+      hipLaunchKernelGGL(gemm_sg_kernel<double>, dim3(xcd_grid(up_tiles, n_items)), dim3(kBlock), 0, s, items,
+                         n_items, (const double*)evec, cur_ws, work, up_tiles);
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -805,13 +906,13 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
     for (int i0 = 0; i0 < n_items; i0 += 65535) {
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work, cl, closec);
-      if (st == 0)
-        hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0, x32, 0, evec,
-                           out_ws, work);
-      else
-        hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(tiles, gy), dim3(kBlock), 0, s, items, i0,
-                           (const double*)evec, cur_ws, evec, out_ws, work);
     }
+    if (st == 0)
+      hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+                         x32, 0, evec, out_ws, work, tiles);
+    else
+      hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+                         (const double*)evec, cur_ws, evec, out_ws, work, tiles);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     cur_ws = out_ws;
