@@ -407,8 +407,12 @@ int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hip
     return fail(WPCD_ERR_INVALID, "wpcd_project: unknown u_dtype %d", u_dtype);
   WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
   if (b->n_fine == 0) return WPCD_OK;
+  const int elem = u_dtype == WPCD_DTYPE_F32 ? 4 : 8;
+  bool generic = false;
+  for (const ItemDev& it : b->h_items) generic = generic || (it.basis < 0 && !project_tiled(it, u_fine, elem));
   WPCD_HIP(timed(b->ctx, WPCD_STAGE_PROJECT, stream,
-                 [&] { return launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64, stream); }),
+                 [&] { return launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64,
+                                       generic, stream); }),
            "wpcd_project launch");
   return WPCD_OK;
 }
@@ -465,7 +469,7 @@ int wpcd_basis_register(wpcd_ctx ctx, int grid_id, int n_ch, int n_terms, const 
   if (e == hipSuccess) e = hipMalloc((void**)&d_g, sizeof(GridDev));
   if (e == hipSuccess) e = hipMemcpy(d_it, it.data(), sizeof(ItemDev) * n_terms, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_g, &g.dev, sizeof(GridDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_project(d_it, n_terms, n, d_g, u_terms, u_dtype, bh.dbuf, stream);
+  if (e == hipSuccess) e = launch_project(d_it, n_terms, n, d_g, u_terms, u_dtype, bh.dbuf, true, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   hipFree(d_it);
   hipFree(d_g);

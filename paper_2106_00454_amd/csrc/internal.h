@@ -61,8 +61,14 @@ inline int size_class(int n) { return n <= 64 ? 0 : (n <= 128 ? 1 : (n <= kMaxLd
 constexpr int kMaxN = 1200;
 
 // Kernel launchers (each returns hipSuccess or the launch error).
+// generic: some fine-mesh item is not taken by the tiled kernel (project_tiled)
 hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const void* u,
-                          int u_dtype, double* v64, hipStream_t s);
+                          int u_dtype, double* v64, bool generic, hipStream_t s);
+// fine-mesh items projected by the tiled ng = 8 kernel: their U block starts
+// on a 16-byte boundary (u: the caller's U buffer, elem: its element size)
+__host__ __device__ inline bool project_tiled(const ItemDev& it, const void* u, int elem) {
+  return it.ng == 8 && (((uintptr_t)u + (uintptr_t)it.u_off * (uintptr_t)elem) & 15) == 0;
+}
 hipError_t launch_project_affine(const ItemDev* items, int n_items, int max_n, const BasisDev* bases,
                                  const double* coef, double* v64, hipStream_t s);
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,

@@ -117,16 +117,6 @@ __device__ Mat<T> col_view(const T* M, int rows_k, int ld) { return Mat<T>(M, (i
 template <typename T>
 __device__ Mat<T> row_view(const T* M, int rows_i, int ld) { return Mat<T>(M, (int64_t)rows_i * ld, ld, 1); }
 
-// Any callable op(i, k) (staged values in LDS); out-of-range reads are clamped and zeroed.
-template <class F>
-struct Fn {
-  using raw_t = double;
-  F f;
-  __device__ static double cvt(double x) { return x; }
-};
-template <class F>
-__device__ Fn<F> fn_view(const F& f) { return Fn<F>{f}; }
-
 template <typename T>
 __device__ __forceinline__ void fetch(typename Mat<T>::raw_t (&r)[8], const Mat<T>& op, int r0, int k0, int n_i,
                                       int n_k) {
@@ -140,21 +130,6 @@ __device__ __forceinline__ void fetch(typename Mat<T>::raw_t (&r)[8], const Mat<
       const int k = k0 + 4 * (wave + 4 * h) + j;  // wave-uniform
       const unsigned ko = k < n_k ? (unsigned)(k * op.sk) * (unsigned)sizeof(T) : kOob;
       r[4 * h + j] = op.load(base + ko);
-    }
-}
-template <class F>
-__device__ __forceinline__ void fetch(double (&r)[8], const Fn<F>& op, int r0, int k0, int n_i, int n_k) {
-  const int tid = threadIdx.x;
-  const int i = r0 + (tid & 63);
-  const bool iv = i < n_i;
-  const int ic = iv ? i : n_i - 1;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + 4 * ((tid >> 6) + 4 * h) + j;
-      const double x = op.f(ic, k < n_k ? k : n_k - 1);
-      r[4 * h + j] = (iv && k < n_k) ? x : 0.0;
     }
 }
 template <class Op>
@@ -544,19 +519,24 @@ __device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short
 // one-sided Jacobi on W7, the sorted Q -> Y, P Q -> W6.  Writes the quotients
 // to lam_pre, the refined eigenvalues to eval, and cl[j] = position of column
 // j among all chain columns, or -1.
-__global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __restrict__ items,
+__global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* __restrict__ items,
                                                               double* __restrict__ lam_pre,
                                                               double* __restrict__ eval, double* work,
                                                               int32_t* __restrict__ cl,
                                                               int32_t* __restrict__ status, double closec) {
   constexpr int ldw = kMaxChain | 1;
-  WPCD_LDS_TILES(1);
+  // the chain matrix W of a batch shares LDS with the GEMM staging tiles: it
+  // is written after the P^T S P product's last chunk and read into Q before
+  // the P Q product stages its first one
+  constexpr int kSmem = (2 * kTileLds > kMaxChain * ldw) ? 2 * kTileLds : kMaxChain * ldw;
+  __shared__ double smem[kSmem];
+  double* const As = smem;
+  double* const Bs = smem + kTileLds;
+  double* const W = smem;
   __shared__ double lam[kMaxN];
   __shared__ int reach[kMaxN];
   __shared__ short ch_start[kMaxN / 2];
   __shared__ short ch_len[kMaxN / 2];
-  __shared__ double W[kMaxChain * ldw];
-  __shared__ double Qs[kMaxChain * kMaxChain];
   __shared__ double shift[kMaxChain];
   __shared__ double nrm[kMaxChain];
   __shared__ int cols[kMaxChain];
@@ -628,6 +608,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
   double* P = ws.W5;   // n x Tb
   double* SP = ws.Y;   // n x Tb
   double* MC = ws.W6;  // n x Ttot
+  double* QB = ws.W7;  // Tb x Tb sorted Q of a batch (W7 holds a long chain's matrix later)
   d4 acc[2][2];
   while (true) {
     // next batch: chains [c0, c1) with at most kMaxChain columns in total
@@ -668,6 +649,7 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
     }
     __syncthreads();
     gemm_tile(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(SP, n, Tb), acc);
+    __syncthreads();  // W overlays the staging tiles
     tile_store(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
       if (r > cc) return;  // symmetric: one writer per pair
       const double w = (blk[r] == blk[cc]) ? v : 0.0;
@@ -713,14 +695,13 @@ __global__ __launch_bounds__(kBlock) void refine_chain_kernel(const ItemDev* __r
         const double lq = nrm[q] - shift[q];
         rank += (lq < lj || (lq == lj && q < j)) ? 1 : 0;
       }
-      for (int r = 0; r < Tb; ++r) Qs[r * kMaxChain + rank] = W[j * ldw + r] / nrm[j];
+      for (int r = 0; r < Tb; ++r) QB[r * Tb + rank] = W[j * ldw + r] / nrm[j];
       eval[it.e_off + cols[rank]] = lj;
     }
     __syncthreads();
     // P Q -> chain columns [pos, pos + Tb) of MC
-    auto qb = [&](int j, int k) { return Qs[k * kMaxChain + j]; };  // B(k, j) = Q[k][j]
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile(As, Bs, tm * kTM, 0, n, Tb, Tb, row_view<double>(P, n, Tb), fn_view(qb), acc);
+      gemm_tile(As, Bs, tm * kTM, 0, n, Tb, Tb, row_view<double>(P, n, Tb), col_view<double>(QB, Tb, Tb), acc);
       tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
     }
     __syncthreads();
