@@ -289,7 +289,7 @@ def main() -> int:
     ap.add_argument("--plain-items", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--jacobi-block", type=int, default=0, help="column block width of the LDS Jacobi (0: default)")
+    ap.add_argument("--jacobi-block", type=int, default=0, help="LDS Jacobi variant (wpcd_config.jacobi_block; 0: default)")
     ap.add_argument("--workload", choices=("coupled", "sweep", "large", "serve"), default="coupled",
                     help="coupled: the headline line; sweep / large / serve: the other workloads")
     ap.add_argument("--samples", type=int, default=512, help="sweep: parameter samples per step")
@@ -358,8 +358,11 @@ def main() -> int:
     n = N_CH * N_WP
     avg = {s: (ms / cnt if cnt else 0.0) for s, (ms, cnt) in stages.items()}
     # algorithmic FLOPs of the LDS Jacobi per launch: a dot product (2n) per
-    # column-pair visit, 6n per applied rotation, 2 per norm multiply-add
-    jac_flops = (2.0 * n * counts["pair_visits"] + 6.0 * n * counts["rotations"]
+    # column-pair visit, per applied rotation 4n (scaled rotations, the
+    # default variant: one FMA per element and column) or 6n (plain
+    # rotations), 2 per norm multiply-add
+    rot_flops = 4.0 if args.jacobi_block == 0 else 6.0
+    jac_flops = (2.0 * n * counts["pair_visits"] + rot_flops * n * counts["rotations"]
                  + 2.0 * counts["norm_madds"]) / args.steps
     ref_flops = B * 2 * 6.0 * n ** 3
     cand = {

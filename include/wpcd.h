@@ -94,10 +94,13 @@ typedef struct {
   int32_t jacobi_block;  /* variant of the LDS FP32 Jacobi: 0 (default) column
                             blocks of 2 held in registers, two blocks per lane
                             group and 4 rotations per block step, with tracked
-                            column norms (one dot product per pair); 1 one
-                            column pair per lane group, three dot products per
-                            pair; 2 one pair per group, tracked norms; 4 blocks
-                            of 4 columns, tracked norms                     */
+                            column norms (one dot product per pair) and scaled
+                            rotations (each column carries a scale factor, one
+                            FMA per element and column); 1 one column pair per
+                            lane group, three dot products per pair; 2 one pair
+                            per group, tracked norms; 3 as 0 with plain
+                            rotations; 4 blocks of 4 columns, tracked norms;
+                            other values: WPCD_ERR_INVALID                   */
   int32_t refine_close_log10; /* closeness constant of the first refinement
                             step, c = 10^k (pairs whose first-order update
                             would exceed 1/c are solved by Rayleigh-Ritz);

@@ -120,8 +120,8 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   if (c.max_sweeps < 1 || c.max_sweeps > 60) return fail(WPCD_ERR_INVALID, "max_sweeps must be in [1, 60]");
   if (c.refine_steps < 0 || c.refine_steps > 4) return fail(WPCD_ERR_INVALID, "refine_steps must be in [0, 4]");
   if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
-  if (c.jacobi_block != 0 && c.jacobi_block != 1 && c.jacobi_block != 2 && c.jacobi_block != 4)
-    return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2 or 4");
+  if (c.jacobi_block < 0 || c.jacobi_block > 4)
+    return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2, 3 or 4");
   if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
     return fail(WPCD_ERR_INVALID, "refine_close_log10 must be in [1, 8] (0 = default)");
   WPCD_HIP(hipSetDevice(hip_device), "hipSetDevice");

@@ -378,6 +378,200 @@ __device__ int onesided_jacobi_blocked_tracked(float* W, int n, int ld, float to
   return max_sweeps + 1;
 }
 
+// Scaled rotations for the blocked iteration: column j is stored as w~_j with
+// w_j = d_j w~_j.  The rotation w_p' = c (w_p - t w_q), w_q' = c (w_q + t w_p)
+// is applied as two in-place shears, w~_q <- w~_q + (t d_p/d_q) w~_p, then
+// w~_p <- w~_p - (t c^2 d_q/d_p) w~_q (with the updated w~_q), and the scales
+// d_p <- d_p / c, d_q <- c d_q: one FMA per element and column, no copies.
+// Squared norms are tracked for the true columns w; the pair's inner product
+// is d_p d_q (w~_p . w~_q).  The angle uses t = 2 g sgn(D) / (|D| +
+// sqrt(D^2 + 4 g^2)), D = |w_q|^2 - |w_p|^2, g = w_p . w_q (the smaller of the
+// two Jacobi angles), c = 1/sqrt(1 + t^2).  A scale outside [2^-12, 2^12] is
+// folded back into its column (w~ *= d, d = 1), so the FP32 products stay far
+// from overflow and underflow.
+template <int G, int RMAX, int NP, class IA, class IB, int B>
+__device__ __forceinline__ void rotate_scaled(float (&xs)[B][RMAX], float (&ys)[B][RMAX], float (&ns)[B],
+                                              float (&ms)[B], float (&ds)[B], float (&es)[B], bool (&dx)[B],
+                                              bool (&dy)[B], IA ia, IB ib, float tol2, float& rmax2, int& nrot) {
+  float ga[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) ga[i] = 0.f;
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) ga[i] = fmaf(xs[ia(i)][k], ys[ib(i)][k], ga[i]);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) ga[i] = group_sum<G>(ga[i]);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const float dp = ds[ia(i)], dq = es[ib(i)];
+    const float g = ga[i] * dp * dq;
+    const float al = ns[ia(i)], be = ms[ib(i)];
+    const float ab = al * be, g2 = g * g;
+    if (g2 > tol2 * ab) {
+      const float D = be - al;
+      const float t = copysignf(1.f, D) * (2.f * g) *
+                      __builtin_amdgcn_rcpf(fabsf(D) + __builtin_amdgcn_sqrtf(fmaf(D, D, 4.f * g2)));
+      const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+      const float r = t * __builtin_amdgcn_rcpf(dp * dq);
+      const float bq = r * dp * dp, ap = r * dq * dq * c * c;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) {
+        ys[ib(i)][k] = fmaf(bq, xs[ia(i)][k], ys[ib(i)][k]);
+        xs[ia(i)][k] = fmaf(-ap, ys[ib(i)][k], xs[ia(i)][k]);
+      }
+      ds[ia(i)] = dp * fmaf(t, t, 1.f) * c;
+      es[ib(i)] = c * dq;
+      ns[ia(i)] = al - t * g;
+      ms[ib(i)] = be + t * g;
+      const float rel2 = g2 * __builtin_amdgcn_rcpf(ab);
+      rmax2 = rel2 > rmax2 ? rel2 : rmax2;
+      dx[ia(i)] = true;
+      dy[ib(i)] = true;
+      if (threadIdx.x % G == 0) ++nrot;
+    }
+  }
+}
+
+// Columns blk*B .. blk*B+B-1 (column n, the zero column of odd n, included);
+// rows below (RMAX-1)*G are read unguarded (zero-padded up to there), the
+// last row chunk is read in full (W has G spare floats at its end) and masked.
+template <int G, int RMAX, int B>
+__device__ __forceinline__ void load_block_scaled(const float* W, const float* nrm2, const float* dsc, int blk,
+                                                  int n, int ld, int lane, float (&x)[B][RMAX], float (&nx)[B],
+                                                  float (&d)[B]) {
+  const bool last_ok = lane + (RMAX - 1) * G < n;
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const int c = blk * B + i;
+    const float* col = W + c * ld + lane;
+#pragma unroll
+    for (int k = 0; k < RMAX - 1; ++k) x[i][k] = col[k * G];
+    const float v = col[(RMAX - 1) * G];
+    x[i][RMAX - 1] = last_ok ? v : 0.f;
+    nx[i] = nrm2[c];
+    d[i] = dsc[c];
+  }
+}
+
+template <int G, int RMAX, int B>
+__device__ __forceinline__ void store_block_scaled(float* W, float* nrm2, float* dsc, int blk, int n, int ld,
+                                                   int lane, float (&x)[B][RMAX], const float (&nx)[B],
+                                                   float (&d)[B], const bool (&dirty)[B]) {
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const int c = blk * B + i;
+    if (c >= n || !dirty[i]) continue;
+    if (d[i] < 0x1p-12f || d[i] > 0x1p12f) {  // fold the scale back into the column
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) x[i][k] *= d[i];
+      d[i] = 1.f;
+    }
+    float* col = W + c * ld + lane;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+      if (k < RMAX - 1 || lane + k * G < n) col[k * G] = x[i][k];
+    if (lane == 0) {
+      nrm2[c] = nx[i];
+      dsc[c] = d[i];
+    }
+  }
+}
+
+// The blocked iteration of onesided_jacobi_blocked_tracked with scaled
+// rotations (same ordering, skip test and stopping rule).  W holds nb*B
+// columns (for odd n column n is zero and never rotates) and G spare floats
+// after the last one.  On return the scales are folded into W, so its columns
+// are the true w_j.
+template <int BLOCK, int G, int RMAX, int B>
+__device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
+                                              float* nrm2, float* dsc, int& nrot) {
+  static_assert(B == 2 || B == 4, "block width");
+  const int nb = (n + B - 1) / B;
+  const int nbp = (nb + 1) >> 1;
+  const int nbe = nbp << 1;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
+  const float tol2 = tol * tol;
+  for (int c = threadIdx.x; c < nb * B; c += BLOCK) {
+    dsc[c] = 1.f;
+    nrm2[c] = 0.f;  // stays 0 for the zero column of odd n
+  }
+  int sweeps = max_sweeps + 1;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    float rmax2 = 0.f;
+    __syncthreads();
+    // exact squared norms of the true columns at the start of the sweep
+    for (int c = grp; c < n; c += ngrp) {
+      const float* col = W + c * ld + lane;
+      float s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k)
+        if (k < RMAX - 1 || lane + k * G < n) s2 = fmaf(col[k * G], col[k * G], s2);
+      s2 = group_sum<G>(s2);
+      if (lane == 0) nrm2[c] = s2 * dsc[c] * dsc[c];
+    }
+    __syncthreads();
+    for (int blk = grp; blk < nb; blk += ngrp) {
+      float x[B][RMAX], nx[B], d[B];
+      bool dx[B];
+      load_block_scaled<G, RMAX, B>(W, nrm2, dsc, blk, n, ld, lane, x, nx, d);
+#pragma unroll
+      for (int i = 0; i < B; ++i) dx[i] = false;
+#pragma unroll
+      for (int st = 0; st < B - 1; ++st) {
+        auto col = [st](int q) { return q == 0 ? 0 : 1 + (q - 1 + st) % (B - 1); };
+        rotate_scaled<G, RMAX, B / 2>(x, x, nx, nx, d, d, dx, dx, [&](int i) { return col(i); },
+                                      [&](int i) { return col(B - 1 - i); }, tol2, rmax2, nrot);
+      }
+      store_block_scaled<G, RMAX, B>(W, nrm2, dsc, blk, n, ld, lane, x, nx, d, dx);
+    }
+    __syncthreads();
+    for (int step = 0; step < nbe - 1; ++step) {
+      for (int pr = grp; pr < nbp; pr += ngrp) {
+        const int P = rr_index_nodiv(pr, step, nbe);
+        const int Q = rr_index_nodiv(nbe - 1 - pr, step, nbe);
+        if (P >= nb || Q >= nb) continue;  // the padding block of odd nb
+        float x[B][RMAX], y[B][RMAX], nx[B], ny[B], dxs[B], dys[B];
+        bool dx[B], dy[B];
+        load_block_scaled<G, RMAX, B>(W, nrm2, dsc, P, n, ld, lane, x, nx, dxs);
+        load_block_scaled<G, RMAX, B>(W, nrm2, dsc, Q, n, ld, lane, y, ny, dys);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          dx[i] = false;
+          dy[i] = false;
+        }
+#pragma unroll
+        for (int st = 0; st < B; ++st)
+          rotate_scaled<G, RMAX, B>(x, y, nx, ny, dxs, dys, dx, dy, [](int i) { return i; },
+                                    [st](int i) { return (i + st) % B; }, tol2, rmax2, nrot);
+        store_block_scaled<G, RMAX, B>(W, nrm2, dsc, P, n, ld, lane, x, nx, dxs, dx);
+        store_block_scaled<G, RMAX, B>(W, nrm2, dsc, Q, n, ld, lane, y, ny, dys, dy);
+      }
+      __syncthreads();
+    }
+    if (lane == 0 && rmax2 > 0.f) atomicMax(&rot_flag[sweep], __float_as_int(__builtin_amdgcn_sqrtf(rmax2)));
+    __syncthreads();
+    if (__int_as_float(rot_flag[sweep]) < 8.0f * tol) {
+      sweeps = sweep + 1;
+      break;
+    }
+  }
+  // fold the remaining scales into the columns
+  __syncthreads();
+  for (int c = grp; c < n; c += ngrp) {
+    const float dc = dsc[c];
+    if (dc == 1.f) continue;
+    float* col = W + c * ld + lane;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+      if (k < RMAX - 1 || lane + k * G < n) col[k * G] *= dc;
+  }
+  __syncthreads();
+  return sweeps;
+}
+
 // Work-group reductions through a small shared scratch array (>= BLOCK/64 slots).
 template <int BLOCK, typename T, typename Op>
 __device__ T block_reduce(T v, T* scratch, Op op) {

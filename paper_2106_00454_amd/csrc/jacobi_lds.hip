@@ -26,9 +26,10 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   extern __shared__ float W[];
   __shared__ int s_nrot;
   __shared__ float nrm[kMaxLdsN];
-  constexpr bool kSorted = B == 0 || B == 5 || B == 6;  // variants with sorted columns, tracked norms
+  constexpr bool kSorted = B == 0 || B == 5 || B == 6 || B == 7;  // variants with sorted columns, tracked norms
   __shared__ float diag[kSorted ? kMaxLdsN : 1];
   __shared__ int perm[kSorted ? kMaxLdsN : 1];
+  __shared__ float dsc[B == 7 ? kMaxLdsN : 1];  // column scales of the scaled-rotation variant
   __shared__ int rot_flag[64];
   __shared__ float scratch[BLOCK / 64];
   __shared__ int bad;
@@ -36,9 +37,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
   const int n = it.n, N = it.N;
-  // variant 0 reads RMAX*G rows per column unguarded, variants 5 and 6 guard
+  // variant 0 reads RMAX*G rows per column unguarded, variants 5, 6 and 7 guard
   // only their last row chunk: the rows up to there (n .. rows-1) are zero
-  const int rows = B == 0 ? max(n, RMAX * G) : ((B == 5 || B == 6) ? max(n, (RMAX - 1) * G) : n);
+  const int rows = B == 0 ? max(n, RMAX * G) : ((B == 5 || B == 6 || B == 7) ? max(n, (RMAX - 1) * G) : n);
   const int ld = lds_stride(rows);
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
@@ -101,6 +102,8 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
       if (r == c) w += sigma;
       W[j * ld + r] = w;
     }
+    if (B == 7 && (n & 1))  // the zero column completing the last block of 2
+      for (int r = threadIdx.x; r < rows; r += BLOCK) W[n * ld + r] = 0.f;
     __syncthreads();
   } else {
     const int nr = n * rows;
@@ -127,6 +130,8 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
     sweeps = onesided_jacobi_lds_tracked<BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
   else if constexpr (B == 5)  // blocks of 2 columns, tracked norms
     sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 2>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+  else if constexpr (B == 7)  // blocks of 2 columns, tracked norms, scaled rotations
+    sweeps = onesided_jacobi_blocked_scaled<BLOCK, G, RMAX, 2>(W, n, ld, tol, max_sweeps, rot_flag, nrm, dsc, nrot);
   else if constexpr (B == 6)  // blocks of 4 columns, tracked norms
     sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 4>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
   else  // unblocked, three dot products per pair
@@ -188,8 +193,11 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
-  auto go = [&](auto kern, int block, int rows_min) -> hipError_t {
-    const size_t lds = (size_t)lds_stride(max_n > rows_min ? max_n : rows_min) * max_n * sizeof(float);
+  auto go = [&](auto kern, int block, int rows_min, bool pad = false) -> hipError_t {
+    // pad: one more column for odd sizes and 16 spare floats (scaled-rotation variant)
+    const int cols = pad ? (max_n + 1) / 2 * 2 : max_n;
+    const size_t lds =
+        ((size_t)lds_stride(max_n > rows_min ? max_n : rows_min) * cols + (pad ? 16 : 0)) * sizeof(float);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -198,12 +206,15 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
     return hipGetLastError();
   };
   // configuration value -> kernel variant: 0 (default) blocks of 2 columns
-  // with tracked norms, 1 unblocked with three dot products per pair, 2
-  // unblocked with tracked norms, 4 blocks of 4 columns with tracked norms
-  const int B = block_cols == 0 ? 5 : (block_cols == 1 ? 1 : (block_cols == 2 ? 0 : 6));
+  // with tracked norms and scaled rotations, 1 unblocked with three dot
+  // products per pair, 2 unblocked with tracked norms, 3 blocks of 2 columns
+  // with tracked norms and plain rotations, 4 blocks of 4 columns with
+  // tracked norms
+  const int B = block_cols == 0 ? 7 : (block_cols == 1 ? 1 : (block_cols == 2 ? 0 : (block_cols == 3 ? 5 : 6)));
   if (max_n <= 64) {
     if (B == 0) return go(jacobi_f32_lds_kernel<256, 4, 16, 0>, 256, 64);
     if (B == 5) return go(jacobi_f32_lds_kernel<256, 16, 4, 5>, 256, 48);
+    if (B == 7) return go(jacobi_f32_lds_kernel<256, 16, 4, 7>, 256, 48, true);
     if (B == 6) return go(jacobi_f32_lds_kernel<256, 32, 2, 6>, 256, 32);
     if (B == 1) return go(jacobi_f32_lds_kernel<256, 4, 16, 1>, 256, 0);
     return hipErrorInvalidValue;
@@ -211,12 +222,14 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
   if (max_n <= 128) {
     if (B == 0) return go(jacobi_f32_lds_kernel<512, 8, 16, 0>, 512, 128);
     if (B == 5) return go(jacobi_f32_lds_kernel<512, 16, 8, 5>, 512, 112);
+    if (B == 7) return go(jacobi_f32_lds_kernel<512, 16, 8, 7>, 512, 112, true);
     if (B == 6) return go(jacobi_f32_lds_kernel<512, 32, 4, 6>, 512, 96);
     if (B == 1) return go(jacobi_f32_lds_kernel<512, 8, 16, 1>, 512, 0);
     return hipErrorInvalidValue;
   }
   if (B == 0) return go(jacobi_f32_lds_kernel<1024, 8, 25, 0>, 1024, 200);
   if (B == 5) return go(jacobi_f32_lds_kernel<1024, 16, 13, 5>, 1024, 192);
+  if (B == 7) return go(jacobi_f32_lds_kernel<1024, 16, 13, 7>, 1024, 192, true);
   if (B == 6) return go(jacobi_f32_lds_kernel<1024, 32, 7, 6>, 1024, 192);
   if (B == 1) return go(jacobi_f32_lds_kernel<1024, 8, 25, 1>, 1024, 0);
   return hipErrorInvalidValue;

@@ -160,3 +160,34 @@ def test_argument_errors_are_reported_before_launch(ctx):
     with pytest.raises(wp.WPCDError) as e:
         b.eigh(bufs["v64"], 7, bufs["eval"], bufs["evec"], bufs["eig_status"])
     assert e.value.code == wp.WPCD_ERR_INVALID
+
+
+# ------------------------------------------------- LDS Jacobi variants
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_lds_jacobi_variants_match_oracle(variant):
+    # every variant of the in-LDS FP32 Jacobi (wpcd_config.jacobi_block), on
+    # one item of each LDS size class (n = 37, 40, 128, 200), mixed precision
+    vctx = wp.Context(0, jacobi_block=variant)
+    specs = [("yam", 37, 1), ("cyuk", 20, 2), ("cyuk", 64, 2), ("cyuk", 100, 2)]
+    items, mats, refs = [], [], []
+    for sid, (kind, N, K) in enumerate(specs):
+        k = configs.grid("coupled_yukawa") if N == 100 else grids.tan2_bounded(N)
+        g = vctx.grid(k, 8)
+        xo, _ = ow.gauss_nodes(k, 8)
+        if kind == "yam":
+            f = lambda x: potentials.yamaguchi(x, x, 1.7, 1.4)
+            J = 0
+        else:
+            c = configs.yukawa_coefficients(200 + sid)
+            f = lambda x, c=c: sum(ci * ti for ci, ti in zip(c, configs.coupled_yukawa_terms(x)))
+            J = 1
+        items.append((g, K, J, sid))
+        mats.append(f(g.nodes))
+        refs.append((k, ow.solve_channel(k, 8, f(xo), K), J))
+    b, host = run_items(vctx, items, mats, wp.MIXED)
+    for i, (k, ref, J) in enumerate(refs):
+        _, kbar, _ = ow.bins(k)
+        it = item_view(b, host, i)
+        sig_ref = oo.sigma_tot([(J, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
+        check_item(f"jacobi variant={variant} item={i} n={it['v'].shape[0]}", it, ref, k, wp.MIXED, J, sig_ref,
+                   host["sigma"][i])
