@@ -105,6 +105,12 @@ typedef struct {
                             step, c = 10^k (pairs whose first-order update
                             would exceed 1/c are solved by Rayleigh-Ritz);
                             later steps use 10x more each; 0 = default 3    */
+  double jacobi_stop_f32; /* FP32 Jacobi (LDS and device-memory): end the
+                            iteration after a sweep whose largest rotated
+                            pair had |w_p.w_q|/(|w_p||w_q|) below this; must
+                            lie in (0, 1); 0 = default max(3e-5, 8 x
+                            jacobi_tol_f32).  The FP64 path always uses
+                            8 x jacobi_tol_f64                               */
 } wpcd_config;
 
 /* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */

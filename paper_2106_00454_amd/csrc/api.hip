@@ -114,12 +114,19 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   WPCD_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   if (hip_device < 0 || hip_device >= ndev)
     return fail(WPCD_ERR_INVALID, "wpcd_create: device %d out of range (%d devices)", hip_device, ndev);
-  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0};
+  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0, 0.0};
   if (cfg) c = *cfg;
   if (c.refine_close_log10 == 0) c.refine_close_log10 = 3;
+  // default stop: one sweep after the largest rotation fell below 3e-5 the
+  // columns are orthogonal to FP32 rounding (the next sweep would rotate at
+  // most pairs at the tolerance level); never below 8 x tol, where rotations
+  // at the skip threshold would recur
+  if (c.jacobi_stop_f32 == 0.0) c.jacobi_stop_f32 = std::max(3e-5, 8.0 * c.jacobi_tol_f32);
   if (c.max_sweeps < 1 || c.max_sweeps > 60) return fail(WPCD_ERR_INVALID, "max_sweeps must be in [1, 60]");
   if (c.refine_steps < 0 || c.refine_steps > 4) return fail(WPCD_ERR_INVALID, "refine_steps must be in [0, 4]");
   if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
+  if (!(c.jacobi_stop_f32 > 0) || !(c.jacobi_stop_f32 < 1))
+    return fail(WPCD_ERR_INVALID, "jacobi_stop_f32 must be in (0, 1) (0 = default)");
   if (c.jacobi_block < 0 || c.jacobi_block > 4)
     return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2, 3 or 4");
   if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
@@ -503,12 +510,12 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                        if (k < kNumClasses - 1)
                          e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
                                                    b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
-                                                   c.jacobi_block, b->ctx->profiling ? b->ctx->d_counters : nullptr,
-                                                   stream);
+                                                   (float)c.jacobi_stop_f32, c.jacobi_block,
+                                                   b->ctx->profiling ? b->ctx->d_counters : nullptr, stream);
                        else
                          e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
                                                   b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
-                                                  c.jacobi_tol_f32, stream);
+                                                  c.jacobi_tol_f32, c.jacobi_stop_f32, stream);
                      }
                      return e;
                    }),
@@ -525,7 +532,7 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                    [&] {
                      return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids, v64,
                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
-                                                 c.jacobi_tol_f64, stream);
+                                                 c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, stream);
                    }),
              "wpcd_eigh: FP64 Jacobi launch");
   }

@@ -91,7 +91,7 @@ __device__ __forceinline__ void hestenes_rotation(T al, T be, T ga, T& c, T& s) 
 // number of sweeps run, or max_sweeps + 1 if the last allowed sweep still
 // rotated larger pairs (not converged).  Ends with a barrier.
 template <typename T, int BLOCK, int G, int RMAX>
-__device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, int* rot_flag) {
+__device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, T stop, int max_sweeps, int* rot_flag) {
   const int npair = (n + 1) >> 1;
   const int ne = npair << 1;
   const int lane = threadIdx.x % G;
@@ -142,7 +142,7 @@ __device__ int onesided_jacobi_lds(T* W, int n, int ld, T tol, int max_sweeps, i
       }
       __syncthreads();
     }
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+    if (__int_as_float(rot_flag[sweep]) < (float)stop) return sweep + 1;
   }
   return max_sweeps + 1;
 }
@@ -168,7 +168,7 @@ __device__ __forceinline__ int rr_index_nodiv(int pos, int step, int ne) {
 // value as onesided_jacobi_lds; nrot (lane 0 of each group) counts the
 // rotations the group applied.
 template <int BLOCK, int G, int RMAX>
-__device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
+__device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, float stop, int max_sweeps, int* rot_flag,
                                            float* nrm2, int& nrot) {
   const int npair = (n + 1) >> 1;
   const int ne = npair << 1;
@@ -224,7 +224,7 @@ __device__ int onesided_jacobi_lds_tracked(float* W, int n, int ld, float tol, i
       }
       __syncthreads();
     }
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * tol) return sweep + 1;
+    if (__int_as_float(rot_flag[sweep]) < stop) return sweep + 1;
   }
   return max_sweeps + 1;
 }
@@ -310,7 +310,8 @@ __device__ __forceinline__ void store_block(float* W, float* nrm2, int blk, int 
 }
 
 template <int BLOCK, int G, int RMAX, int B>
-__device__ int onesided_jacobi_blocked_tracked(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
+__device__ int onesided_jacobi_blocked_tracked(float* W, int n, int ld, float tol, float stop, int max_sweeps,
+                                               int* rot_flag,
                                                float* nrm2, int& nrot) {
   static_assert(B == 2 || B == 4, "block width");
   const int nb = (n + B - 1) / B;
@@ -373,7 +374,7 @@ __device__ int onesided_jacobi_blocked_tracked(float* W, int n, int ld, float to
     }
     if (lane == 0 && rmax > 0.f) atomicMax(&rot_flag[sweep], __float_as_int(rmax));
     __syncthreads();
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * tol) return sweep + 1;
+    if (__int_as_float(rot_flag[sweep]) < stop) return sweep + 1;
   }
   return max_sweeps + 1;
 }
@@ -484,7 +485,8 @@ __device__ __forceinline__ void store_block_scaled(float* W, float* nrm2, float*
 // after the last one.  On return the scales are folded into W, so its columns
 // are the true w_j.
 template <int BLOCK, int G, int RMAX, int B>
-__device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol, int max_sweeps, int* rot_flag,
+__device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol, float stop, int max_sweeps,
+                                              int* rot_flag,
                                               float* nrm2, float* dsc, int& nrot) {
   static_assert(B == 2 || B == 4, "block width");
   const int nb = (n + B - 1) / B;
@@ -553,7 +555,7 @@ __device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol
     }
     if (lane == 0 && rmax2 > 0.f) atomicMax(&rot_flag[sweep], __float_as_int(__builtin_amdgcn_sqrtf(rmax2)));
     __syncthreads();
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * tol) {
+    if (__int_as_float(rot_flag[sweep]) < stop) {
       sweeps = sweep + 1;
       break;
     }

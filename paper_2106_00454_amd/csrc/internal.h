@@ -73,11 +73,12 @@ hipError_t launch_project_affine(const ItemDev* items, int n_items, int max_n, c
                                  const double* coef, double* v64, hipStream_t s);
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
-                                 int32_t* status, int max_sweeps, float tol, int block_cols,
+                                 int32_t* status, int max_sweeps, float tol, float stop, int block_cols,
                                  unsigned long long* counters, hipStream_t s);
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
-                                double* eval, int32_t* status, int max_sweeps, double tol, hipStream_t s);
+                                double* eval, int32_t* status, int max_sweeps, double tol, double stop,
+                                hipStream_t s);
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                          const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
                          int32_t* status, int steps, int close_log10, hipStream_t s);

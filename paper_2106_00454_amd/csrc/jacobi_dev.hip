@@ -27,7 +27,8 @@ namespace {
 template <typename T>
 struct GJacState {
   T sigma;
-  int32_t pad[3];
+  float stop;          // the iteration ends after a sweep whose largest rotated pair was below this
+  int32_t pad[2];
   int32_t rotmax[64];  // per sweep, float bits of the largest rotated pair
 };
 
@@ -39,15 +40,16 @@ __device__ __forceinline__ GJacState<T>* gjac_state(double* work, const ItemDev&
 }
 
 template <typename T>
-__device__ __forceinline__ bool gjac_converged(const GJacState<T>* st, int sweep, T tol) {
-  return sweep > 0 && __int_as_float(__atomic_load_n(&st->rotmax[sweep - 1], __ATOMIC_RELAXED)) < 8.0f * (float)tol;
+__device__ __forceinline__ bool gjac_converged(const GJacState<T>* st, int sweep) {
+  return sweep > 0 && __int_as_float(__atomic_load_n(&st->rotmax[sweep - 1], __ATOMIC_RELAXED)) < st->stop;
 }
 
 template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restrict__ items,
                                                           const int32_t* __restrict__ sel,
                                                           const GridDev* __restrict__ grids,
-                                                          const double* __restrict__ v64, double* work) {
+                                                          const double* __restrict__ v64, double* work,
+                                                          float stop) {
   __shared__ T scratch[BLOCK / 64];
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
@@ -108,7 +110,10 @@ __global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restr
     W[e] = w;
   }
   for (int i = threadIdx.x; i < 64; i += BLOCK) st->rotmax[i] = 0;
-  if (threadIdx.x == 0) st->sigma = sigma;
+  if (threadIdx.x == 0) {
+    st->sigma = sigma;
+    st->stop = stop;
+  }
 }
 
 // LDS column stride of the block kernels: the smallest ld >= n with
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
   }
   T* W = reinterpret_cast<T*>(work + it.w_off);
   GJacState<T>* st = gjac_state<T>(work, it);
-  if (gjac_converged(st, sweep, tol)) return;
+  if (gjac_converged(st, sweep)) return;
   const int ld = gjac_ld<G>(n);
   // stage the columns (absent columns beyond n are zero and never written back)
   for (int b = 0; b < nblk; ++b)
@@ -267,7 +272,7 @@ __global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __res
   const T sigma = st->sigma;
   int sweeps = max_sweeps + 1;
   for (int s = 0; s < max_sweeps; ++s)
-    if (__int_as_float(st->rotmax[s]) < 8.0f * (float)tol) {
+    if (__int_as_float(st->rotmax[s]) < st->stop) {
       sweeps = s + 1;
       break;
     }
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __res
 template <typename T, int BW, int G, int RMAX>
 hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max_n, const GridDev* grids,
                     const double* v64, double* work, double* evec, float* x32, double* eval, int32_t* status,
-                    int max_sweeps, T tol, hipStream_t s) {
+                    int max_sweeps, T tol, float stop, hipStream_t s) {
   static_assert(BW * G <= 1024, "block size");
   if (max_n > RMAX * G) return hipErrorInvalidValue;
   const size_t lds = (size_t)2 * BW * gjac_ld<G>(max_n) * sizeof(T);
@@ -354,7 +359,8 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
                             (int)lds);
   if (e != hipSuccess) return e;
   const int nb = (max_n + BW - 1) / BW, nbp = (nb + 1) >> 1, nbe = nbp << 1;
-  hipLaunchKernelGGL((gjac_init_kernel<T, 1024>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work);
+  hipLaunchKernelGGL((gjac_init_kernel<T, 1024>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work,
+                     stop);
   for (int sw = 0; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(intra, dim3(nb, n_sel), dim3(G, BW), lds, s, items, sel, work, sw, 0, tol);
     for (int step = 0; step < nbe - 1; ++step)
@@ -369,7 +375,8 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
 
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
-                                double* eval, int32_t* status, int max_sweeps, double tol, hipStream_t s) {
+                                double* eval, int32_t* status, int max_sweeps, double tol, double stop,
+                                hipStream_t s) {
   if (max_n > kMaxN || max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
   // block width: two blocks of the largest item fill at most 160 KiB of LDS;
@@ -378,24 +385,24 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
     const float t = (float)tol;
     if (max_n <= 304)
       return gjac_run<float, 64, 16, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                         max_sweeps, t, s);
+                                         max_sweeps, t, (float)stop, s);
     if (max_n <= 608)
       return gjac_run<float, 32, 32, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                         max_sweeps, t, s);
+                                         max_sweeps, t, (float)stop, s);
     return gjac_run<float, 16, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, t, s);
+                                       max_sweeps, t, (float)stop, s);
   }
   if (max_n <= 144)
     return gjac_run<double, 64, 16, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, tol, s);
+                                       max_sweeps, tol, (float)stop, s);
   if (max_n <= 288)
     return gjac_run<double, 32, 32, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, tol, s);
+                                       max_sweeps, tol, (float)stop, s);
   if (max_n <= 576)
     return gjac_run<double, 16, 64, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                        max_sweeps, tol, s);
+                                        max_sweeps, tol, (float)stop, s);
   return gjac_run<double, 8, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status, max_sweeps,
-                                     tol, s);
+                                     tol, (float)stop, s);
 }
 
 }  // namespace wpcd

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
                                                                const double* __restrict__ v64,
                                                                float* __restrict__ x32, double* __restrict__ eval,
                                                                int32_t* __restrict__ status, int max_sweeps,
-                                                               float tol, unsigned long long* counters) {
+                                                               float tol, float stop, unsigned long long* counters) {
   extern __shared__ float W[];
   __shared__ int s_nrot;
   __shared__ float nrm[kMaxLdsN];
@@ -127,15 +127,16 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   if (threadIdx.x == 0) s_nrot = 0;
   // (nrm holds |w|^2 during the sweeps of the tracked variants)
   if constexpr (B == 0)  // unblocked, tracked column norms
-    sweeps = onesided_jacobi_lds_tracked<BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+    sweeps = onesided_jacobi_lds_tracked<BLOCK, G, RMAX>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, nrot);
   else if constexpr (B == 5)  // blocks of 2 columns, tracked norms
-    sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 2>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+    sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 2>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, nrot);
   else if constexpr (B == 7)  // blocks of 2 columns, tracked norms, scaled rotations
-    sweeps = onesided_jacobi_blocked_scaled<BLOCK, G, RMAX, 2>(W, n, ld, tol, max_sweeps, rot_flag, nrm, dsc, nrot);
+    sweeps = onesided_jacobi_blocked_scaled<BLOCK, G, RMAX, 2>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc,
+                                                                nrot);
   else if constexpr (B == 6)  // blocks of 4 columns, tracked norms
-    sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 4>(W, n, ld, tol, max_sweeps, rot_flag, nrm, nrot);
+    sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 4>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, nrot);
   else  // unblocked, three dot products per pair
-    sweeps = onesided_jacobi_lds<float, BLOCK, G, RMAX>(W, n, ld, tol, max_sweeps, rot_flag);
+    sweeps = onesided_jacobi_lds<float, BLOCK, G, RMAX>(W, n, ld, tol, stop, max_sweeps, rot_flag);
   __syncthreads();
 
   // column norms
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
 
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
-                                 int32_t* status, int max_sweeps, float tol, int block_cols,
+                                 int32_t* status, int max_sweeps, float tol, float stop, int block_cols,
                                  unsigned long long* counters, hipStream_t s) {
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
@@ -202,7 +203,7 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_sel), dim3(block), lds, s, items, sel, grids, v64, x32, eval, status,
-                       max_sweeps, tol, counters);
+                       max_sweeps, tol, stop, counters);
     return hipGetLastError();
   };
   // configuration value -> kernel variant: 0 (default) blocks of 2 columns

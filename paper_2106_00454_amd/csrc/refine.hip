@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     for (int j = threadIdx.x; j < m; j += kBlock) C[(int64_t)j * m + j] += sh;
     __syncthreads();
-    const int swb = onesided_jacobi_lds<double, kBlock, 64, kBigRows>(C, m, m, 1e-15, 40, rot_flag);
+    const int swb = onesided_jacobi_lds<double, kBlock, 64, kBigRows>(C, m, m, 1e-15, 8e-15, 40, rot_flag);
     if (swb > 40 && threadIdx.x == 0) s_fail = 1;
     for (int j = wave; j < m; j += kBlock / 64) {
       double s2 = 0.0;
