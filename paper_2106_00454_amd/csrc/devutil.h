@@ -393,7 +393,8 @@ __device__ int onesided_jacobi_blocked_tracked(float* W, int n, int ld, float to
 template <int G, int RMAX, int NP, class IA, class IB, int B>
 __device__ __forceinline__ void rotate_scaled(float (&xs)[B][RMAX], float (&ys)[B][RMAX], float (&ns)[B],
                                               float (&ms)[B], float (&ds)[B], float (&es)[B], bool (&dx)[B],
-                                              bool (&dy)[B], IA ia, IB ib, float tol2, float& rmax2, int& nrot) {
+                                              bool (&dy)[B], IA ia, IB ib, float tol2, float stop2, bool& big,
+                                              int& nrot) {
   float ga[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) ga[i] = 0.f;
@@ -406,27 +407,28 @@ __device__ __forceinline__ void rotate_scaled(float (&xs)[B][RMAX], float (&ys)[
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
     const float dp = ds[ia(i)], dq = es[ib(i)];
-    const float g = ga[i] * dp * dq;
+    const float pq = dp * dq;
+    const float g = ga[i] * pq;
     const float al = ns[ia(i)], be = ms[ib(i)];
     const float ab = al * be, g2 = g * g;
     if (g2 > tol2 * ab) {
       const float D = be - al;
       const float t = copysignf(1.f, D) * (2.f * g) *
                       __builtin_amdgcn_rcpf(fabsf(D) + __builtin_amdgcn_sqrtf(fmaf(D, D, 4.f * g2)));
-      const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-      const float r = t * __builtin_amdgcn_rcpf(dp * dq);
+      const float u = fmaf(t, t, 1.f);
+      const float c = __builtin_amdgcn_rsqf(u);
+      const float r = t * __builtin_amdgcn_rcpf(pq);
       const float bq = r * dp * dp, ap = r * dq * dq * c * c;
 #pragma unroll
       for (int k = 0; k < RMAX; ++k) {
         ys[ib(i)][k] = fmaf(bq, xs[ia(i)][k], ys[ib(i)][k]);
         xs[ia(i)][k] = fmaf(-ap, ys[ib(i)][k], xs[ia(i)][k]);
       }
-      ds[ia(i)] = dp * fmaf(t, t, 1.f) * c;
+      ds[ia(i)] = dp * u * c;
       es[ib(i)] = c * dq;
       ns[ia(i)] = al - t * g;
       ms[ib(i)] = be + t * g;
-      const float rel2 = g2 * __builtin_amdgcn_rcpf(ab);
-      rmax2 = rel2 > rmax2 ? rel2 : rmax2;
+      big = big || g2 > stop2 * ab;  // a rotation at or above the stopping threshold
       dx[ia(i)] = true;
       dy[ib(i)] = true;
       if (threadIdx.x % G == 0) ++nrot;
@@ -480,7 +482,8 @@ __device__ __forceinline__ void store_block_scaled(float* W, float* nrm2, float*
 }
 
 // The blocked iteration of onesided_jacobi_blocked_tracked with scaled
-// rotations (same ordering, skip test and stopping rule).  W holds nb*B
+// rotations (same ordering, skip test and stopping rule; rot_flag[sweep]
+// becomes 1 when a rotation of the sweep reached the stopping threshold).  W holds nb*B
 // columns (for odd n column n is zero and never rotates) and G spare floats
 // after the last one.  On return the scales are folded into W, so its columns
 // are the true w_j.
@@ -495,14 +498,14 @@ __device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol
   const int lane = threadIdx.x % G;
   const int grp = threadIdx.x / G;
   constexpr int ngrp = BLOCK / G;
-  const float tol2 = tol * tol;
+  const float tol2 = tol * tol, stop2 = stop * stop;
   for (int c = threadIdx.x; c < nb * B; c += BLOCK) {
     dsc[c] = 1.f;
     nrm2[c] = 0.f;  // stays 0 for the zero column of odd n
   }
   int sweeps = max_sweeps + 1;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    float rmax2 = 0.f;
+    bool big = false;
     __syncthreads();
     // exact squared norms of the true columns at the start of the sweep
     for (int c = grp; c < n; c += ngrp) {
@@ -525,7 +528,7 @@ __device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol
       for (int st = 0; st < B - 1; ++st) {
         auto col = [st](int q) { return q == 0 ? 0 : 1 + (q - 1 + st) % (B - 1); };
         rotate_scaled<G, RMAX, B / 2>(x, x, nx, nx, d, d, dx, dx, [&](int i) { return col(i); },
-                                      [&](int i) { return col(B - 1 - i); }, tol2, rmax2, nrot);
+                                      [&](int i) { return col(B - 1 - i); }, tol2, stop2, big, nrot);
       }
       store_block_scaled<G, RMAX, B>(W, nrm2, dsc, blk, n, ld, lane, x, nx, d, dx);
     }
@@ -547,13 +550,13 @@ __device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol
 #pragma unroll
         for (int st = 0; st < B; ++st)
           rotate_scaled<G, RMAX, B>(x, y, nx, ny, dxs, dys, dx, dy, [](int i) { return i; },
-                                    [st](int i) { return (i + st) % B; }, tol2, rmax2, nrot);
+                                    [st](int i) { return (i + st) % B; }, tol2, stop2, big, nrot);
         store_block_scaled<G, RMAX, B>(W, nrm2, dsc, P, n, ld, lane, x, nx, dxs, dx);
         store_block_scaled<G, RMAX, B>(W, nrm2, dsc, Q, n, ld, lane, y, ny, dys, dy);
       }
       __syncthreads();
     }
-    if (lane == 0 && rmax2 > 0.f) atomicMax(&rot_flag[sweep], __float_as_int(__builtin_amdgcn_sqrtf(rmax2)));
+    if (lane == 0 && big) rot_flag[sweep] = __float_as_int(1.f);  // any group may set it
     __syncthreads();
     if (__int_as_float(rot_flag[sweep]) < stop) {
       sweeps = sweep + 1;

@@ -79,6 +79,12 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,
                                 hipStream_t s);
+// FP64 device-memory Jacobi epilogue: Rayleigh quotients x^T H x of the
+// normalised columns it left in the work-space (MFMA product H X), sort by
+// them, write eval and the row-major evec of every item of the batch.
+hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
+                               const double* v64, double* work, double* evec, double* eval, int32_t* status,
+                               hipStream_t s);
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                          const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
                          int32_t* status, int steps, int close_log10, hipStream_t s);

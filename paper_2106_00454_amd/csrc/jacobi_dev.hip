@@ -264,9 +264,7 @@ __global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __res
   __shared__ double nrm[kMaxN];
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
-  const int n = it.n, N = it.N;
-  const GridDev g = grids[it.grid];
-  const double* V = v64 + it.v_off;
+  const int n = it.n;
   const T* W = reinterpret_cast<const T*>(work + it.w_off);
   const GJacState<T>* st = gjac_state<T>(work, it);
   const T sigma = st->sigma;
@@ -279,64 +277,61 @@ __global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __res
   if (threadIdx.x == 0) bad = 0;
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
   constexpr int ngrp = BLOCK / G;
-  for (int c = grp; c < n; c += ngrp) {
-    const T* col = W + (int64_t)c * n;
-    T s2 = 0;
-    for (int r = lane; r < n; r += G) s2 = fma(col[r], col[r], s2);
-    const T nc = sqrt(group_sum<G>(s2));
-    double lam = (double)nc - (double)sigma;
-    if (sizeof(T) == 8) {
-      // v = w/|w| by division, so an unrotated column is an exact unit vector
-      double q = 0, vv = 0;
-      for (int r = lane; r < n; r += G) {
-        const double* hrow = V + (int64_t)r * n;
-        double hv = 0;
-        for (int t = 0; t < n; ++t) hv = fma(hrow[t], (double)col[t] / (double)nc, hv);
-        const double vr = (double)col[r] / (double)nc;
-        hv = fma(g.e0[r % N], vr, hv);
-        q = fma(vr, hv, q);
-        vv = fma(vr, vr, vv);
+  if constexpr (sizeof(T) == 8) {
+    // FP64: normalise the columns in place (v = w/|w| by division, so an
+    // unrotated column is an exact unit vector); the Rayleigh quotients, the
+    // sort and the outputs follow in launch_rayleigh_f64
+    T* Wm = reinterpret_cast<T*>(work + it.w_off);
+    for (int c = grp; c < n; c += ngrp) {
+      T* col = Wm + (int64_t)c * n;
+      T s2 = 0;
+      for (int r = lane; r < n; r += G) s2 = fma(col[r], col[r], s2);
+      const T nc = sqrt(group_sum<G>(s2));
+      if (!(nc > 0.0) || !isfinite(nc)) {
+        if (lane == 0) bad = 1;
+        continue;
       }
-      q = group_sum<G>(q);
-      vv = group_sum<G>(vv);
-      lam = q / vv;
+      for (int r = lane; r < n; r += G) col[r] = col[r] / nc;
     }
-    if (lane == 0) {
-      nrm[c] = (double)nc;
-      rq[c] = lam;
+    __syncthreads();
+  } else {
+    for (int c = grp; c < n; c += ngrp) {
+      const T* col = W + (int64_t)c * n;
+      T s2 = 0;
+      for (int r = lane; r < n; r += G) s2 = fma(col[r], col[r], s2);
+      const T nc = sqrt(group_sum<G>(s2));
+      if (lane == 0) {
+        nrm[c] = (double)nc;
+        rq[c] = (double)nc - (double)sigma;
+      }
     }
-  }
-  __syncthreads();
-  for (int c = grp; c < n; c += ngrp) {
-    const double lc = rq[c];
-    double cnt = 0;
-    for (int i = lane; i < n; i += G) {
-      const double li = rq[i];
-      cnt += (li < lc || (li == lc && i < c)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int c = grp; c < n; c += ngrp) {
+      const double lc = rq[c];
+      double cnt = 0;
+      for (int i = lane; i < n; i += G) {
+        const double li = rq[i];
+        cnt += (li < lc || (li == lc && i < c)) ? 1.0 : 0.0;
+      }
+      cnt = group_sum<G>(cnt);
+      if (lane == 0) rank_of[c] = (int)cnt;
     }
-    cnt = group_sum<G>(cnt);
-    if (lane == 0) rank_of[c] = (int)cnt;
-  }
-  __syncthreads();
-  for (int c = grp; c < n; c += ngrp) {
-    const double nc = nrm[c];
-    if (!(nc > 0.0) || !isfinite(nc) || !isfinite(rq[c])) {
-      if (lane == 0) bad = 1;
-      continue;
-    }
-    const int rank = rank_of[c];
-    const T* col = W + (int64_t)c * n;
-    if (sizeof(T) == 8) {
-      double* X = evec + it.v_off;
-      for (int r = lane; r < n; r += G) X[(int64_t)r * n + rank] = (double)col[r] / nc;
-    } else {
+    __syncthreads();
+    for (int c = grp; c < n; c += ngrp) {
+      const double nc = nrm[c];
+      if (!(nc > 0.0) || !isfinite(nc)) {
+        if (lane == 0) bad = 1;
+        continue;
+      }
+      const int rank = rank_of[c];
+      const T* col = W + (int64_t)c * n;
       float* X = x32 + it.v_off;
       for (int r = lane; r < n; r += G) X[(int64_t)r * n + rank] = (float)col[r] / (float)nc;
     }
+    __syncthreads();
+    double* ev = eval + it.e_off;
+    for (int c = threadIdx.x; c < n; c += BLOCK) ev[rank_of[c]] = rq[c];
   }
-  __syncthreads();
-  double* ev = eval + it.e_off;
-  for (int c = threadIdx.x; c < n; c += BLOCK) ev[rank_of[c]] = rq[c];
   if (threadIdx.x == 0)
     status[item] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
 }
@@ -368,6 +363,10 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
   }
   hipLaunchKernelGGL((gjac_finish_kernel<T, 1024, 16>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work,
                      evec, x32, eval, status, max_sweeps, tol);
+  if (sizeof(T) == 8) {
+    if (sel) return hipErrorInvalidValue;  // the FP64 path runs on whole batches
+    return launch_rayleigh_f64(items, n_sel, max_n, grids, v64, work, evec, eval, status, s);
+  }
   return hipGetLastError();
 }
 

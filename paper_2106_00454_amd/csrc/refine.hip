@@ -849,6 +849,84 @@ __global__ __launch_bounds__(kBlock) void refine_finish_kernel(const ItemDev* __
   if (threadIdx.x == 0 && s_bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
+// ------------------------------------------------- FP64 Jacobi epilogue
+// Y = H X for the normalised columns of the device-memory FP64 Jacobi (column
+// c of X contiguous at ws.P1 + c n, as the iteration stores W); Y column-major
+// in ws.Y.
+__global__ __launch_bounds__(kBlock, 3) void rq_hx_kernel(const ItemDev* __restrict__ items, int n_items,
+                                                         const GridDev* __restrict__ grids,
+                                                         const double* __restrict__ v64, double* work, int tiles) {
+  WPCD_LDS_TILES(1);
+  int item, tile;
+  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
+  const ItemDev it = items[item];
+  const int n = it.n;
+  const int nt = (n + kTM - 1) / kTM;
+  if (tile >= nt * nt) return;
+  const int tm = tile / nt, tc = tile % nt;
+  const GridDev g = grids[it.grid];
+  const WS ws(work, it);
+  const double* X = ws.P1;
+  d4 acc[2][2];
+  // B(k, j) = component k of column j = X[j n + k]
+  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(v64 + it.v_off, n, n), row_view<double>(X, n, n), acc);
+  double* Y = ws.Y;
+  const int N = it.N;
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+    Y[(int64_t)c * n + r] = fma(g.e0[r % N], X[(int64_t)c * n + r], v);  // + H0 X
+  });
+}
+
+// lambda_c = x_c . (H x_c) / x_c . x_c, ranked ascending (ties by index);
+// eval[rank] = lambda, evec[r][rank] = x_c[r].  One work-group per item.
+__global__ __launch_bounds__(kBlock) void rq_sort_kernel(const ItemDev* __restrict__ items, const double* work,
+                                                        double* __restrict__ evec, double* __restrict__ eval,
+                                                        int32_t* __restrict__ status) {
+  __shared__ double lam[kMaxN];
+  __shared__ int rank[kMaxN];
+  __shared__ int s_bad;
+  const ItemDev it = items[blockIdx.x];
+  const int n = it.n;
+  const double* X = work + it.w_off;
+  const double* Y = X + (int64_t)n * n;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < n; c += kBlock / 64) {
+    double q = 0.0, vv = 0.0;
+    for (int r = lane; r < n; r += 64) {
+      const double x = X[(int64_t)c * n + r];
+      q = fma(x, Y[(int64_t)c * n + r], q);
+      vv = fma(x, x, vv);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      q += __shfl_xor(q, off, 64);
+      vv += __shfl_xor(vv, off, 64);
+    }
+    if (lane == 0) {
+      const double l = q / vv;
+      lam[c] = l;
+      if (!isfinite(l)) s_bad = 1;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += kBlock) {
+    const double lc = lam[c];
+    int k = 0;
+    for (int i = 0; i < n; ++i) k += (lam[i] < lc || (lam[i] == lc && i < c)) ? 1 : 0;
+    rank[c] = k;
+  }
+  __syncthreads();
+  double* E = evec + it.v_off;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kBlock) {
+    const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
+    E[(int64_t)r * n + rank[c]] = X[e];
+  }
+  for (int c = threadIdx.x; c < n; c += kBlock) eval[it.e_off + rank[c]] = lam[c];
+  if (threadIdx.x == 0 && s_bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
+}
+
 }  // namespace
 
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
@@ -900,6 +978,21 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
   }
   hipLaunchKernelGGL(refine_finish_kernel, dim3(n_items), dim3(kBlock), 0, s, items, evec, cur_ws, work, eval,
                      status);
+  return hipGetLastError();
+}
+
+}  // namespace wpcd
+
+namespace wpcd {
+
+hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
+                               const double* v64, double* work, double* evec, double* eval, int32_t* status,
+                               hipStream_t s) {
+  if (max_n > kMaxN) return hipErrorInvalidValue;
+  const int nt = (max_n + kTM - 1) / kTM;
+  hipLaunchKernelGGL(rq_hx_kernel, dim3(xcd_grid(nt * nt, n_items)), dim3(kBlock), 0, s, items, n_items, grids, v64,
+                     work, nt * nt);
+  hipLaunchKernelGGL(rq_sort_kernel, dim3(n_items), dim3(kBlock), 0, s, items, work, evec, eval, status);
   return hipGetLastError();
 }
 
