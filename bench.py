@@ -173,7 +173,8 @@ def run_sweep(args) -> dict:
     """J <= 6 batched sweep: args.samples x 20 channels, N_WP from {50, 100, 150}, affine bases."""
     import paper_2106_00454_amd as wp
     from synth import sweep
-    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop)
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
+                     jacobi_start=args.jacobi_start)
     t0 = time.perf_counter()
     _, bases = _register_bases(ctx, sweep.TermCache(), sweep.N_WP_CHOICES, range(len(sweep.CHANNELS)))
     log(f"sweep: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
@@ -193,7 +194,8 @@ def run_large(args) -> dict:
     """Large mesh: 64 samples x 6 coupled channels (J = 1..6) at N_WP = args.large_nwp."""
     import paper_2106_00454_amd as wp
     from synth import sweep
-    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop)
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
+                     jacobi_start=args.jacobi_start)
     coupled = [c for c in range(len(sweep.CHANNELS)) if sweep.CHANNELS[c][1] == 2]
     N = args.large_nwp
     t0 = time.perf_counter()
@@ -215,7 +217,8 @@ def run_serve(args) -> dict:
     """Poisson arrivals of parameter-vector requests with random channel subsets."""
     import paper_2106_00454_amd as wp
     from synth import sweep
-    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop)
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
+                     jacobi_start=args.jacobi_start)
     n_wps = (50, 100, 150, 200)
     t0 = time.perf_counter()
     _, bases = _register_bases(ctx, sweep.TermCache(), n_wps, range(len(sweep.CHANNELS)))
@@ -290,6 +293,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jacobi-block", type=int, default=0, help="LDS Jacobi variant (wpcd_config.jacobi_block; 0: default)")
+    ap.add_argument("--jacobi-start", type=int, default=0, help="LDS Jacobi start (wpcd_config.jacobi_start; 0: warm, 1: cold)")
     ap.add_argument("--jacobi-stop", type=float, default=0.0, help="FP32 Jacobi stopping threshold (wpcd_config.jacobi_stop_f32; 0: default)")
     ap.add_argument("--workload", choices=("coupled", "sweep", "large", "serve"), default="coupled",
                     help="coupled: the headline line; sweep / large / serve: the other workloads")
@@ -315,7 +319,8 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop)
+    ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
+                     jacobi_start=args.jacobi_start)
     k = configs.grid("coupled_yukawa")
     g = ctx.grid(k, configs.N_GAUSS)
     B = args.batch

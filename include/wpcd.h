@@ -111,6 +111,18 @@ typedef struct {
                             lie in (0, 1); 0 = default max(3e-5, 8 x
                             jacobi_tol_f32).  The FP64 path always uses
                             8 x jacobi_tol_f64                               */
+  int32_t jacobi_start;  /* start of the LDS FP32 Jacobi in wpcd_eigh: 0
+                            (default) warm: items of a batch that share grid,
+                            channel count, J and basis form a group; the
+                            first ones (up to one per compute unit and size
+                            class, each group's first among them) start from
+                            the columns of B in descending norm order, the
+                            others from B Q0 with Q0 the eigenvectors of
+                            their group's first item (fewer sweeps when the
+                            potentials are alike); 1 cold: every item starts
+                            from B.  Results agree within the refinement's
+                            accuracy either way.                             */
+  int32_t reserved;      /* 0 */
 } wpcd_config;
 
 /* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */

@@ -6,9 +6,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "handles.h"
@@ -114,7 +116,7 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   WPCD_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   if (hip_device < 0 || hip_device >= ndev)
     return fail(WPCD_ERR_INVALID, "wpcd_create: device %d out of range (%d devices)", hip_device, ndev);
-  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0, 0.0};
+  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0, 0.0, 0, 0};
   if (cfg) c = *cfg;
   if (c.refine_close_log10 == 0) c.refine_close_log10 = 3;
   // default stop: one sweep after the largest rotation fell below 3e-5 the
@@ -127,6 +129,7 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
   if (!(c.jacobi_stop_f32 > 0) || !(c.jacobi_stop_f32 < 1))
     return fail(WPCD_ERR_INVALID, "jacobi_stop_f32 must be in (0, 1) (0 = default)");
+  if (c.jacobi_start != 0 && c.jacobi_start != 1) return fail(WPCD_ERR_INVALID, "jacobi_start must be 0 or 1");
   if (c.jacobi_block < 0 || c.jacobi_block > 4)
     return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2, 3 or 4");
   if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
@@ -239,6 +242,8 @@ void wpcd_batch_destroy(wpcd_batch b) {
   hipFree(b->d_cl);
   hipFree(b->d_lam);
   hipFree(b->d_class);
+  hipFree(b->d_jlist);
+  hipFree(b->d_ref);
   hipFree(b->d_bases);
   delete b;
 }
@@ -341,6 +346,52 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     for (int c = 0; c < kNumClasses; ++c) fill[c] = b->class_ptr[c];
     for (int i = 0; i < n_items; ++i) cls[fill[size_class(b->h_items[i].n)]++] = i;
   }
+  // warm-start lists of the LDS classes: per class, each group's first item
+  // and then further items up to one per compute unit start cold; the rest
+  // of a group starts from its first item's eigenvectors
+  constexpr int L = wpcd_batch_s::kLdsClasses;
+  std::vector<int32_t> ref(n_items, -1);
+  std::vector<int32_t> seg[2 * L + 1];
+  {
+    int n_cu = 256;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n_cu < 1)
+      n_cu = 256;
+    const bool warm = ctx->cfg.jacobi_start == 0;
+    for (int c = 0; c < L; ++c) {
+      std::map<std::tuple<int, int, int, int>, int> first;  // group key -> its first (reference) item
+      std::vector<int32_t> rest;
+      for (int q = b->class_ptr[c]; q < b->class_ptr[c + 1]; ++q) {
+        const int i = cls[q];
+        const ItemDev& d = b->h_items[i];
+        const auto key = std::make_tuple(d.grid, d.nch, d.J, d.basis);
+        if (!warm || first.emplace(key, i).second)
+          seg[c].push_back(i);
+        else
+          rest.push_back(i);
+      }
+      for (int32_t i : rest) {
+        if ((int)seg[c].size() < n_cu) {
+          seg[c].push_back(i);
+        } else {
+          const ItemDev& d = b->h_items[i];
+          ref[i] = first[std::make_tuple(d.grid, d.nch, d.J, d.basis)];
+          seg[L + c].push_back(i);
+        }
+      }
+    }
+    std::vector<char> is_ref(n_items, 0);
+    for (int i = 0; i < n_items; ++i)
+      if (ref[i] >= 0 && !is_ref[ref[i]]) {
+        is_ref[ref[i]] = 1;
+        seg[2 * L].push_back(ref[i]);
+      }
+  }
+  std::vector<int32_t> jlist;
+  for (int t = 0; t <= 2 * L; ++t) {
+    b->jl_ptr[t] = (int)jlist.size();
+    jlist.insert(jlist.end(), seg[t].begin(), seg[t].end());
+  }
+  b->jl_ptr[2 * L + 1] = (int)jlist.size();
   std::vector<GridDev> gd(ctx->grids.size());
   for (size_t i = 0; i < gd.size(); ++i) gd[i] = ctx->grids[i].dev;
   hipError_t e = hipSuccess;
@@ -356,6 +407,8 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   alloc((void**)&b->d_cl, sizeof(int32_t) * b->eval_elems);
   alloc((void**)&b->d_lam, sizeof(double) * b->eval_elems);
   alloc((void**)&b->d_class, sizeof(int32_t) * n_items);
+  alloc((void**)&b->d_jlist, sizeof(int32_t) * jlist.size());
+  alloc((void**)&b->d_ref, sizeof(int32_t) * n_items);
   std::vector<BasisDev> bd(ctx->bases.size());
   for (size_t i = 0; i < bd.size(); ++i) bd[i] = BasisDev{ctx->bases[i].dbuf, ctx->bases[i].n, ctx->bases[i].n_terms};
   alloc((void**)&b->d_bases, sizeof(BasisDev) * bd.size());
@@ -368,6 +421,9 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   if (e == hipSuccess)
     e = hipMemcpy(b->d_sample_items, sitems.data(), sizeof(int32_t) * sitems.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_class, cls.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !jlist.empty())
+    e = hipMemcpy(b->d_jlist, jlist.data(), sizeof(int32_t) * jlist.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_ref, ref.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     wpcd_batch_destroy(b);
     return hip_fail(e, "wpcd_batch_create");
@@ -503,20 +559,36 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream,
                    [&] {
                      hipError_t e = hipSuccess;
-                     for (int k = 0; k < kNumClasses && e == hipSuccess; ++k) {
-                       const int n_sel = b->class_ptr[k + 1] - b->class_ptr[k];
-                       const int32_t* sel = b->d_class + b->class_ptr[k];
-                       if (n_sel == 0) continue;
-                       if (k < kNumClasses - 1)
-                         e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
-                                                   b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
-                                                   (float)c.jacobi_stop_f32, c.jacobi_block,
-                                                   b->ctx->profiling ? b->ctx->d_counters : nullptr, stream);
-                       else
-                         e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
-                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
-                                                  c.jacobi_tol_f32, c.jacobi_stop_f32, stream);
+                     constexpr int L = wpcd_batch_s::kLdsClasses;
+                     unsigned long long* cnt = b->ctx->profiling ? b->ctx->d_counters : nullptr;
+                     auto lds = [&](int seg, int k, const int32_t* ref) {
+                       const int n_sel = b->jl_ptr[seg + 1] - b->jl_ptr[seg];
+                       if (n_sel == 0 || e != hipSuccess) return;
+                       e = launch_jacobi_f32_lds(b->d_items, b->d_jlist + b->jl_ptr[seg], n_sel, b->class_maxn[k],
+                                                 b->d_grids, v64, b->d_x32, eval, status, c.max_sweeps,
+                                                 (float)c.jacobi_tol_f32, (float)c.jacobi_stop_f32, c.jacobi_block,
+                                                 ref, b->d_work, cnt, stream);
+                     };
+                     // cold starts (each group's reference among them), then the
+                     // warm starts from the references' eigenvectors
+                     for (int k = 0; k < L; ++k) lds(k, k, nullptr);
+                     const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
+                     if (e == hipSuccess && n_warm > 0) {
+                       int wmax = 0;
+                       for (int k = 0; k < L; ++k)
+                         if (b->jl_ptr[L + k + 1] > b->jl_ptr[L + k]) wmax = b->class_maxn[k];
+                       e = launch_jacobi_warm_prep(b->d_items, b->d_jlist + b->jl_ptr[2 * L],
+                                                   b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L], b->d_jlist + b->jl_ptr[L],
+                                                   n_warm, b->d_ref, wmax, b->d_grids, v64, b->d_x32, b->d_work,
+                                                   stream);
                      }
+                     for (int k = 0; k < L; ++k) lds(L + k, k, b->d_ref);
+                     const int k = kNumClasses - 1;
+                     const int n_sel = b->class_ptr[k + 1] - b->class_ptr[k];
+                     if (e == hipSuccess && n_sel > 0)
+                       e = launch_jacobi_global(1, b->d_items, b->d_class + b->class_ptr[k], n_sel, b->class_maxn[k],
+                                                b->d_grids, v64, b->d_work, evec, b->d_x32, eval, status,
+                                                c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32, stream);
                      return e;
                    }),
              "wpcd_eigh: FP32 Jacobi launch");

@@ -74,7 +74,15 @@ hipError_t launch_project_affine(const ItemDev* items, int n_items, int max_n, c
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
                                  int32_t* status, int max_sweeps, float tol, float stop, int block_cols,
-                                 unsigned long long* counters, hipStream_t s);
+                                 const int32_t* ref, const double* work, unsigned long long* counters,
+                                 hipStream_t s);
+// Warm start of the LDS Jacobi (items with a reference, ref[item] >= 0):
+// writes each reference's eigenvectors, columns in descending eigenvalue
+// order, column-major as floats into the reference's work-space, then
+// H Q0 of every warm item, column-major FP32, into the item's x32.
+hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, int n_refs, const int32_t* warm,
+                                   int n_warm, const int32_t* ref, int max_n, const GridDev* grids,
+                                   const double* v64, float* x32, double* work, hipStream_t s);
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,

@@ -22,7 +22,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
                                                                const double* __restrict__ v64,
                                                                float* __restrict__ x32, double* __restrict__ eval,
                                                                int32_t* __restrict__ status, int max_sweeps,
-                                                               float tol, float stop, unsigned long long* counters) {
+                                                               float tol, float stop, const int32_t* __restrict__ ref,
+                                                               const double* __restrict__ work,
+                                                               unsigned long long* counters) {
   extern __shared__ float W[];
   __shared__ int s_nrot;
   __shared__ float nrm[kMaxLdsN];
@@ -79,6 +81,24 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
     lo = block_reduce<BLOCK>(lo, scratch, MinOp<float>());
     hi = block_reduce<BLOCK>(hi, scratch, MaxOp<float>());
     sigma = (lo < 0.f ? -lo : 0.f) + 0.05f * (hi - lo);
+  }
+  const int rid = (kSorted && ref) ? ref[item] : -1;
+  if (rid >= 0) {
+    // warm start from the reference item's eigenvectors Q0 (columns in
+    // descending eigenvalue order, stored column-major as floats in the
+    // reference's work-space): W = B Q0 = H Q0 + sigma Q0, with H Q0 formed
+    // by the batched product into this item's x32 (column-major)
+    const float* Y0 = x32 + it.v_off;
+    const float* Q0 = reinterpret_cast<const float*>(work + items[rid].w_off);
+    const int nr = n * rows;
+    for (int e = threadIdx.x; e < nr; e += BLOCK) {
+      const int j = e / rows, r = e - j * rows;
+      W[j * ld + r] = r < n ? fmaf(sigma, Q0[j * n + r], Y0[j * n + r]) : 0.f;
+    }
+    if (B == 7 && (n & 1))  // the zero column completing the last block of 2
+      for (int r = threadIdx.x; r < rows; r += BLOCK) W[n * ld + r] = 0.f;
+    __syncthreads();
+  } else if constexpr (kSorted) {
     // |B e_c|^2 = |H e_c|^2 + 2 sigma H_cc + sigma^2; rank by descending norm
     for (int c = threadIdx.x; c < n; c += BLOCK) diag[c] = nrm[c] + sigma * (2.f * diag[c] + sigma);
     __syncthreads();
@@ -190,7 +210,8 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
 hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                  const GridDev* grids, const double* v64, float* x32, double* eval,
                                  int32_t* status, int max_sweeps, float tol, float stop, int block_cols,
-                                 unsigned long long* counters, hipStream_t s) {
+                                 const int32_t* ref, const double* work, unsigned long long* counters,
+                                 hipStream_t s) {
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
@@ -203,7 +224,7 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_sel), dim3(block), lds, s, items, sel, grids, v64, x32, eval, status,
-                       max_sweeps, tol, stop, counters);
+                       max_sweeps, tol, stop, ref, work, counters);
     return hipGetLastError();
   };
   // configuration value -> kernel variant: 0 (default) blocks of 2 columns

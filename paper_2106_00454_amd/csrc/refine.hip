@@ -927,6 +927,52 @@ __global__ __launch_bounds__(kBlock) void rq_sort_kernel(const ItemDev* __restri
   if (threadIdx.x == 0 && s_bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
+// ------------------------------------------------ LDS Jacobi warm start
+// Reference eigenvectors (x32: row-major, ascending) -> Q0 with columns in
+// descending eigenvalue order, column-major floats at the reference's
+// work-space (free until the refinement).  One work-group per reference.
+__global__ __launch_bounds__(kBlock) void warm_q0_kernel(const ItemDev* __restrict__ items,
+                                                        const int32_t* __restrict__ refs,
+                                                        const float* __restrict__ x32, double* work) {
+  const ItemDev it = items[refs[blockIdx.x]];
+  const int n = it.n;
+  const float* X = x32 + it.v_off;
+  float* Q0 = reinterpret_cast<float*>(work + it.w_off);
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kBlock) {
+    const int j = (int)(e / n), r = (int)(e - (int64_t)j * n);
+    Q0[e] = X[(int64_t)r * n + (n - 1 - j)];
+  }
+}
+
+// H Q0 for every warm item (its reference's Q0), column-major FP32 into the
+// item's x32, where the Jacobi kernel reads it as the start of W.
+__global__ __launch_bounds__(kBlock, 3) void warm_y_kernel(const ItemDev* __restrict__ items,
+                                                          const int32_t* __restrict__ warm, int n_warm,
+                                                          const int32_t* __restrict__ ref,
+                                                          const GridDev* __restrict__ grids,
+                                                          const double* __restrict__ v64, float* x32,
+                                                          const double* work, int tiles) {
+  WPCD_LDS_TILES(1);
+  int w, tile;
+  if (!xcd_item_tile(tiles, n_warm, w, tile)) return;
+  const int item = warm[w];
+  const ItemDev it = items[item];
+  const int n = it.n;
+  const int nt = (n + kTM - 1) / kTM;
+  if (tile >= nt * nt) return;
+  const int tm = tile / nt, tc = tile % nt;
+  const GridDev g = grids[it.grid];
+  const float* Q0 = reinterpret_cast<const float*>(work + items[ref[item]].w_off);
+  d4 acc[2][2];
+  // B(k, j) = component k of column j = Q0[j n + k]
+  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(v64 + it.v_off, n, n), row_view<float>(Q0, n, n), acc);
+  float* Y0 = x32 + it.v_off;
+  const int N = it.N;
+  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+    Y0[(int64_t)c * n + r] = (float)fma(g.e0[r % N], (double)Q0[(int64_t)c * n + r], v);  // + H0 Q0
+  });
+}
+
 }  // namespace
 
 hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
@@ -993,6 +1039,22 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
   hipLaunchKernelGGL(rq_hx_kernel, dim3(xcd_grid(nt * nt, n_items)), dim3(kBlock), 0, s, items, n_items, grids, v64,
                      work, nt * nt);
   hipLaunchKernelGGL(rq_sort_kernel, dim3(n_items), dim3(kBlock), 0, s, items, work, evec, eval, status);
+  return hipGetLastError();
+}
+
+}  // namespace wpcd
+
+namespace wpcd {
+
+hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, int n_refs, const int32_t* warm,
+                                   int n_warm, const int32_t* ref, int max_n, const GridDev* grids,
+                                   const double* v64, float* x32, double* work, hipStream_t s) {
+  if (max_n > kMaxN) return hipErrorInvalidValue;
+  if (n_refs == 0 || n_warm == 0) return hipSuccess;
+  hipLaunchKernelGGL(warm_q0_kernel, dim3(n_refs), dim3(kBlock), 0, s, items, refs, x32, work);
+  const int nt = (max_n + kTM - 1) / kTM;
+  hipLaunchKernelGGL(warm_y_kernel, dim3(xcd_grid(nt * nt, n_warm)), dim3(kBlock), 0, s, items, warm, n_warm, ref,
+                     grids, v64, x32, work, nt * nt);
   return hipGetLastError();
 }
 

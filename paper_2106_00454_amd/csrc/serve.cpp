@@ -291,7 +291,7 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
     if (k < kNumClasses - 1)
       e = launch_jacobi_f32_lds(d_items, d_cls + class_ptr[k], n_sel, class_maxn[k], d_grids, d_v64, d_x32, d_eval,
                                 d_est, c.max_sweeps, (float)c.jacobi_tol_f32, (float)c.jacobi_stop_f32, c.jacobi_block,
-                                nullptr, s.stream);
+                                nullptr, d_work, nullptr, s.stream);
     else
       e = launch_jacobi_global(1, d_items, d_cls + class_ptr[k], n_sel, class_maxn[k], d_grids, d_v64, d_work,
                                d_evec, d_x32, d_eval, d_est, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32,

@@ -191,3 +191,33 @@ def test_lds_jacobi_variants_match_oracle(variant):
         sig_ref = oo.sigma_tot([(J, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
         check_item(f"jacobi variant={variant} item={i} n={it['v'].shape[0]}", it, ref, k, wp.MIXED, J, sig_ref,
                    host["sigma"][i])
+
+
+# ------------------------------------------- warm-started LDS Jacobi
+def test_warm_started_jacobi_matches_oracle_and_cold_start():
+    # more items of one channel than compute units: the first 256 (one per
+    # CU) start cold, the rest warm from the first item's eigenvectors
+    # (wpcd_config.jacobi_start = 0, the default); the same batch solved with
+    # cold starts only (jacobi_start = 1) must agree with it and the oracle
+    k = configs.grid("yamaguchi_s")
+    n_items = 300
+    lams = [configs.yamaguchi_lambda(s) for s in range(n_items)]
+    res = {}
+    for start in (0, 1):
+        c = wp.Context(0, jacobi_start=start)
+        g = c.grid(k, configs.N_GAUSS)
+        mats = [potentials.yamaguchi(g.nodes, g.nodes, lam, configs.YAMAGUCHI_BETA) for lam in lams]
+        b, host = run_items(c, [(g, 1, 0, s) for s in range(n_items)], mats, wp.MIXED)
+        assert (host["eig_status"] > 0).all() and (host["t_status"] == 0).all()
+        res[start] = (b, host)
+    xo, _ = ow.gauss_nodes(k, configs.N_GAUSS)
+    _, kbar, _ = ow.bins(k)
+    bw, hw = res[0]
+    bc, hc = res[1]
+    assert dmod180(hw["delta"], hc["delta"]).max() <= 1e-6
+    assert np.abs(hw["sigma"] - hc["sigma"]).max() <= 1e-6
+    for s in (0, 1, 255, 256, 257, 280, 299):
+        ref = oracle_item(k, potentials.yamaguchi(xo, xo, lams[s], configs.YAMAGUCHI_BETA), 1)
+        it = item_view(bw, hw, s)
+        sig_ref = oo.sigma_tot([(0, ref["delta"], None)], kbar, TLAB, k[-1])
+        check_item(f"warm start s={s}", it, ref, k, wp.MIXED, 0, sig_ref, hw["sigma"][s])
