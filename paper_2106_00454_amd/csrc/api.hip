@@ -346,10 +346,11 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     for (int c = 0; c < kNumClasses; ++c) fill[c] = b->class_ptr[c];
     for (int i = 0; i < n_items; ++i) cls[fill[size_class(b->h_items[i].n)]++] = i;
   }
-  // warm-start lists of the LDS classes: per class, each group's first item
-  // and then further items up to one per compute unit start cold; the rest
-  // of a group starts from its first item's eigenvectors
-  constexpr int L = wpcd_batch_s::kLdsClasses;
+  // warm-start lists: per size class, each group's first item starts cold,
+  // and in the LDS classes further items up to one per compute unit do too
+  // (they would otherwise wait for the references); the rest of a group
+  // starts from its first item's eigenvectors
+  constexpr int L = wpcd_batch_s::kC;
   std::vector<int32_t> ref(n_items, -1);
   std::vector<int32_t> seg[2 * L + 1];
   {
@@ -358,6 +359,7 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
       n_cu = 256;
     const bool warm = ctx->cfg.jacobi_start == 0;
     for (int c = 0; c < L; ++c) {
+      const int cold_cap = c < L - 1 ? n_cu : 0;
       std::map<std::tuple<int, int, int, int>, int> first;  // group key -> its first (reference) item
       std::vector<int32_t> rest;
       for (int q = b->class_ptr[c]; q < b->class_ptr[c + 1]; ++q) {
@@ -370,7 +372,7 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
           rest.push_back(i);
       }
       for (int32_t i : rest) {
-        if ((int)seg[c].size() < n_cu) {
+        if ((int)seg[c].size() < cold_cap) {
           seg[c].push_back(i);
         } else {
           const ItemDev& d = b->h_items[i];
@@ -559,19 +561,25 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream,
                    [&] {
                      hipError_t e = hipSuccess;
-                     constexpr int L = wpcd_batch_s::kLdsClasses;
+                     constexpr int L = wpcd_batch_s::kC;
                      unsigned long long* cnt = b->ctx->profiling ? b->ctx->d_counters : nullptr;
-                     auto lds = [&](int seg, int k, const int32_t* ref) {
+                     auto solve = [&](int seg, int k, const int32_t* ref) {
                        const int n_sel = b->jl_ptr[seg + 1] - b->jl_ptr[seg];
                        if (n_sel == 0 || e != hipSuccess) return;
-                       e = launch_jacobi_f32_lds(b->d_items, b->d_jlist + b->jl_ptr[seg], n_sel, b->class_maxn[k],
-                                                 b->d_grids, v64, b->d_x32, eval, status, c.max_sweeps,
-                                                 (float)c.jacobi_tol_f32, (float)c.jacobi_stop_f32, c.jacobi_block,
-                                                 ref, b->d_work, cnt, stream);
+                       const int32_t* sel = b->d_jlist + b->jl_ptr[seg];
+                       if (k < L - 1)
+                         e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
+                                                   b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
+                                                   (float)c.jacobi_stop_f32, c.jacobi_block, ref, b->d_work, cnt,
+                                                   stream);
+                       else
+                         e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
+                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
+                                                  c.jacobi_tol_f32, c.jacobi_stop_f32, ref, stream);
                      };
                      // cold starts (each group's reference among them), then the
                      // warm starts from the references' eigenvectors
-                     for (int k = 0; k < L; ++k) lds(k, k, nullptr);
+                     for (int k = 0; k < L; ++k) solve(k, k, nullptr);
                      const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
                      if (e == hipSuccess && n_warm > 0) {
                        int wmax = 0;
@@ -582,13 +590,7 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                                                    n_warm, b->d_ref, wmax, b->d_grids, v64, b->d_x32, b->d_work,
                                                    stream);
                      }
-                     for (int k = 0; k < L; ++k) lds(L + k, k, b->d_ref);
-                     const int k = kNumClasses - 1;
-                     const int n_sel = b->class_ptr[k + 1] - b->class_ptr[k];
-                     if (e == hipSuccess && n_sel > 0)
-                       e = launch_jacobi_global(1, b->d_items, b->d_class + b->class_ptr[k], n_sel, b->class_maxn[k],
-                                                b->d_grids, v64, b->d_work, evec, b->d_x32, eval, status,
-                                                c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32, stream);
+                     for (int k = 0; k < L; ++k) solve(L + k, k, b->d_ref);
                      return e;
                    }),
              "wpcd_eigh: FP32 Jacobi launch");
@@ -604,7 +606,7 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                    [&] {
                      return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids, v64,
                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
-                                                 c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, stream);
+                                                 c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, nullptr, stream);
                    }),
              "wpcd_eigh: FP64 Jacobi launch");
   }

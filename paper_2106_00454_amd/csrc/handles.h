@@ -63,14 +63,13 @@ struct wpcd_batch_s {
   int32_t* d_class = nullptr;
   int class_ptr[wpcd::kNumClasses + 1] = {0};
   int class_maxn[wpcd::kNumClasses] = {0};
-  // warm start of the LDS classes (wpcd_config.jacobi_start): d_jlist holds
-  // the segments cold_0 .. cold_{L-1}, warm_0 .. warm_{L-1}, refs (L = the
-  // kNumClasses - 1 LDS classes), segment t at [jl_ptr[t], jl_ptr[t + 1]);
-  // the warm segments are contiguous; d_ref gives each warm item its
-  // reference (-1 otherwise)
-  static constexpr int kLdsClasses = wpcd::kNumClasses - 1;
+  // warm start of the FP32 Jacobi (wpcd_config.jacobi_start): d_jlist holds
+  // the segments cold_0 .. cold_{C-1}, warm_0 .. warm_{C-1}, refs (C size
+  // classes), segment t at [jl_ptr[t], jl_ptr[t + 1]); the warm segments are
+  // contiguous; d_ref gives each warm item its reference (-1 otherwise)
+  static constexpr int kC = wpcd::kNumClasses;
   int32_t* d_jlist = nullptr;
   int32_t* d_ref = nullptr;
-  int jl_ptr[2 * kLdsClasses + 2] = {0};
+  int jl_ptr[2 * kC + 2] = {0};
 };
 

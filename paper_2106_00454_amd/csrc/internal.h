@@ -86,7 +86,7 @@ hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, in
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,
-                                hipStream_t s);
+                                const int32_t* ref, hipStream_t s);
 // FP64 device-memory Jacobi epilogue: Rayleigh quotients x^T H x of the
 // normalised columns it left in the work-space (MFMA product H X), sort by
 // them, write eval and the row-major evec of every item of the batch.

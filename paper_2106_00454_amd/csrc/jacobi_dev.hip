@@ -49,7 +49,8 @@ __global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restr
                                                           const int32_t* __restrict__ sel,
                                                           const GridDev* __restrict__ grids,
                                                           const double* __restrict__ v64, double* work,
-                                                          float stop) {
+                                                          float stop, const int32_t* __restrict__ ref,
+                                                          const float* __restrict__ x32) {
   __shared__ T scratch[BLOCK / 64];
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
@@ -90,6 +91,23 @@ __global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restr
   lo = block_reduce<BLOCK>(lo, scratch, MinOp<T>());
   hi = block_reduce<BLOCK>(hi, scratch, MaxOp<T>());
   const T sigma = (lo < T(0) ? -lo : T(0)) + T(0.05) * (hi - lo);
+  const int rid = ref ? ref[item] : -1;
+  if (rid >= 0) {
+    // warm start: W = B Q0 = H Q0 + sigma Q0, with H Q0 (column-major FP32 in
+    // this item's x32) and Q0 (the reference's eigenvectors, descending,
+    // column-major floats in the reference's work-space) prepared by
+    // launch_jacobi_warm_prep
+    const float* Y0 = x32 + it.v_off;
+    const float* Q0 = reinterpret_cast<const float*>(work + items[rid].w_off);
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t e = threadIdx.x; e < nn; e += BLOCK) W[e] = (T)fmaf((float)sigma, Q0[e], Y0[e]);
+    for (int i = threadIdx.x; i < 64; i += BLOCK) st->rotmax[i] = 0;
+    if (threadIdx.x == 0) {
+      st->sigma = sigma;
+      st->stop = stop;
+    }
+    return;
+  }
   for (int c = threadIdx.x; c < n; c += BLOCK) key[c] = key[c] + sigma * (T(2) * dg[c] + sigma);
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += BLOCK) {
@@ -340,7 +358,7 @@ __global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __res
 template <typename T, int BW, int G, int RMAX>
 hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max_n, const GridDev* grids,
                     const double* v64, double* work, double* evec, float* x32, double* eval, int32_t* status,
-                    int max_sweeps, T tol, float stop, hipStream_t s) {
+                    int max_sweeps, T tol, float stop, const int32_t* ref, hipStream_t s) {
   static_assert(BW * G <= 1024, "block size");
   if (max_n > RMAX * G) return hipErrorInvalidValue;
   const size_t lds = (size_t)2 * BW * gjac_ld<G>(max_n) * sizeof(T);
@@ -355,7 +373,7 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
   if (e != hipSuccess) return e;
   const int nb = (max_n + BW - 1) / BW, nbp = (nb + 1) >> 1, nbe = nbp << 1;
   hipLaunchKernelGGL((gjac_init_kernel<T, 1024>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work,
-                     stop);
+                     stop, ref, x32);
   for (int sw = 0; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(intra, dim3(nb, n_sel), dim3(G, BW), lds, s, items, sel, work, sw, 0, tol);
     for (int step = 0; step < nbe - 1; ++step)
@@ -375,7 +393,7 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,
-                                hipStream_t s) {
+                                const int32_t* ref, hipStream_t s) {
   if (max_n > kMaxN || max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
   // block width: two blocks of the largest item fill at most 160 KiB of LDS;
@@ -384,24 +402,24 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
     const float t = (float)tol;
     if (max_n <= 304)
       return gjac_run<float, 64, 16, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                         max_sweeps, t, (float)stop, s);
+                                         max_sweeps, t, (float)stop, ref, s);
     if (max_n <= 608)
       return gjac_run<float, 32, 32, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                         max_sweeps, t, (float)stop, s);
+                                         max_sweeps, t, (float)stop, ref, s);
     return gjac_run<float, 16, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, t, (float)stop, s);
+                                       max_sweeps, t, (float)stop, ref, s);
   }
   if (max_n <= 144)
     return gjac_run<double, 64, 16, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, tol, (float)stop, s);
+                                       max_sweeps, tol, (float)stop, nullptr, s);
   if (max_n <= 288)
     return gjac_run<double, 32, 32, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, tol, (float)stop, s);
+                                       max_sweeps, tol, (float)stop, nullptr, s);
   if (max_n <= 576)
     return gjac_run<double, 16, 64, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                        max_sweeps, tol, (float)stop, s);
+                                        max_sweeps, tol, (float)stop, nullptr, s);
   return gjac_run<double, 8, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status, max_sweeps,
-                                     tol, (float)stop, s);
+                                     tol, (float)stop, nullptr, s);
 }
 
 }  // namespace wpcd

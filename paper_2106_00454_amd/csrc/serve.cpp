@@ -295,7 +295,7 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
     else
       e = launch_jacobi_global(1, d_items, d_cls + class_ptr[k], n_sel, class_maxn[k], d_grids, d_v64, d_work,
                                d_evec, d_x32, d_eval, d_est, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32,
-                               s.stream);
+                               nullptr, s.stream);
   }
   if (e == hipSuccess)
     e = launch_refine(d_items, n, max_n, d_grids, d_v64, d_x32, d_evec, d_eval, d_lam, d_work, d_cl, d_est,

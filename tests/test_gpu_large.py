@@ -53,3 +53,33 @@ def test_large_mesh_matches_oracle(setup, mode):
     ds = np.abs(host["sigma"][0] - oo.sigma_tot(chans, kbar, sweep.TLAB, k[-1])).max()
     print(f"large mode={mode}: dsigma={ds:.3e} mb", flush=True)
     assert ds <= SIGMA_TOL
+
+
+def test_warm_started_device_memory_jacobi():
+    # three samples of one coupled channel at n = 300 (device-memory Jacobi):
+    # the first starts cold, the others from its eigenvectors (default); the
+    # same batch with cold starts only must agree, and both match the oracle
+    n_wp, chan = 150, 14
+    k = sweep.grid_bounds(n_wp)
+    xo, _ = ow.gauss_nodes(k, sweep.N_GAUSS)
+    or_terms = sweep.TermCache()
+    samples = (0, 1, 2)
+    refs = []
+    for s in samples:
+        u = sum(ci * t for ci, t in zip(sweep.coefficients(s, chan), or_terms.terms(("or", n_wp), xo, chan)))
+        refs.append(ow.solve_channel(k, sweep.N_GAUSS, u, 2))
+    J = sweep.CHANNELS[chan][2]
+    out = {}
+    for start in (0, 1):
+        ctx = wp.Context(0, jacobi_start=start)
+        g = ctx.grid(k, sweep.N_GAUSS)
+        bs = ctx.basis(g, 2, sweep.TermCache().terms(("lib", n_wp), g.nodes, chan))
+        specs = [(g, 2, J, i, bs) for i in range(len(samples))]
+        coefs = [sweep.coefficients(s, chan) for s in samples]
+        b, host = run_items(ctx, specs, None, wp.MIXED, tlab=sweep.TLAB, coef=coefs)
+        assert b.layout["max_n"] == 2 * n_wp
+        out[start] = (b, host)
+    (bw, hw), (bc, hc) = out[0], out[1]
+    assert np.abs(((hw["delta"] - hc["delta"] + 90.0) % 180.0) - 90.0).max() <= 1e-6
+    for i, ref in enumerate(refs):
+        check_item(f"warm device-memory item={i} n={2 * n_wp}", item_view(bw, hw, i), ref, k, wp.MIXED, J)
