@@ -39,10 +39,23 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlock = 256;    // 4 wavefronts
-constexpr int kTM = 64;        // output tile edge
+constexpr int kBlock = 256;    // 4 wavefronts (per-item kernels, 64 x 64 GEMM tiles)
+constexpr int kTM = 64;        // edge of the per-item kernels' GEMM tiles
 constexpr int kTK = 32;        // reduction chunk
-constexpr int kTileLds = kTK * kTM;  // doubles of one staged operand tile
+constexpr int kTileLds = kTK * kTM;  // doubles of one staged 64-row operand tile
+// GEMM tile shapes: WR x WR wavefronts, each computing 32 x 32 (2 x 2 MFMA
+// blocks of 16 x 16); the tile is 32 WR square, staged operands 32 WR x kTK.
+template <int WR_>
+struct TileCfg {
+  static constexpr int WR = WR_;
+  static constexpr int TM = 32 * WR_;          // tile edge
+  static constexpr int NT = 64 * WR_ * WR_;    // threads
+  static constexpr int LDS = kTK * TM;         // doubles of one staged operand
+  static constexpr int HQ = (kTK / 4) * TM / NT;  // k quads staged per thread and operand
+};
+using T64 = TileCfg<2>;    // all products: 4 wavefronts, 64 x 64 tiles
+// (128 x 128 tiles of 16 wavefronts halve the L2 reads per flop but ran
+// slower: one such work-group fills a CU and its barriers stall all of it)
 constexpr int kXcd = 8;        // XCDs; workgroups are dispatched to them round-robin
 constexpr int kMaxChain = 64;  // columns of one LDS Rayleigh-Ritz batch
 constexpr int kMaxBig = 24;    // longer chains per item, solved in device memory
@@ -117,62 +130,64 @@ __device__ Mat<T> col_view(const T* M, int rows_k, int ld) { return Mat<T>(M, (i
 template <typename T>
 __device__ Mat<T> row_view(const T* M, int rows_i, int ld) { return Mat<T>(M, (int64_t)rows_i * ld, ld, 1); }
 
-template <typename T>
-__device__ __forceinline__ void fetch(typename Mat<T>::raw_t (&r)[8], const Mat<T>& op, int r0, int k0, int n_i,
-                                      int n_k) {
-  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int i = r0 + (tid & 63);
+template <class TC, typename T>
+__device__ __forceinline__ void fetch(typename Mat<T>::raw_t (&r)[4 * TC::HQ], const Mat<T>& op, int r0, int k0,
+                                      int n_i, int n_k) {
+  const int tid = threadIdx.x;
+  const int grp = __builtin_amdgcn_readfirstlane(tid / TC::TM);  // wave-uniform
+  const int i = r0 + tid % TC::TM;
   const unsigned base = i < n_i ? (unsigned)(i * op.si) * (unsigned)sizeof(T) : kOob;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < TC::HQ; ++h)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = k0 + 4 * (wave + 4 * h) + j;  // wave-uniform
+      const int k = k0 + 4 * (grp + (TC::NT / TC::TM) * h) + j;  // wave-uniform
       const unsigned ko = k < n_k ? (unsigned)(k * op.sk) * (unsigned)sizeof(T) : kOob;
       r[4 * h + j] = op.load(base + ko);
     }
 }
-template <class Op>
-__device__ __forceinline__ void stash(double* T, const typename Op::raw_t (&r)[8]) {
+template <class TC, class Op>
+__device__ __forceinline__ void stash(double* T, const typename Op::raw_t (&r)[4 * TC::HQ]) {
   const int tid = threadIdx.x;
-  const int i = tid & 63;
+  const int i = tid % TC::TM, grp = tid / TC::TM;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < TC::HQ; ++h)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = 4 * ((tid >> 6) + 4 * h) + j;
-      T[k * kTM + (i ^ ((k & 1) << 4))] = Op::cvt(r[4 * h + j]);
+      const int k = 4 * (grp + (TC::NT / TC::TM) * h) + j;
+      T[k * TC::TM + (i ^ ((k & 1) << 4))] = Op::cvt(r[4 * h + j]);
     }
 }
 
 // The K loop for a wave whose live 16 x 16 sub-blocks are bi < NI, bj < NJ
 // (NI = NJ = 0: the wave only helps staging).  NB = 1 or 2 B operands share
 // the A operand (Bs holds NB staged tiles).
-template <int NI, int NJ, int NB, class OA, class OB0, class OB1>
+template <class TC, int NI, int NJ, int NB, class OA, class OB0, class OB1>
 __device__ __forceinline__ void gemm_loop(double* As, double* Bs, int m0, int c0, int rows, int cols, int K,
                                           const OA& oa, const OB0& ob0, const OB1& ob1, d4 (&acc)[NB][2][2]) {
+  constexpr int R = TC::TM;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  typename OA::raw_t ra[8];
-  typename OB0::raw_t rb0[8];
-  typename OB1::raw_t rb1[8];
-  fetch(ra, oa, m0, 0, rows, K);
-  fetch(rb0, ob0, c0, 0, cols, K);
-  if constexpr (NB > 1) fetch(rb1, ob1, c0, 0, cols, K);
+  const int wr = (wave / TC::WR) * 32, wc = (wave % TC::WR) * 32;
+  typename OA::raw_t ra[4 * TC::HQ];
+  typename OB0::raw_t rb0[4 * TC::HQ];
+  typename OB1::raw_t rb1[4 * TC::HQ];
+  fetch<TC>(ra, oa, m0, 0, rows, K);
+  fetch<TC>(rb0, ob0, c0, 0, cols, K);
+  if constexpr (NB > 1) fetch<TC>(rb1, ob1, c0, 0, cols, K);
   // this lane's read offsets for sub-block 0 / 1 at k = 4q + lane / 16: the
   // swizzle only depends on k & 1 = (lane / 16) & 1
   const int kk = lane >> 4, sw = (kk & 1) << 4;
-  const int pa[2] = {kk * kTM + ((wr + (lane & 15)) ^ sw), kk * kTM + ((wr + 16 + (lane & 15)) ^ sw)};
-  const int pb[2] = {kk * kTM + ((wc + (lane & 15)) ^ sw), kk * kTM + ((wc + 16 + (lane & 15)) ^ sw)};
+  const int pa[2] = {kk * R + ((wr + (lane & 15)) ^ sw), kk * R + ((wr + 16 + (lane & 15)) ^ sw)};
+  const int pb[2] = {kk * R + ((wc + (lane & 15)) ^ sw), kk * R + ((wc + 16 + (lane & 15)) ^ sw)};
   auto quad = [&](int q) {
-    const int o = q * 4 * kTM;
+    const int o = q * 4 * R;
     double a[2], b[NB][2];
 #pragma unroll
     for (int bi = 0; bi < NI; ++bi) a[bi] = As[o + pa[bi]];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int bj = 0; bj < NJ; ++bj) b[nb][bj] = Bs[nb * kTileLds + o + pb[bj]];
+      for (int bj = 0; bj < NJ; ++bj) b[nb][bj] = Bs[nb * TC::LDS + o + pb[bj]];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -183,19 +198,24 @@ __device__ __forceinline__ void gemm_loop(double* As, double* Bs, int m0, int c0
   };
   for (int k0 = 0; k0 < K; k0 += kTK) {
     __syncthreads();  // previous chunk fully consumed
-    stash<OA>(As, ra);
-    stash<OB0>(Bs, rb0);
-    if constexpr (NB > 1) stash<OB1>(Bs + kTileLds, rb1);
+    stash<TC, OA>(As, ra);
+    stash<TC, OB0>(Bs, rb0);
+    if constexpr (NB > 1) stash<TC, OB1>(Bs + TC::LDS, rb1);
     __syncthreads();
     if (k0 + kTK < K) {
-      fetch(ra, oa, m0, k0 + kTK, rows, K);
-      fetch(rb0, ob0, c0, k0 + kTK, cols, K);
-      if constexpr (NB > 1) fetch(rb1, ob1, c0, k0 + kTK, cols, K);
+      fetch<TC>(ra, oa, m0, k0 + kTK, rows, K);
+      fetch<TC>(rb0, ob0, c0, k0 + kTK, cols, K);
+      if constexpr (NB > 1) fetch<TC>(rb1, ob1, c0, k0 + kTK, cols, K);
     }
     if constexpr (NI > 0 && NJ > 0) {
       if (K - k0 >= kTK) {
+        if constexpr (NB == 1) {
 #pragma unroll
-        for (int q = 0; q < kTK / 4; ++q) quad(q);
+          for (int q = 0; q < kTK / 4; ++q) quad(q);
+        } else {  // two accumulator sets: keep fewer quads in flight (registers)
+#pragma unroll 2
+          for (int q = 0; q < kTK / 4; ++q) quad(q);
+        }
       } else {
         const int qend = (K - k0 + 3) >> 2;
         for (int q = 0; q < qend; ++q) quad(q);
@@ -204,11 +224,11 @@ __device__ __forceinline__ void gemm_loop(double* As, double* Bs, int m0, int c0
   }
 }
 
-template <int NB, class OA, class OB0, class OB1>
+template <class TC, int NB, class OA, class OB0, class OB1>
 __device__ void gemm_core(double* As, double* Bs, int m0, int c0, int rows, int cols, int K, const OA& oa,
                           const OB0& ob0, const OB1& ob1, d4 (&acc)[NB][2][2]) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave / TC::WR) * 32, wc = (wave % TC::WR) * 32;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -218,27 +238,27 @@ __device__ void gemm_core(double* As, double* Bs, int m0, int c0, int rows, int 
   const int ni = (m0 + wr < rows) + (m0 + wr + 16 < rows);
   const int nj = (c0 + wc < cols) + (c0 + wc + 16 < cols);
   if (ni == 2 && nj == 2)
-    gemm_loop<2, 2, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+    gemm_loop<TC, 2, 2, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
   else if (ni == 2 && nj == 1)
-    gemm_loop<2, 1, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+    gemm_loop<TC, 2, 1, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
   else if (ni == 1 && nj == 2)
-    gemm_loop<1, 2, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+    gemm_loop<TC, 1, 2, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
   else if (ni == 1 && nj == 1)
-    gemm_loop<1, 1, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+    gemm_loop<TC, 1, 1, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
   else
-    gemm_loop<0, 0, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
+    gemm_loop<TC, 0, 0, NB>(As, Bs, m0, c0, rows, cols, K, oa, ob0, ob1, acc);
 }
 
-template <class OA, class OB>
+template <class TC, class OA, class OB>
 __device__ __forceinline__ void gemm_tile(double* As, double* Bs, int m0, int c0, int rows, int cols, int K,
                                           const OA& oa, const OB& ob, d4 (&acc)[2][2]) {
-  gemm_core<1>(As, Bs, m0, c0, rows, cols, K, oa, ob, ob, reinterpret_cast<d4(&)[1][2][2]>(acc));
+  gemm_core<TC, 1>(As, Bs, m0, c0, rows, cols, K, oa, ob, ob, reinterpret_cast<d4(&)[1][2][2]>(acc));
 }
 
-template <class G>
+template <class TC, class G>
 __device__ __forceinline__ void tile_store(int m0, int c0, int rows, int cols, const d4 (&acc)[2][2], const G& g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave / TC::WR) * 32, wc = (wave % TC::WR) * 32;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -282,22 +302,22 @@ struct WS {
 
 // ------------------------------------------------------------ step kernels
 // One-dimensional grids over (item, tile) from xcd_item_tile.
-#define WPCD_LDS_TILES(NB)     \
-  __shared__ double As[kTileLds]; \
-  __shared__ double Bs[(NB) * kTileLds]
+#define WPCD_LDS_TILES(TC, NB)    \
+  __shared__ double As[TC::LDS]; \
+  __shared__ double Bs[(NB) * TC::LDS]
 
 // Y = H X = V X + H0 X (H0 diagonal)
 template <typename XT>
-__global__ __launch_bounds__(kBlock, 3) void gemm_y_kernel(const ItemDev* __restrict__ items, int n_items,
+__global__ __launch_bounds__(T64::NT, 3) void gemm_y_kernel(const ItemDev* __restrict__ items, int n_items,
                                                         const GridDev* __restrict__ grids,
                                                         const double* __restrict__ v64, const XT* xin, int xin_ws,
                                                         double* work, int tiles) {
-  WPCD_LDS_TILES(1);
+  WPCD_LDS_TILES(T64, 1);
   int item, tile;
   if (!xcd_item_tile(tiles, n_items, item, tile)) return;
   const ItemDev it = items[item];
   const int n = it.n;
-  const int nt = (n + kTM - 1) / kTM;
+  const int nt = (n + T64::TM - 1) / T64::TM;
   if (tile >= nt * nt) return;
   const int tm = tile / nt, tc = tile % nt;
   const GridDev g = grids[it.grid];
@@ -305,10 +325,10 @@ __global__ __launch_bounds__(kBlock, 3) void gemm_y_kernel(const ItemDev* __rest
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
   d4 acc[2][2];
   // V is symmetric: its rows are read as columns (contiguous along the tile's rows)
-  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(v64 + it.v_off, n, n), col_view(X, n, n), acc);
+  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, col_view(v64 + it.v_off, n, n), col_view(X, n, n), acc);
   double* Y = ws.Y;
   const int N = it.N;
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc, [&](int r, int c, double v) {
     Y[(int64_t)r * n + c] = fma(g.e0[r % N], (double)X[(int64_t)r * n + c], v);  // + H0 X
   });
 }
@@ -316,14 +336,14 @@ __global__ __launch_bounds__(kBlock, 3) void gemm_y_kernel(const ItemDev* __rest
 // S = X^T Y and G = X^T X in one pass over the shared operand X^T, on the
 // upper tiles (tm <= tc), mirrored on store
 template <typename XT>
-__global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restrict__ items, int n_items,
-                                                         const XT* xin, int xin_ws, double* work, int tiles) {
-  WPCD_LDS_TILES(2);
+__global__ __launch_bounds__(T64::NT) void gemm_sg_kernel(const ItemDev* __restrict__ items, int n_items,
+                                                        const XT* xin, int xin_ws, double* work, int tiles) {
+  WPCD_LDS_TILES(T64, 2);
   int item, t;
   if (!xcd_item_tile(tiles, n_items, item, t)) return;
   const ItemDev it = items[item];
   const int n = it.n;
-  const int nt = (n + kTM - 1) / kTM;
+  const int nt = (n + T64::TM - 1) / T64::TM;
   int tm = 0;
   while (tm < nt && t >= nt - tm) {
     t -= nt - tm;
@@ -334,16 +354,16 @@ __global__ __launch_bounds__(kBlock) void gemm_sg_kernel(const ItemDev* __restri
   const WS ws(work, it);
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
   d4 acc[2][2][2];
-  gemm_core<2>(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(X, n, n), col_view<double>(ws.Y, n, n),
-               col_view(X, n, n), acc);
+  gemm_core<T64, 2>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, col_view(X, n, n), col_view<double>(ws.Y, n, n),
+                    col_view(X, n, n), acc);
   double* S = ws.S;
   double* G = ws.G;
-  tile_store(tm * kTM, tc * kTM, n, n, acc[0], [&](int r, int c, double v) {
+  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc[0], [&](int r, int c, double v) {
     if (r > c) return;  // one writer per symmetric pair
     S[(int64_t)r * n + c] = v;
     S[(int64_t)c * n + r] = v;
   });
-  tile_store(tm * kTM, tc * kTM, n, n, acc[1], [&](int r, int c, double v) {
+  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc[1], [&](int r, int c, double v) {
     if (r > c) return;
     G[(int64_t)r * n + c] = v;
     G[(int64_t)c * n + r] = v;
@@ -384,23 +404,23 @@ __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restric
 
 // X' = X M with M from form_m_kernel (W5).
 template <typename XT>
-__global__ __launch_bounds__(kBlock, 3) void gemm_xm_kernel(const ItemDev* __restrict__ items, int n_items,
+__global__ __launch_bounds__(T64::NT, 3) void gemm_xm_kernel(const ItemDev* __restrict__ items, int n_items,
                                                          const XT* xin, int xin_ws, double* evec, int xout_ws,
                                                          double* work, int tiles) {
-  WPCD_LDS_TILES(1);
+  WPCD_LDS_TILES(T64, 1);
   int item, tile;
   if (!xcd_item_tile(tiles, n_items, item, tile)) return;
   const ItemDev it = items[item];
   const int n = it.n;
-  const int nt = (n + kTM - 1) / kTM;
+  const int nt = (n + T64::TM - 1) / T64::TM;
   if (tile >= nt * nt) return;
   const int tm = tile / nt, tc = tile % nt;
   const WS ws(work, it);
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
   double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
   d4 acc[2][2];
-  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, row_view(X, n, n), col_view<double>(ws.W5, n, n), acc);
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
+  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, row_view(X, n, n), col_view<double>(ws.W5, n, n), acc);
+  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
 }
 
 // ------------------------------------------------------------ reach kernel
@@ -644,13 +664,13 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     }
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile(As, Bs, tm * kTM, 0, n, Tb, n, col_view(S, n, n), col_view<double>(P, n, Tb), acc);
-      tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { SP[(int64_t)r * Tb + cc] = v; });
+      gemm_tile<T64>(As, Bs, tm * kTM, 0, n, Tb, n, col_view(S, n, n), col_view<double>(P, n, Tb), acc);
+      tile_store<T64>(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { SP[(int64_t)r * Tb + cc] = v; });
     }
     __syncthreads();
-    gemm_tile(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(SP, n, Tb), acc);
+    gemm_tile<T64>(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(SP, n, Tb), acc);
     __syncthreads();  // W overlays the staging tiles
-    tile_store(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
+    tile_store<T64>(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
       if (r > cc) return;  // symmetric: one writer per pair
       const double w = (blk[r] == blk[cc]) ? v : 0.0;
       W[cc * ldw + r] = w;
@@ -701,8 +721,8 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     // P Q -> chain columns [pos, pos + Tb) of MC
     for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile(As, Bs, tm * kTM, 0, n, Tb, Tb, row_view<double>(P, n, Tb), col_view<double>(QB, Tb, Tb), acc);
-      tile_store(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
+      gemm_tile<T64>(As, Bs, tm * kTM, 0, n, Tb, Tb, row_view<double>(P, n, Tb), col_view<double>(QB, Tb, Tb), acc);
+      tile_store<T64>(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
     }
     __syncthreads();
     if (threadIdx.x == 0) s_pos = pos + Tb;
@@ -722,14 +742,14 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm)
       for (int tc = 0; tc < mt; ++tc) {
-        gemm_tile(As, Bs, tm * kTM, tc * kTM, n, m, n, col_view(S, n, n), col_view<double>(P, n, m), acc);
-        tile_store(tm * kTM, tc * kTM, n, m, acc, [&](int r, int cc, double v) { SP[(int64_t)r * m + cc] = v; });
+        gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, n, m, n, col_view(S, n, n), col_view<double>(P, n, m), acc);
+        tile_store<T64>(tm * kTM, tc * kTM, n, m, acc, [&](int r, int cc, double v) { SP[(int64_t)r * m + cc] = v; });
       }
     __syncthreads();
     for (int tm = 0; tm < mt; ++tm)
       for (int tc = tm; tc < mt; ++tc) {
-        gemm_tile(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc);
-        tile_store(tm * kTM, tc * kTM, m, m, acc, [&](int r, int cc, double v) {
+        gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc);
+        tile_store<T64>(tm * kTM, tc * kTM, m, m, acc, [&](int r, int cc, double v) {
           if (r > cc) return;  // symmetric: one writer per pair
           C[(int64_t)cc * m + r] = v;
           C[(int64_t)r * m + cc] = v;
@@ -786,8 +806,8 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm)
       for (int tc = 0; tc < mt; ++tc) {
-        gemm_tile(As, Bs, tm * kTM, tc * kTM, n, m, m, row_view<double>(P, n, m), col_view<double>(Q, m, m), acc);
-        tile_store(tm * kTM, tc * kTM, n, m, acc,
+        gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, n, m, m, row_view<double>(P, n, m), col_view<double>(Q, m, m), acc);
+        tile_store<T64>(tm * kTM, tc * kTM, n, m, acc,
                    [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
       }
     __syncthreads();
@@ -853,15 +873,15 @@ __global__ __launch_bounds__(kBlock) void refine_finish_kernel(const ItemDev* __
 // Y = H X for the normalised columns of the device-memory FP64 Jacobi (column
 // c of X contiguous at ws.P1 + c n, as the iteration stores W); Y column-major
 // in ws.Y.
-__global__ __launch_bounds__(kBlock, 3) void rq_hx_kernel(const ItemDev* __restrict__ items, int n_items,
+__global__ __launch_bounds__(T64::NT, 3) void rq_hx_kernel(const ItemDev* __restrict__ items, int n_items,
                                                          const GridDev* __restrict__ grids,
                                                          const double* __restrict__ v64, double* work, int tiles) {
-  WPCD_LDS_TILES(1);
+  WPCD_LDS_TILES(T64, 1);
   int item, tile;
   if (!xcd_item_tile(tiles, n_items, item, tile)) return;
   const ItemDev it = items[item];
   const int n = it.n;
-  const int nt = (n + kTM - 1) / kTM;
+  const int nt = (n + T64::TM - 1) / T64::TM;
   if (tile >= nt * nt) return;
   const int tm = tile / nt, tc = tile % nt;
   const GridDev g = grids[it.grid];
@@ -869,10 +889,10 @@ __global__ __launch_bounds__(kBlock, 3) void rq_hx_kernel(const ItemDev* __restr
   const double* X = ws.P1;
   d4 acc[2][2];
   // B(k, j) = component k of column j = X[j n + k]
-  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(v64 + it.v_off, n, n), row_view<double>(X, n, n), acc);
+  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, col_view(v64 + it.v_off, n, n), row_view<double>(X, n, n), acc);
   double* Y = ws.Y;
   const int N = it.N;
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
+  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc, [&](int r, int c, double v) {
     Y[(int64_t)c * n + r] = fma(g.e0[r % N], X[(int64_t)c * n + r], v);  // + H0 X
   });
 }
@@ -945,32 +965,96 @@ __global__ __launch_bounds__(kBlock) void warm_q0_kernel(const ItemDev* __restri
 }
 
 // H Q0 for every warm item (its reference's Q0), column-major FP32 into the
-// item's x32, where the Jacobi kernel reads it as the start of W.
-__global__ __launch_bounds__(kBlock, 3) void warm_y_kernel(const ItemDev* __restrict__ items,
-                                                          const int32_t* __restrict__ warm, int n_warm,
-                                                          const int32_t* __restrict__ ref,
-                                                          const GridDev* __restrict__ grids,
-                                                          const double* __restrict__ v64, float* x32,
-                                                          const double* work, int tiles) {
-  WPCD_LDS_TILES(1);
+// item's x32, where the Jacobi kernel reads it as the start of W.  The result
+// only seeds an FP32 iteration, so the product runs on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k, D[i][j] in lane j + 16 (i / 4), register i % 4) with 64 x 64 tiles
+// of 4 wavefronts (32 x 32 each) and K chunks of 32; staged tiles are
+// T[k * 64 + (i ^ 16 (k % 4))] floats, so the 4 k of an operand read land in
+// 4 distinct 16-bank ranges and the stores (64 lanes over i) in all 64.
+typedef float f4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(T64::NT, 3) void warm_y_kernel(const ItemDev* __restrict__ items,
+                                                           const int32_t* __restrict__ warm, int n_warm,
+                                                           const int32_t* __restrict__ ref,
+                                                           const GridDev* __restrict__ grids,
+                                                           const double* __restrict__ v64, float* x32,
+                                                           const double* work, int tiles) {
+  __shared__ float As[kTK * 64];
+  __shared__ float Bs[kTK * 64];
   int w, tile;
   if (!xcd_item_tile(tiles, n_warm, w, tile)) return;
   const int item = warm[w];
   const ItemDev it = items[item];
   const int n = it.n;
-  const int nt = (n + kTM - 1) / kTM;
+  const int nt = (n + 63) / 64;
   if (tile >= nt * nt) return;
-  const int tm = tile / nt, tc = tile % nt;
+  const int m0 = (tile / nt) * 64, c0 = (tile % nt) * 64;
   const GridDev g = grids[it.grid];
   const float* Q0 = reinterpret_cast<const float*>(work + items[ref[item]].w_off);
-  d4 acc[2][2];
-  // B(k, j) = component k of column j = Q0[j n + k]
-  gemm_tile(As, Bs, tm * kTM, tc * kTM, n, n, n, col_view(v64 + it.v_off, n, n), row_view<float>(Q0, n, n), acc);
+  const Mat<double> A = col_view(v64 + it.v_off, n, n);  // A(i, k) = V[k][i] = V[i][k]
+  const Mat<float> B = row_view<float>(Q0, n, n);        // B(k, j) = Q0[j n + k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // staging map: thread t loads i = t % 64 and k = 4 (t / 64 + 4h) + j
+  const int si = tid & 63, sg = wave;
+  Mat<double>::raw_t ra[8];
+  Mat<float>::raw_t rb[8];
+  auto load = [&](int k0) {
+    const unsigned ba = m0 + si < n ? (unsigned)((m0 + si) * A.si) * 8u : kOob;
+    const unsigned bb = c0 + si < n ? (unsigned)((c0 + si) * B.si) * 4u : kOob;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 4 * (sg + 4 * h) + j;
+        ra[4 * h + j] = A.load(ba + (k < n ? (unsigned)(k * A.sk) * 8u : kOob));
+        rb[4 * h + j] = B.load(bb + (k < n ? (unsigned)(k * B.sk) * 4u : kOob));
+      }
+  };
+  f4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+  const int kk = lane >> 4, sw = kk << 4;  // k % 4 = lane / 16 for k = 4q + lane / 16
+  const int pa[2] = {kk * 64 + ((wr + (lane & 15)) ^ sw), kk * 64 + ((wr + 16 + (lane & 15)) ^ sw)};
+  const int pb[2] = {kk * 64 + ((wc + (lane & 15)) ^ sw), kk * 64 + ((wc + 16 + (lane & 15)) ^ sw)};
+  load(0);
+  for (int k0 = 0; k0 < n; k0 += kTK) {
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * (sg + 4 * h) + j;
+        As[k * 64 + (si ^ ((k & 3) << 4))] = (float)Mat<double>::cvt(ra[4 * h + j]);
+        Bs[k * 64 + (si ^ ((k & 3) << 4))] = (float)Mat<float>::cvt(rb[4 * h + j]);
+      }
+    __syncthreads();
+    if (k0 + kTK < n) load(k0 + kTK);
+    const int qend = (n - k0) < kTK ? (n - k0 + 3) >> 2 : kTK / 4;
+    for (int q = 0; q < qend; ++q) {
+      const int o = q * 256;
+      const float a0 = As[o + pa[0]], a1 = As[o + pa[1]], b0 = Bs[o + pb[0]], b1 = Bs[o + pb[1]];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
   float* Y0 = x32 + it.v_off;
   const int N = it.N;
-  tile_store(tm * kTM, tc * kTM, n, n, acc, [&](int r, int c, double v) {
-    Y0[(int64_t)c * n + r] = (float)fma(g.e0[r % N], (double)Q0[(int64_t)c * n + r], v);  // + H0 Q0
-  });
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int c = c0 + wc + bj * 16 + (lane & 15);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int r = m0 + wr + bi * 16 + 4 * (lane >> 4) + rr;
+        if (r < n && c < n) Y0[(int64_t)c * n + r] = fmaf((float)g.e0[r % N], Q0[(int64_t)c * n + r], acc[bi][bj][rr]);
+      }
+    }
 }
 
 }  // namespace
@@ -979,22 +1063,23 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
                          const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
                          int32_t* status, int steps, int close_log10, hipStream_t s) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
-  const int nt = (max_n + kTM - 1) / kTM;
-  const int tiles = nt * nt, up_tiles = nt * (nt + 1) / 2;
+  const int nt = (max_n + kTM - 1) / kTM;  // 64-row blocks of form_m
+  const int nt2 = (max_n + T64::TM - 1) / T64::TM;  // GEMM tiles
+  const int tiles = nt2 * nt2, up_tiles = nt2 * (nt2 + 1) / 2;
   int cur_ws = 0;  // X in the caller's evec (0) or in the work-space P1 (1); step 0 reads x32
   for (int st = 0; st < steps; ++st) {
     const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
     double closec = 1.0;
     for (int q = 0; q < close_log10 + st; ++q) closec *= 10.0;
     if (st == 0) {
-      hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+      hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          grids, v64, x32, 0, work, tiles);
-      hipLaunchKernelGGL(gemm_sg_kernel<float>, dim3(xcd_grid(up_tiles, n_items)), dim3(kBlock), 0, s, items,
+      hipLaunchKernelGGL(gemm_sg_kernel<float>, dim3(xcd_grid(up_tiles, n_items)), dim3(T64::NT), 0, s, items,
                          n_items, x32, 0, work, up_tiles);
     } else {
-      hipLaunchKernelGGL(gemm_y_kernel<double>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+      hipLaunchKernelGGL(gemm_y_kernel<double>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          grids, v64, (const double*)evec, cur_ws, work, tiles);
-      hipLaunchKernelGGL(gemm_sg_kernel<double>, dim3(xcd_grid(up_tiles, n_items)), dim3(kBlock), 0, s, items,
+      hipLaunchKernelGGL(gemm_sg_kernel<double>, dim3(xcd_grid(up_tiles, n_items)), dim3(T64::NT), 0, s, items,
                          n_items, (const double*)evec, cur_ws, work, up_tiles);
     }
     hipError_t err = hipGetLastError();
@@ -1013,10 +1098,10 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
       hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work, cl, closec);
     }
     if (st == 0)
-      hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+      hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          x32, 0, evec, out_ws, work, tiles);
     else
-      hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(xcd_grid(tiles, n_items)), dim3(kBlock), 0, s, items, n_items,
+      hipLaunchKernelGGL(gemm_xm_kernel<double>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          (const double*)evec, cur_ws, evec, out_ws, work, tiles);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -1035,8 +1120,8 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
                                const double* v64, double* work, double* evec, double* eval, int32_t* status,
                                hipStream_t s) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
-  const int nt = (max_n + kTM - 1) / kTM;
-  hipLaunchKernelGGL(rq_hx_kernel, dim3(xcd_grid(nt * nt, n_items)), dim3(kBlock), 0, s, items, n_items, grids, v64,
+  const int nt = (max_n + T64::TM - 1) / T64::TM;
+  hipLaunchKernelGGL(rq_hx_kernel, dim3(xcd_grid(nt * nt, n_items)), dim3(T64::NT), 0, s, items, n_items, grids, v64,
                      work, nt * nt);
   hipLaunchKernelGGL(rq_sort_kernel, dim3(n_items), dim3(kBlock), 0, s, items, work, evec, eval, status);
   return hipGetLastError();
@@ -1052,8 +1137,8 @@ hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, in
   if (max_n > kMaxN) return hipErrorInvalidValue;
   if (n_refs == 0 || n_warm == 0) return hipSuccess;
   hipLaunchKernelGGL(warm_q0_kernel, dim3(n_refs), dim3(kBlock), 0, s, items, refs, x32, work);
-  const int nt = (max_n + kTM - 1) / kTM;
-  hipLaunchKernelGGL(warm_y_kernel, dim3(xcd_grid(nt * nt, n_warm)), dim3(kBlock), 0, s, items, warm, n_warm, ref,
+  const int nt = (max_n + T64::TM - 1) / T64::TM;
+  hipLaunchKernelGGL(warm_y_kernel, dim3(xcd_grid(nt * nt, n_warm)), dim3(T64::NT), 0, s, items, warm, n_warm, ref,
                      grids, v64, x32, work, nt * nt);
   return hipGetLastError();
 }
