@@ -329,8 +329,10 @@ int wpcd_server_stats_get(wpcd_server s, wpcd_server_stats* out);
 
 /* ------------------------------------------------------------ stage timers --
  * When enabled, every compute call records a pair of HIP events on its stream
- * around each kernel group it launches (the eigensolver counts as two stages:
- * the Jacobi sweeps and the refinement).  wpcd_stage_times waits for the
+ * around each kernel group it launches (the eigensolver counts as three
+ * stages: the Jacobi sweeps (one group per launch of the LDS kernel or per
+ * device-memory launch sequence), the preparation of warm starts and the
+ * refinement).  wpcd_stage_times waits for the
  * recorded events, adds their elapsed times to per-stage totals and returns
  * the totals in milliseconds and the number of launches per stage (arrays of
  * WPCD_N_STAGES, host memory, either may be NULL).  Enabling (again) resets
@@ -343,7 +345,8 @@ enum {
   WPCD_STAGE_TMATRIX = 4,
   WPCD_STAGE_OBSERVABLES = 5,
   WPCD_STAGE_SIGMA = 6,
-  WPCD_N_STAGES = 7
+  WPCD_STAGE_WARM_PREP = 7,
+  WPCD_N_STAGES = 8
 };
 int wpcd_profile_enable(wpcd_ctx ctx, int on);
 int wpcd_stage_times(wpcd_ctx ctx, double* ms_host, int64_t* launches_host);

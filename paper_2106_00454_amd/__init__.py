@@ -40,7 +40,7 @@ EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wp
            "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times",
            "wpcd_jacobi_counts")
 
-STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma")
+STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma", "warm_prep")
 
 
 class WPCDError(RuntimeError):

@@ -558,42 +558,44 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
       return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED needs refine_steps >= 1");
     // one FP32 Jacobi launch per size class: LDS-resident up to n = kMaxLdsN,
     // device memory above
-    WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream,
-                   [&] {
-                     hipError_t e = hipSuccess;
-                     constexpr int L = wpcd_batch_s::kC;
-                     unsigned long long* cnt = b->ctx->profiling ? b->ctx->d_counters : nullptr;
-                     auto solve = [&](int seg, int k, const int32_t* ref) {
-                       const int n_sel = b->jl_ptr[seg + 1] - b->jl_ptr[seg];
-                       if (n_sel == 0 || e != hipSuccess) return;
-                       const int32_t* sel = b->d_jlist + b->jl_ptr[seg];
-                       if (k < L - 1)
-                         e = launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
-                                                   b->d_x32, eval, status, c.max_sweeps, (float)c.jacobi_tol_f32,
-                                                   (float)c.jacobi_stop_f32, c.jacobi_block, ref, b->d_work, cnt,
-                                                   stream);
-                       else
-                         e = launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64,
-                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
-                                                  c.jacobi_tol_f32, c.jacobi_stop_f32, ref, stream);
-                     };
-                     // cold starts (each group's reference among them), then the
-                     // warm starts from the references' eigenvectors
-                     for (int k = 0; k < L; ++k) solve(k, k, nullptr);
-                     const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
-                     if (e == hipSuccess && n_warm > 0) {
-                       int wmax = 0;
-                       for (int k = 0; k < L; ++k)
-                         if (b->jl_ptr[L + k + 1] > b->jl_ptr[L + k]) wmax = b->class_maxn[k];
-                       e = launch_jacobi_warm_prep(b->d_items, b->d_jlist + b->jl_ptr[2 * L],
-                                                   b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L], b->d_jlist + b->jl_ptr[L],
-                                                   n_warm, b->d_ref, wmax, b->d_grids, v64, b->d_x32, b->d_work,
-                                                   stream);
-                     }
-                     for (int k = 0; k < L; ++k) solve(L + k, k, b->d_ref);
-                     return e;
-                   }),
-             "wpcd_eigh: FP32 Jacobi launch");
+    {
+      constexpr int L = wpcd_batch_s::kC;
+      unsigned long long* cnt = b->ctx->profiling ? b->ctx->d_counters : nullptr;
+      // one timed group per launch of the LDS kernel (per launch sequence of
+      // the device-memory Jacobi)
+      auto solve = [&](int seg, int k, const int32_t* ref) -> hipError_t {
+        const int n_sel = b->jl_ptr[seg + 1] - b->jl_ptr[seg];
+        if (n_sel == 0) return hipSuccess;
+        const int32_t* sel = b->d_jlist + b->jl_ptr[seg];
+        return timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream, [&] {
+          if (k < L - 1)
+            return launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, b->d_x32, eval,
+                                         status, c.max_sweeps, (float)c.jacobi_tol_f32, (float)c.jacobi_stop_f32,
+                                         c.jacobi_block, ref, b->d_work, cnt, stream);
+          return launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, b->d_work, evec,
+                                      b->d_x32, eval, status, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32, ref,
+                                      stream);
+        });
+      };
+      // cold starts (each group's reference among them), then the warm starts
+      // from the references' eigenvectors
+      for (int k = 0; k < L; ++k) WPCD_HIP(solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
+      const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
+      if (n_warm > 0) {
+        int wmax = 0;
+        for (int k = 0; k < L; ++k)
+          if (b->jl_ptr[L + k + 1] > b->jl_ptr[L + k]) wmax = b->class_maxn[k];
+        WPCD_HIP(timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
+                       [&] {
+                         return launch_jacobi_warm_prep(b->d_items, b->d_jlist + b->jl_ptr[2 * L],
+                                                        b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L],
+                                                        b->d_jlist + b->jl_ptr[L], n_warm, b->d_ref, wmax,
+                                                        b->d_grids, v64, b->d_x32, b->d_work, stream);
+                       }),
+                 "wpcd_eigh: warm-start preparation launch");
+      }
+      for (int k = 0; k < L; ++k) WPCD_HIP(solve(L + k, k, b->d_ref), "wpcd_eigh: FP32 Jacobi launch");
+    }
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_REFINE, stream,
                    [&] {
                      return launch_refine(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, evec, eval,
