@@ -174,7 +174,7 @@ def run_sweep(args) -> dict:
     import paper_2106_00454_amd as wp
     from synth import sweep
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
-                     jacobi_start=args.jacobi_start, refine_steps=args.refine_steps,
+                     jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
                      refine_close_log10=args.refine_close)
     t0 = time.perf_counter()
     _, bases = _register_bases(ctx, sweep.TermCache(), sweep.N_WP_CHOICES, range(len(sweep.CHANNELS)))
@@ -196,7 +196,7 @@ def run_large(args) -> dict:
     import paper_2106_00454_amd as wp
     from synth import sweep
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
-                     jacobi_start=args.jacobi_start, refine_steps=args.refine_steps,
+                     jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
                      refine_close_log10=args.refine_close)
     coupled = [c for c in range(len(sweep.CHANNELS)) if sweep.CHANNELS[c][1] == 2]
     N = args.large_nwp
@@ -220,7 +220,7 @@ def run_serve(args) -> dict:
     import paper_2106_00454_amd as wp
     from synth import sweep
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
-                     jacobi_start=args.jacobi_start, refine_steps=args.refine_steps,
+                     jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
                      refine_close_log10=args.refine_close)
     n_wps = (50, 100, 150, 200)
     t0 = time.perf_counter()
@@ -297,6 +297,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jacobi-block", type=int, default=0, help="LDS Jacobi variant (wpcd_config.jacobi_block; 0: default)")
     ap.add_argument("--jacobi-start", type=int, default=0, help="LDS Jacobi start (wpcd_config.jacobi_start; 0: warm, 1: cold)")
+    ap.add_argument("--refine-gemm", type=int, default=0,
+                    help="refinement products (wpcd_config.refine_gemm; 0: whole-item for n 193..208, 1: tiles)")
     ap.add_argument("--refine-steps", type=int, default=2, help="FP64 refinement steps (wpcd_config.refine_steps)")
     ap.add_argument("--refine-close", type=int, default=0, help="wpcd_config.refine_close_log10 (0: default)")
     ap.add_argument("--jacobi-stop", type=float, default=0.0, help="FP32 Jacobi stopping threshold (wpcd_config.jacobi_stop_f32; 0: default)")
@@ -325,7 +327,7 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
-                     jacobi_start=args.jacobi_start, refine_steps=args.refine_steps,
+                     jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
                      refine_close_log10=args.refine_close)
     k = configs.grid("coupled_yukawa")
     g = ctx.grid(k, configs.N_GAUSS)

@@ -122,7 +122,12 @@ typedef struct {
                             potentials are alike); 1 cold: every item starts
                             from B.  Results agree within the refinement's
                             accuracy either way.                             */
-  int32_t reserved;      /* 0 */
+  int32_t refine_gemm;   /* dense products of the FP64 refinement: 0
+                            (default) whole-item products (one work-group of
+                            12 wavefronts per item, persistent over the
+                            items) when every item of the batch has 193..208
+                            rows, else 64 x 64 tiles; 1 always tiles.  Same
+                            results up to rounding order.                    */
 } wpcd_config;
 
 /* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */

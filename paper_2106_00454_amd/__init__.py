@@ -54,7 +54,7 @@ class _Config(ctypes.Structure):
                 ("jacobi_tol_f32", ctypes.c_double), ("jacobi_tol_f64", ctypes.c_double),
                 ("jacobi_block", ctypes.c_int32), ("refine_close_log10", ctypes.c_int32),
                 ("jacobi_stop_f32", ctypes.c_double), ("jacobi_start", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("refine_gemm", ctypes.c_int32)]
 
 
 class _Item(ctypes.Structure):
@@ -187,10 +187,11 @@ class Grid:
 class Context:
     def __init__(self, device: int = 0, max_sweeps: int = 30, refine_steps: int = 2,
                  jacobi_tol_f32: float = 2e-7, jacobi_tol_f64: float = 1e-15, jacobi_block: int = 0,
-                 refine_close_log10: int = 0, jacobi_stop_f32: float = 0.0, jacobi_start: int = 0):
+                 refine_close_log10: int = 0, jacobi_stop_f32: float = 0.0, jacobi_start: int = 0,
+                 refine_gemm: int = 0):
         L = lib()
         cfg = _Config(max_sweeps, refine_steps, jacobi_tol_f32, jacobi_tol_f64, jacobi_block, refine_close_log10,
-                      jacobi_stop_f32, jacobi_start, 0)
+                      jacobi_stop_f32, jacobi_start, refine_gemm)
         h = ctypes.c_void_p()
         _check(L.wpcd_create(ctypes.byref(h), device, ctypes.byref(cfg)))
         self._h = h

@@ -130,6 +130,7 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   if (!(c.jacobi_stop_f32 > 0) || !(c.jacobi_stop_f32 < 1))
     return fail(WPCD_ERR_INVALID, "jacobi_stop_f32 must be in (0, 1) (0 = default)");
   if (c.jacobi_start != 0 && c.jacobi_start != 1) return fail(WPCD_ERR_INVALID, "jacobi_start must be 0 or 1");
+  if (c.refine_gemm != 0 && c.refine_gemm != 1) return fail(WPCD_ERR_INVALID, "refine_gemm must be 0 or 1");
   if (c.jacobi_block < 0 || c.jacobi_block > 4)
     return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2, 3 or 4");
   if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
@@ -320,6 +321,7 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     b->mix_elems += g.N;
     b->work_doubles += eig_work_doubles(n);
     b->max_n = std::max(b->max_n, n);
+    b->min_n = b->min_n == 0 ? n : std::min(b->min_n, n);
     b->max_nbins = std::max(b->max_nbins, g.N);
     max_sample = std::max(max_sample, in.sample_id);
   }
@@ -381,6 +383,12 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
         }
       }
     }
+    for (int c = 0; c < L; ++c)
+      for (int32_t i : seg[L + c]) {
+        const int n = b->h_items[i].n;
+        b->warm_min_n = b->warm_min_n == 0 ? n : std::min(b->warm_min_n, n);
+        b->warm_max_n = std::max(b->warm_max_n, n);
+      }
     std::vector<char> is_ref(n_items, 0);
     for (int i = 0; i < n_items; ++i)
       if (ref[i] >= 0 && !is_ref[ref[i]]) {
@@ -582,15 +590,13 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
       for (int k = 0; k < L; ++k) WPCD_HIP(solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
       const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
       if (n_warm > 0) {
-        int wmax = 0;
-        for (int k = 0; k < L; ++k)
-          if (b->jl_ptr[L + k + 1] > b->jl_ptr[L + k]) wmax = b->class_maxn[k];
         WPCD_HIP(timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
                        [&] {
                          return launch_jacobi_warm_prep(b->d_items, b->d_jlist + b->jl_ptr[2 * L],
                                                         b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L],
-                                                        b->d_jlist + b->jl_ptr[L], n_warm, b->d_ref, wmax,
-                                                        b->d_grids, v64, b->d_x32, b->d_work, stream);
+                                                        b->d_jlist + b->jl_ptr[L], n_warm, b->d_ref,
+                                                        b->warm_min_n, b->warm_max_n, b->d_grids, v64, b->d_x32,
+                                                        b->d_work, stream);
                        }),
                  "wpcd_eigh: warm-start preparation launch");
       }
@@ -598,9 +604,10 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
     }
     WPCD_HIP(timed(b->ctx, WPCD_STAGE_REFINE, stream,
                    [&] {
-                     return launch_refine(b->d_items, b->n_items, b->max_n, b->d_grids, v64, b->d_x32, evec, eval,
+                     return launch_refine(b->d_items, b->n_items, b->min_n, b->max_n, b->d_grids, v64, b->d_x32,
+                                          evec, eval,
                                           b->d_lam, b->d_work, b->d_cl, status, c.refine_steps,
-                                          c.refine_close_log10, stream);
+                                          c.refine_close_log10, c.refine_gemm, stream);
                    }),
              "wpcd_eigh: FP64 refinement launch");
   } else {

@@ -44,7 +44,8 @@ struct wpcd_context {
 
 struct wpcd_batch_s {
   wpcd_ctx ctx = nullptr;
-  int n_items = 0, n_samples = 0, max_n = 0, max_nbins = 0;
+  int n_items = 0, n_samples = 0, max_n = 0, min_n = 0, max_nbins = 0;
+  int warm_min_n = 0, warm_max_n = 0;  // sizes of the warm-started items
   std::vector<wpcd::ItemDev> h_items;
   wpcd::ItemDev* d_items = nullptr;
   wpcd::GridDev* d_grids = nullptr;

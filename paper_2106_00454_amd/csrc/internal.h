@@ -79,9 +79,10 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
 // Warm start of the LDS Jacobi (items with a reference, ref[item] >= 0):
 // writes each reference's eigenvectors, columns in descending eigenvalue
 // order, column-major as floats into the reference's work-space, then
-// H Q0 of every warm item, column-major FP32, into the item's x32.
+// H Q0 of every warm item, column-major FP32, into the item's x32 (min_n,
+// max_n: the warm items' smallest and largest n).
 hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, int n_refs, const int32_t* warm,
-                                   int n_warm, const int32_t* ref, int max_n, const GridDev* grids,
+                                   int n_warm, const int32_t* ref, int min_n, int max_n, const GridDev* grids,
                                    const double* v64, float* x32, double* work, hipStream_t s);
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
@@ -93,9 +94,12 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
 hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, const GridDev* grids,
                                const double* v64, double* work, double* evec, double* eval, int32_t* status,
                                hipStream_t s);
-hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
-                         const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
-                         int32_t* status, int steps, int close_log10, hipStream_t s);
+// gemm: 0 = whole-item products when every item has 193..208 rows, else
+// 64 x 64 tiles; 1 = tiles
+hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n, const GridDev* grids,
+                         const double* v64, const float* x32, double* evec, double* eval, double* lam_pre,
+                         double* work, int32_t* cl, int32_t* status, int steps, int close_log10, int gemm,
+                         hipStream_t s);
 hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                           const double* eval, const double* evec, int mode, double* t, int32_t* status,
                           hipStream_t s);

@@ -1057,21 +1057,425 @@ __global__ __launch_bounds__(T64::NT, 3) void warm_y_kernel(const ItemDev* __res
     }
 }
 
+// ------------------------------------ whole-item products (193 <= n <= 208)
+// For items of 193..208 rows (13 x 13 output blocks of 16 x 16) one
+// work-group of 12 wavefronts computes a whole n x n product, in two passes
+// over K.  Wavefront w owns row strip w of the blocks, and the 13 blocks of
+// strip 12 are shared out:
+//   general products: pass 0 the columns 0..6, plus (12, w) for w < 7;
+//                     pass 1 the columns 7..12, plus (12, w) for w >= 7 and,
+//                     for w = 0, (12, 12);
+//   symmetric products (one block per unordered pair, stored mirrored; the
+//                     two passes are two products): columns (w + j) mod 13,
+//                     j < 7, plus (12, (12 + w) mod 13) for w < 7.
+// Each SIMD (wavefronts s, s + 4, s + 8) then carries 22-23 and 19-20 blocks
+// in the two passes of a general product, 22-23 per symmetric one, and no
+// wavefront holds more than 8 accumulator blocks.  K is staged in chunks of
+// 16 as panels in LDS: the A panel over all 208 rows, the B panel over the
+// pass's columns only, so both MFMA operands of every block come from LDS;
+// the B panel is fetched once per item and the A panel once per pass
+// (64 x 64 tiles fetch each panel four times).  The work-groups are
+// persistent, one per CU, and load the next chunk -- of the same pass, of
+// the next pass or of their next item -- into registers while the current
+// one is multiplied; LDS holds two chunks, one barrier per chunk.
+// Panel layouts: a source contiguous along i (a column view) is staged
+// k-major, element (i, k) at P[k * 208 + i]: the stores cover consecutive i,
+// and an MFMA read (16 lanes over i at k and at k + 1 in one half wavefront)
+// puts k + 1 416 four-byte banks = half of the banks away.  A source
+// contiguous along k (a row view) is staged i-major, P[i * 18 + k]: the loads
+// cover 16 consecutive k of 4 rows (128-byte segments), and the 16 rows of an
+// MFMA read start 36 banks apart, so rows at k and k + 1 touch all 64 banks.
+constexpr int kIW = 12;                  // wavefronts (3 per SIMD)
+constexpr int kIT = 64 * kIW;            // threads
+constexpr int kIKC = 16;                 // K chunk
+constexpr int kIN = 208;                 // largest n
+constexpr int kINMin = 193;              // smallest n (13 block rows)
+constexpr int kIBlk = kIN / 16;          // blocks per side
+constexpr int kILdI = kIKC + 2;          // row stride of an i-major panel
+constexpr int kIPanelLds = kIN * kILdI;  // LDS doubles per panel (either layout)
+static_assert(kIBlk == kIW + 1, "one row strip per wavefront plus one shared strip");
+
+// staging of the panel rows [I0, I0 + W) of one K chunk: ceil(16 W / kIT)
+// elements per thread; the last round covers whole wavefronts
+template <int W>
+struct IStage {
+  static constexpr int E = W * kIKC;
+  static constexpr int NS = (E + kIT - 1) / kIT;
+  static constexpr int LAST = E - kIT * (NS - 1);
+  static_assert(LAST % 64 == 0, "the last staging round must cover whole wavefronts");
+};
+constexpr int kIStage = IStage<kIN>::NS;  // the largest
+
+template <bool KMAJ, int W, int I0, typename T>
+__device__ __forceinline__ void ifetch(typename Mat<T>::raw_t (&r)[kIStage], const Mat<T>& m, int k0, int n) {
+  using S = IStage<W>;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < S::NS; ++s) {
+    if (s < S::NS - 1 || tid < S::LAST) {
+      const int e = tid + kIT * s;
+      int i, k;
+      if constexpr (KMAJ) {
+        k = e / W;
+        i = I0 + e - k * W;
+      } else {
+        static_assert(W == kIN && I0 == 0, "i-major panels span all rows");
+        i = e / kIKC;
+        k = e - i * kIKC;
+      }
+      k += k0;
+      r[s] = m.load(i < n && k < n ? (unsigned)(i * m.si + k * m.sk) * (unsigned)sizeof(T) : kOob);
+    }
+  }
+}
+// dg (k-major panels only): LDS table added to the diagonal elements
+// (i = k < n) of the chunk starting at k0, or nullptr
+template <bool KMAJ, int W, int I0, typename T>
+__device__ __forceinline__ void istash(double* P, const typename Mat<T>::raw_t (&r)[kIStage], const double* dg = nullptr,
+                                       int k0 = 0, int n = 0) {
+  using S = IStage<W>;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < S::NS; ++s) {
+    if (s < S::NS - 1 || tid < S::LAST) {
+      const int e = tid + kIT * s;
+      if constexpr (KMAJ) {
+        const int k = e / W, i = I0 + e - k * W;
+        double v = Mat<T>::cvt(r[s]);
+        if (dg != nullptr && i == k0 + k && i < n) v += dg[i];
+        P[k * kIN + i] = v;
+      } else {
+        P[(e / kIKC) * kILdI + e % kIKC] = Mat<T>::cvt(r[s]);
+      }
+    }
+  }
+}
+// offset of block row/column b (16 rows) and of k step q in a panel
+template <bool KMAJ>
+__device__ __forceinline__ constexpr int ipan_blk(int b) { return KMAJ ? b * 16 : b * 16 * kILdI; }
+template <bool KMAJ>
+__device__ __forceinline__ constexpr int ipan_kstep(int q) { return KMAJ ? 4 * q * kIN : 4 * q; }
+
+// block sets of a pass (above)
+enum { kSetLo = 0, kSetHi = 1, kSetSym = 2 };
+// result stores: row-major FP64 or FP32 (out<pass>() gives the buffer),
+// symmetric FP64 (mirrored), or per element through store<pass>()
+enum { kOutF64 = 0, kOutF32 = 1, kOutSym = 2, kOutCall = 3 };
+template <int SET>
+struct IBlocks {
+  static constexpr int NC = SET == kSetHi ? 6 : 7;           // blocks of the own strip
+  static constexpr int BC0 = SET == kSetHi ? 7 : 0;          // first staged B column block
+  static constexpr int BW = SET == kSetSym ? kIBlk : NC;     // staged B column blocks
+  __device__ static int col(int w, int j) { return SET == kSetSym ? (w + j) % kIBlk : BC0 + j; }
+  __device__ static bool e_live(int w) { return SET == kSetHi ? w >= 7 : w < 7; }  // block (12, ce)
+  __device__ static int ce(int w) { return SET == kSetSym ? (kIBlk - 1 + w) % kIBlk : w; }
+  __device__ static bool x_live(int w) { return SET == kSetHi && w == 0; }         // block (12, 12)
+};
+
+// A problem P: element types TA/TB and layouts KA/KB of the A and B sources
+// (A = viewA(item) in every pass, B = viewB<pass>(item) unless
+// same_panel<pass>(), then B is the A panel), the block set of each pass,
+// and store<pass>(item, row, col, value).
+template <class P, int PS>
+__device__ __forceinline__ void ifetch_pass(typename Mat<typename P::TA>::raw_t (&ra)[kIStage],
+                                            typename Mat<typename P::TB>::raw_t (&rb)[kIStage], const P& p,
+                                            const ItemDev& it, int item, int k0) {
+  using B = IBlocks<P::set(PS)>;
+  ifetch<P::KA, kIN, 0>(ra, p.viewA(it, item), k0, it.n);
+  if constexpr (!P::same_panel(PS))
+    ifetch<P::KB, B::BW * 16, B::BC0 * 16>(rb, p.template viewB<PS>(it, item), k0, it.n);
+}
+
+template <class P, int PS>
+__device__ __forceinline__ void ipass(const P& p, const ItemDev* __restrict__ items, const int32_t* sel,
+                                      int n_items, int i, int item, const ItemDev& it, double (*lds)[2][kIPanelLds], double* dg, int& buf,
+                                      typename Mat<typename P::TA>::raw_t (&ra)[kIStage],
+                                      typename Mat<typename P::TB>::raw_t (&rb)[kIStage]) {
+  using B = IBlocks<P::set(PS)>;
+  constexpr bool SAME = P::same_panel(PS);
+  constexpr bool KB = SAME ? P::KA : P::KB;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int loa = P::KA ? lk * kIN + li : li * kILdI + lk;
+  const int lob = KB ? lk * kIN + li : li * kILdI + lk;
+  const int oa = loa + ipan_blk<P::KA>(w), oa12 = loa + ipan_blk<P::KA>(kIBlk - 1);
+  int ob[B::NC];
+#pragma unroll
+  for (int j = 0; j < B::NC; ++j) ob[j] = lob + ipan_blk<KB>(B::col(w, j));
+  const int obe = lob + ipan_blk<KB>(B::ce(w)), obx = lob + ipan_blk<KB>(kIBlk - 1);
+  const bool e_live = B::e_live(w), x_live = B::x_live(w);
+  const int n = it.n;
+  d4 acc[B::NC], ace = {0.0, 0.0, 0.0, 0.0}, acx = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < B::NC; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nck = (n + kIKC - 1) / kIKC;
+  if constexpr (P::DIAG_A || P::DIAG_B) {
+    // the diagonal added to A or B; every wavefront has passed the last
+    // barrier of the previous item, so none still stages from the old table
+    if (PS == 0) {
+      for (int i = threadIdx.x; i < n; i += kIT) dg[i] = p.diag(it, i);
+      __syncthreads();
+    }
+  }
+  for (int c = 0; c < nck; ++c) {
+    double* const LA = lds[buf][0];
+    double* const LB = SAME ? LA : lds[buf][1];
+    istash<P::KA, kIN, 0, typename P::TA>(LA, ra, P::DIAG_A ? dg : nullptr, c * kIKC, n);
+    if constexpr (!SAME) istash<KB, B::BW * 16, B::BC0 * 16, typename P::TB>(LB, rb, P::DIAG_B ? dg : nullptr, c * kIKC, n);
+    __syncthreads();
+    if (c + 1 < nck) {
+      ifetch_pass<P, PS>(ra, rb, p, it, item, (c + 1) * kIKC);
+    } else if constexpr (PS + 1 < P::NPASS) {
+      ifetch_pass<P, (PS + 1 < P::NPASS ? PS + 1 : 0)>(ra, rb, p, it, item, 0);
+    } else if (i + (int)gridDim.x < n_items) {
+      const int nx = sel ? sel[i + gridDim.x] : i + gridDim.x;
+      ifetch_pass<P, 0>(ra, rb, p, items[nx], nx, 0);
+    }
+    const int qn = (n - c * kIKC + 3) >> 2 < kIKC / 4 ? (n - c * kIKC + 3) >> 2 : kIKC / 4;
+#pragma unroll 1
+    for (int q = 0; q < qn; ++q) {
+      const double a = LA[oa + ipan_kstep<P::KA>(q)];
+      const double* const Lq = LB + ipan_kstep<KB>(q);
+#pragma unroll
+      for (int j = 0; j < B::NC; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Lq[ob[j]], acc[j], 0, 0, 0);
+    }
+    if (e_live || x_live) {
+#pragma unroll 1
+      for (int q = 0; q < qn; ++q) {
+        const double a = LA[oa12 + ipan_kstep<P::KA>(q)];
+        const double* const Lq = LB + ipan_kstep<KB>(q);
+        if (e_live) ace = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Lq[obe], ace, 0, 0, 0);
+        if (x_live) acx = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Lq[obx], acx, 0, 0, 0);
+      }
+    }
+    buf ^= 1;
+  }
+  auto put = [&](const d4& v, int br, int bc) {
+    const int col = bc * 16 + li;
+    const double e[4] = {v[0], v[1], v[2], v[3]};  // (a bit_cast of v[r] itself stored v[0] four times)
+    if constexpr (P::OUT == kOutF64 || P::OUT == kOutF32) {
+      // row-major n x n result through buffer stores: a column past n goes
+      // to an offset past the buffer, a row past n lands past it too, and
+      // both are dropped
+      constexpr unsigned SZ = P::OUT == kOutF64 ? 8u : 4u;
+      const __amdgpu_buffer_rsrc_t o = p.template out<PS>(it, item);
+      const unsigned vo = col < n ? (unsigned)((br * 16 + lk) * n + col) * SZ : kOob;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (P::OUT == kOutF64)
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, e[r]), o, vo + (unsigned)(4 * r * n) * SZ,
+                                                0, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)e[r]), o,
+                                                vo + (unsigned)(4 * r * n) * SZ, 0, 0);
+      }
+    } else if constexpr (P::OUT == kOutSym) {
+      // symmetric result: element (row, col) also goes to (col, row); in a
+      // diagonal block only row <= col is stored; dropped stores get an
+      // offset past the buffer
+      const __amdgpu_buffer_rsrc_t o = p.template out<PS>(it, item);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = br * 16 + lk + 4 * r;
+        const bool keep = row < n && col < n && !(br == bc && row > col);
+        const unsigned od = keep ? (unsigned)(row * n + col) * 8u : kOob;
+        const unsigned om = keep ? (unsigned)(col * n + row) * 8u : kOob;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, e[r]), o, od, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, e[r]), o, om, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = br * 16 + lk + 4 * r;
+        if (row < n && col < n) p.template store<PS>(it, item, br == bc, row, col, e[r]);
+      }
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < B::NC; ++j) put(acc[j], w, B::col(w, j));
+  if (e_live) put(ace, kIBlk - 1, B::ce(w));
+  if (x_live) put(acx, kIBlk - 1, kIBlk - 1);
+}
+
+// The work-group's items: sel[i] (or i without a list) for i = blockIdx.x,
+// blockIdx.x + gridDim.x, ... below n_items.
+template <class P>
+__global__ __launch_bounds__(kIT, 1) void igemm_kernel(const ItemDev* __restrict__ items,
+                                                       const int32_t* __restrict__ sel, int n_items, P p) {
+  __shared__ double lds[2][2][kIPanelLds];
+  __shared__ double dg[P::DIAG_A || P::DIAG_B ? kIN : 1];
+  if ((int)blockIdx.x >= n_items) return;
+  typename Mat<typename P::TA>::raw_t ra[kIStage];
+  typename Mat<typename P::TB>::raw_t rb[kIStage];
+  {
+    const int item = sel ? sel[blockIdx.x] : blockIdx.x;
+    ifetch_pass<P, 0>(ra, rb, p, items[item], item, 0);
+  }
+  int buf = 0;
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const int item = sel ? sel[i] : i;
+    const ItemDev it = items[item];
+    ipass<P, 0>(p, items, sel, n_items, i, item, it, lds, dg, buf, ra, rb);
+    ipass<P, 1>(p, items, sel, n_items, i, item, it, lds, dg, buf, ra, rb);
+  }
+}
+
+// Y = V X + H0 X
+template <typename XT>
+struct IgY {
+  using TA = double;
+  using TB = XT;
+  static constexpr bool KA = true, KB = true, DIAG_A = true, DIAG_B = false;
+  static constexpr int OUT = kOutF64, NPASS = 2;
+  static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
+  static constexpr bool same_panel(int) { return false; }
+  const GridDev* grids;
+  const double* v64;
+  const XT* xin;
+  int xin_ws;
+  double* work;
+  __device__ const XT* X(const ItemDev& it) const {
+    return xin_ws ? reinterpret_cast<const XT*>(WS(work, it).P1) : (xin + it.v_off);
+  }
+  // A = V + H0 (H0 added to the staged diagonal); V is symmetric: its rows
+  // are read as the columns of A
+  __device__ Mat<double> viewA(const ItemDev& it, int) const { return col_view(v64 + it.v_off, it.n, it.n); }
+  __device__ double diag(const ItemDev& it, int i) const { return grids[it.grid].e0[i % it.N]; }
+  template <int PS>
+  __device__ Mat<XT> viewB(const ItemDev& it, int) const { return col_view(X(it), it.n, it.n); }
+  template <int PS>
+  __device__ __amdgpu_buffer_rsrc_t out(const ItemDev& it, int) const {
+    return Mat<double>(WS(work, it).Y, (int64_t)it.n * it.n, 0, 0).r;
+  }
+  template <int PS>
+  __device__ void store(const ItemDev&, int, bool, int, int, double) const {}
+};
+// S = X^T Y (pass 0) and G = X^T X (pass 1), symmetric
+template <typename XT>
+struct IgSG {
+  using TA = XT;
+  using TB = double;
+  static constexpr bool KA = true, KB = true, DIAG_A = false, DIAG_B = false;
+  static constexpr int OUT = kOutSym, NPASS = 2;
+  static constexpr int set(int) { return kSetSym; }
+  static constexpr bool same_panel(int ps) { return ps == 1; }
+  const XT* xin;
+  int xin_ws;
+  double* work;
+  __device__ Mat<XT> viewA(const ItemDev& it, int) const {
+    const XT* X = xin_ws ? reinterpret_cast<const XT*>(WS(work, it).P1) : (xin + it.v_off);
+    return col_view(X, it.n, it.n);
+  }
+  template <int PS>
+  __device__ Mat<double> viewB(const ItemDev& it, int) const { return col_view<double>(WS(work, it).Y, it.n, it.n); }
+  __device__ double diag(const ItemDev&, int) const { return 0.0; }
+  template <int PS>
+  __device__ __amdgpu_buffer_rsrc_t out(const ItemDev& it, int) const {
+    const WS ws(work, it);
+    return Mat<double>(PS == 0 ? ws.S : ws.G, (int64_t)it.n * it.n, 0, 0).r;
+  }
+  template <int PS>
+  __device__ void store(const ItemDev&, int, bool, int, int, double) const {}
+};
+// X' = X M (M from form_m_kernel in W5)
+template <typename XT>
+struct IgXM {
+  using TA = XT;
+  using TB = double;
+  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = false;
+  static constexpr int OUT = kOutF64, NPASS = 2;
+  static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
+  static constexpr bool same_panel(int) { return false; }
+  const XT* xin;
+  int xin_ws;
+  double* evec;
+  int xout_ws;
+  double* work;
+  __device__ Mat<XT> viewA(const ItemDev& it, int) const {
+    const XT* X = xin_ws ? reinterpret_cast<const XT*>(WS(work, it).P1) : (xin + it.v_off);
+    return row_view(X, it.n, it.n);
+  }
+  template <int PS>
+  __device__ Mat<double> viewB(const ItemDev& it, int) const { return col_view<double>(WS(work, it).W5, it.n, it.n); }
+  __device__ double diag(const ItemDev&, int) const { return 0.0; }
+  template <int PS>
+  __device__ __amdgpu_buffer_rsrc_t out(const ItemDev& it, int) const {
+    return Mat<double>(xout_ws ? WS(work, it).P1 : (evec + it.v_off), (int64_t)it.n * it.n, 0, 0).r;
+  }
+  template <int PS>
+  __device__ void store(const ItemDev&, int, bool, int, int, double) const {}
+};
+
+// Warm start of the LDS Jacobi: Z = Q0^T H for a warm item (Q0: its
+// reference's eigenvectors, column-major floats at the reference's
+// work-space), i.e. Z[i][j] = (H Q0)[j][i], stored as floats row-major =
+// H Q0 column-major in the item's x32.  The FP64 matrix cores take V + H0
+// (H0 added to the staged diagonal of B).
+struct IgWarm {
+  using TA = float;
+  using TB = double;
+  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = true;
+  static constexpr int OUT = kOutF32, NPASS = 2;
+  static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
+  static constexpr bool same_panel(int) { return false; }
+  const ItemDev* items;
+  const int32_t* ref;
+  const GridDev* grids;
+  const double* v64;
+  float* x32;
+  const double* work;
+  __device__ const float* Q0(int item) const { return reinterpret_cast<const float*>(work + items[ref[item]].w_off); }
+  // A(i, k) = Q0[i n + k] (row i of A = column i of Q0)
+  __device__ Mat<float> viewA(const ItemDev& it, int item) const { return row_view(Q0(item), it.n, it.n); }
+  template <int PS>
+  __device__ Mat<double> viewB(const ItemDev& it, int) const { return col_view(v64 + it.v_off, it.n, it.n); }
+  __device__ double diag(const ItemDev& it, int i) const { return grids[it.grid].e0[i % it.N]; }
+  template <int PS>
+  __device__ __amdgpu_buffer_rsrc_t out(const ItemDev& it, int) const {
+    return Mat<float>(x32 + it.v_off, (int64_t)it.n * it.n, 0, 0).r;
+  }
+  template <int PS>
+  __device__ void store(const ItemDev&, int, bool, int, int, double) const {}
+};
+
 }  // namespace
 
-hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
-                         const float* x32, double* evec, double* eval, double* lam_pre, double* work, int32_t* cl,
-                         int32_t* status, int steps, int close_log10, hipStream_t s) {
+hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n, const GridDev* grids,
+                         const double* v64, const float* x32, double* evec, double* eval, double* lam_pre,
+                         double* work, int32_t* cl, int32_t* status, int steps, int close_log10, int gemm,
+                         hipStream_t s) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
   const int nt = (max_n + kTM - 1) / kTM;  // 64-row blocks of form_m
   const int nt2 = (max_n + T64::TM - 1) / T64::TM;  // GEMM tiles
   const int tiles = nt2 * nt2, up_tiles = nt2 * (nt2 + 1) / 2;
+  // whole-item products when every item has 193..208 rows (unless tiles are asked for)
+  const bool whole = gemm == 0 && min_n >= kINMin && max_n <= kIN;
+  unsigned ig = 0;  // persistent grid: one work-group per CU
+  if (whole) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    ig = (unsigned)(n_items < cus ? n_items : cus);
+  }
   int cur_ws = 0;  // X in the caller's evec (0) or in the work-space P1 (1); step 0 reads x32
   for (int st = 0; st < steps; ++st) {
     const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
     double closec = 1.0;
     for (int q = 0; q < close_log10 + st; ++q) closec *= 10.0;
-    if (st == 0) {
+    if (whole) {
+      if (st == 0) {
+        hipLaunchKernelGGL(igemm_kernel<IgY<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
+                           IgY<float>{grids, v64, x32, 0, work});
+        hipLaunchKernelGGL(igemm_kernel<IgSG<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
+                           IgSG<float>{x32, 0, work});
+      } else {
+        hipLaunchKernelGGL(igemm_kernel<IgY<double>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
+                           IgY<double>{grids, v64, (const double*)evec, cur_ws, work});
+        hipLaunchKernelGGL(igemm_kernel<IgSG<double>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
+                           IgSG<double>{(const double*)evec, cur_ws, work});
+      }
+    } else if (st == 0) {
       hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          grids, v64, x32, 0, work, tiles);
       hipLaunchKernelGGL(gemm_sg_kernel<float>, dim3(xcd_grid(up_tiles, n_items)), dim3(T64::NT), 0, s, items,
@@ -1097,7 +1501,14 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int max_n, const Gri
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work, cl, closec);
     }
-    if (st == 0)
+    if (whole) {
+      if (st == 0)
+        hipLaunchKernelGGL(igemm_kernel<IgXM<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
+                           IgXM<float>{x32, 0, evec, out_ws, work});
+      else
+        hipLaunchKernelGGL(igemm_kernel<IgXM<double>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
+                           IgXM<double>{(const double*)evec, cur_ws, evec, out_ws, work});
+    } else if (st == 0)
       hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          x32, 0, evec, out_ws, work, tiles);
     else
@@ -1132,11 +1543,20 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
 namespace wpcd {
 
 hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, int n_refs, const int32_t* warm,
-                                   int n_warm, const int32_t* ref, int max_n, const GridDev* grids,
+                                   int n_warm, const int32_t* ref, int min_n, int max_n, const GridDev* grids,
                                    const double* v64, float* x32, double* work, hipStream_t s) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
   if (n_refs == 0 || n_warm == 0) return hipSuccess;
   hipLaunchKernelGGL(warm_q0_kernel, dim3(n_refs), dim3(kBlock), 0, s, items, refs, x32, work);
+  if (min_n >= kINMin && max_n <= kIN) {  // whole-item products, one work-group per CU
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(igemm_kernel<IgWarm>, dim3(n_warm < cus ? n_warm : cus), dim3(kIT), 0, s, items, warm, n_warm,
+                       IgWarm{items, ref, grids, v64, x32, work});
+    return hipGetLastError();
+  }
   const int nt = (max_n + T64::TM - 1) / T64::TM;
   hipLaunchKernelGGL(warm_y_kernel, dim3(xcd_grid(nt * nt, n_warm)), dim3(T64::NT), 0, s, items, warm, n_warm, ref,
                      grids, v64, x32, work, nt * nt);

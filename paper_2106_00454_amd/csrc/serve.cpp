@@ -192,7 +192,7 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
   s.d_off.assign(ni, 0);
   s.m_off.assign(ni, 0);
   int class_ptr[kNumClasses + 1] = {0}, class_maxn[kNumClasses] = {0};
-  int max_n = 0, max_nbins = 0;
+  int max_n = 0, min_n = 0, max_nbins = 0;
   if (s.err == hipSuccess) {
     char* P = s.pinned;
     ItemDev* items = reinterpret_cast<ItemDev*>(P + L.items);
@@ -243,6 +243,7 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
         c += ch.n_terms;
         w += eig_work_doubles(ch.n);
         max_n = std::max(max_n, ch.n);
+        min_n = min_n == 0 ? ch.n : std::min(min_n, ch.n);
         max_nbins = std::max(max_nbins, ch.N);
         class_ptr[size_class(ch.n) + 1]++;
         class_maxn[size_class(ch.n)] = std::max(class_maxn[size_class(ch.n)], ch.n);
@@ -298,8 +299,8 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
                                nullptr, s.stream);
   }
   if (e == hipSuccess)
-    e = launch_refine(d_items, n, max_n, d_grids, d_v64, d_x32, d_evec, d_eval, d_lam, d_work, d_cl, d_est,
-                      std::max(1, c.refine_steps), c.refine_close_log10, s.stream);
+    e = launch_refine(d_items, n, min_n, max_n, d_grids, d_v64, d_x32, d_evec, d_eval, d_lam, d_work, d_cl, d_est,
+                      std::max(1, c.refine_steps), c.refine_close_log10, c.refine_gemm, s.stream);
   if (e == hipSuccess)
     e = launch_tmatrix(d_items, n, max_n, d_grids, d_v64, d_eval, d_evec, WPCD_MIXED, d_t, d_tst, s.stream);
   if (e == hipSuccess) e = launch_observables(d_items, n, max_nbins, d_grids, d_t, d_delta, d_mix, d_sdev, s.stream);

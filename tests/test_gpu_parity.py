@@ -221,3 +221,57 @@ def test_warm_started_jacobi_matches_oracle_and_cold_start():
         it = item_view(bw, hw, s)
         sig_ref = oo.sigma_tot([(0, ref["delta"], None)], kbar, TLAB, k[-1])
         check_item(f"warm start s={s}", it, ref, k, wp.MIXED, 0, sig_ref, hw["sigma"][s])
+
+
+# ------------------------------------ whole-item refinement products
+def test_whole_item_products_match_tiles_and_oracle():
+    # batches whose items all have 193..208 rows take the whole-item products
+    # of the refinement (one work-group per item, persistent over the items,
+    # wpcd_config.refine_gemm = 0); ragged and odd n, more items than compute
+    # units so work-groups move on to items of another size; the same batch
+    # with 64 x 64 tiles (refine_gemm = 1) must agree, and both the oracle
+    specs = [("yam", 193, 1), ("cyuk", 100, 2), ("yam", 203, 1), ("cyuk", 104, 2), ("yam", 197, 1),
+             ("cyuk", 97, 2)]
+    n_items = 264
+    res = {}
+    for mode_g in (0, 1):
+        c = wp.Context(0, refine_gemm=mode_g)
+        gs = {}
+        items, mats = [], []
+        for s in range(n_items):
+            kind, N, K = specs[s % len(specs)]
+            if N not in gs:
+                gs[N] = c.grid(configs.grid("coupled_yukawa") if N == 100 else grids.tan2_bounded(N), 8)
+            g = gs[N]
+            if kind == "yam":
+                mats.append(potentials.yamaguchi(g.nodes, g.nodes, configs.yamaguchi_lambda(s), 1.4))
+                items.append((g, 1, 0, s))
+            else:
+                cf = configs.yukawa_coefficients(300 + s)
+                mats.append(sum(ci * ti for ci, ti in zip(cf, configs.coupled_yukawa_terms(g.nodes))))
+                items.append((g, 2, 1, s))
+        b, host = run_items(c, items, mats, wp.MIXED)
+        assert (host["eig_status"] > 0).all() and (host["t_status"] == 0).all()
+        res[mode_g] = (b, host)
+    (bw, hw), (bt, ht) = res[0], res[1]
+    assert dmod180(hw["delta"], ht["delta"]).max() <= 1e-6
+    assert np.abs(hw["mix"] - ht["mix"]).max() <= 1e-6
+    assert np.abs(hw["sigma"] - ht["sigma"]).max() <= 1e-6
+    for s in list(range(len(specs))) + [256, 257, 263]:
+        kind, N, K = specs[s % len(specs)]
+        k = configs.grid("coupled_yukawa") if N == 100 else grids.tan2_bounded(N)
+        xo, _ = ow.gauss_nodes(k, 8)
+        if kind == "yam":
+            uo, J = potentials.yamaguchi(xo, xo, configs.yamaguchi_lambda(s), 1.4), 0
+        else:
+            cf = configs.yukawa_coefficients(300 + s)
+            uo, J = sum(ci * ti for ci, ti in zip(cf, configs.coupled_yukawa_terms(xo))), 1
+        ref = oracle_item(k, uo, K)
+        _, kbar, _ = ow.bins(k)
+        sig_ref = oo.sigma_tot([(J, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
+        for tag, (b, host) in (("whole", (bw, hw)), ("tiles", (bt, ht))):
+            it = item_view(b, host, s)
+            iw = item_view(bw, hw, s)
+            assert np.abs(it["evals"] - iw["evals"]).max() <= 1e-10 * np.abs(iw["evals"]).max()
+            check_item(f"refine products={tag} s={s} n={it['v'].shape[0]}", it, ref, k, wp.MIXED, J, sig_ref,
+                       host["sigma"][s])
