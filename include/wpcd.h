@@ -117,8 +117,11 @@ typedef struct {
                             first ones (up to one per compute unit and size
                             class, each group's first among them) start from
                             the columns of B in descending norm order, the
-                            others from B Q0 with Q0 the eigenvectors of
-                            their group's first item (fewer sweeps when the
+                            others from B Q0 with Q0 the eigenvectors of a
+                            cold item of their group: in the LDS-resident
+                            sizes the one whose V is nearest to theirs on a
+                            strided sample of 1024 entries, in device memory
+                            the group's first (fewer sweeps when the
                             potentials are alike); 1 cold: every item starts
                             from B.  Results agree within the refinement's
                             accuracy either way.                             */

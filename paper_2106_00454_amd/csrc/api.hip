@@ -245,6 +245,9 @@ void wpcd_batch_destroy(wpcd_batch b) {
   hipFree(b->d_class);
   hipFree(b->d_jlist);
   hipFree(b->d_ref);
+  hipFree(b->d_cand);
+  hipFree(b->d_pick);
+  hipFree(b->d_sig);
   hipFree(b->d_bases);
   delete b;
 }
@@ -355,6 +358,8 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   constexpr int L = wpcd_batch_s::kC;
   std::vector<int32_t> ref(n_items, -1);
   std::vector<int32_t> seg[2 * L + 1];
+  std::vector<int32_t> cand, pick;  // reference candidates and pick tasks (jlist offsets relative to the class)
+  std::vector<int> pick_cls;
   {
     int n_cu = 256;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n_cu < 1)
@@ -382,6 +387,32 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
           seg[L + c].push_back(i);
         }
       }
+      if (c < L - 1 && !seg[L + c].empty()) {
+        // LDS classes: the warm items of a group take the group's cold item
+        // nearest in V (chosen on the device; ref[] keeps the group's first
+        // item until then); warm items ordered by group, in runs of <= 16
+        std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> cold_of, warm_of;
+        for (int32_t i : seg[c]) {
+          const ItemDev& d = b->h_items[i];
+          cold_of[std::make_tuple(d.grid, d.nch, d.J, d.basis)].push_back(i);
+        }
+        for (int32_t i : seg[L + c]) {
+          const ItemDev& d = b->h_items[i];
+          warm_of[std::make_tuple(d.grid, d.nch, d.J, d.basis)].push_back(i);
+        }
+        seg[L + c].clear();
+        for (auto& kv : warm_of) {
+          const std::vector<int32_t>& cl_items = cold_of[kv.first];
+          const int coff = (int)cand.size();
+          cand.insert(cand.end(), cl_items.begin(), cl_items.end());
+          for (size_t w0 = 0; w0 < kv.second.size(); w0 += kWarmPick) {
+            const int cnt = (int)std::min<size_t>(kWarmPick, kv.second.size() - w0);
+            pick.insert(pick.end(), {(int32_t)(seg[L + c].size() + w0), cnt, coff, (int32_t)cl_items.size()});
+            pick_cls.push_back(c);
+          }
+          seg[L + c].insert(seg[L + c].end(), kv.second.begin(), kv.second.end());
+        }
+      }
     }
     for (int c = 0; c < L; ++c)
       for (int32_t i : seg[L + c]) {
@@ -395,6 +426,11 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
         is_ref[ref[i]] = 1;
         seg[2 * L].push_back(ref[i]);
       }
+    for (int32_t i : cand)
+      if (!is_ref[i]) {
+        is_ref[i] = 1;
+        seg[2 * L].push_back(i);
+      }
   }
   std::vector<int32_t> jlist;
   for (int t = 0; t <= 2 * L; ++t) {
@@ -402,6 +438,8 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     jlist.insert(jlist.end(), seg[t].begin(), seg[t].end());
   }
   b->jl_ptr[2 * L + 1] = (int)jlist.size();
+  for (size_t t = 0; t < pick_cls.size(); ++t) pick[4 * t] += b->jl_ptr[L + pick_cls[t]];
+  b->n_pick = (int)pick_cls.size();
   std::vector<GridDev> gd(ctx->grids.size());
   for (size_t i = 0; i < gd.size(); ++i) gd[i] = ctx->grids[i].dev;
   hipError_t e = hipSuccess;
@@ -419,6 +457,9 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   alloc((void**)&b->d_class, sizeof(int32_t) * n_items);
   alloc((void**)&b->d_jlist, sizeof(int32_t) * jlist.size());
   alloc((void**)&b->d_ref, sizeof(int32_t) * n_items);
+  alloc((void**)&b->d_cand, sizeof(int32_t) * cand.size());
+  alloc((void**)&b->d_pick, sizeof(int32_t) * pick.size());
+  alloc((void**)&b->d_sig, b->n_pick > 0 ? sizeof(float) * kWarmSig * (size_t)n_items : 0);
   std::vector<BasisDev> bd(ctx->bases.size());
   for (size_t i = 0; i < bd.size(); ++i) bd[i] = BasisDev{ctx->bases[i].dbuf, ctx->bases[i].n, ctx->bases[i].n_terms};
   alloc((void**)&b->d_bases, sizeof(BasisDev) * bd.size());
@@ -434,6 +475,10 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   if (e == hipSuccess && !jlist.empty())
     e = hipMemcpy(b->d_jlist, jlist.data(), sizeof(int32_t) * jlist.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_ref, ref.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !cand.empty())
+    e = hipMemcpy(b->d_cand, cand.data(), sizeof(int32_t) * cand.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !pick.empty())
+    e = hipMemcpy(b->d_pick, pick.data(), sizeof(int32_t) * pick.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     wpcd_batch_destroy(b);
     return hip_fail(e, "wpcd_batch_create");
@@ -592,10 +637,11 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
       if (n_warm > 0) {
         WPCD_HIP(timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
                        [&] {
-                         return launch_jacobi_warm_prep(b->d_items, b->d_jlist + b->jl_ptr[2 * L],
+                         return launch_jacobi_warm_prep(b->d_items, b->n_items, b->d_jlist + b->jl_ptr[2 * L],
                                                         b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L],
                                                         b->d_jlist + b->jl_ptr[L], n_warm, b->d_ref,
-                                                        b->warm_min_n, b->warm_max_n, b->d_grids, v64, b->d_x32,
+                                                        b->warm_min_n, b->warm_max_n, b->d_jlist, b->d_pick,
+                                                        b->n_pick, b->d_cand, b->d_sig, b->d_grids, v64, b->d_x32,
                                                         b->d_work, stream);
                        }),
                  "wpcd_eigh: warm-start preparation launch");

@@ -72,5 +72,13 @@ struct wpcd_batch_s {
   int32_t* d_jlist = nullptr;
   int32_t* d_ref = nullptr;
   int jl_ptr[2 * kC + 2] = {0};
+  // reference choice of the LDS-class warm items (on the device, from a
+  // strided sample of V): d_cand holds each group's cold items, d_pick one
+  // task per run of up to 16 warm items of one group (jlist offset, count,
+  // candidate offset, count), d_sig the samples (kWarmSig floats per item)
+  int32_t* d_cand = nullptr;
+  int32_t* d_pick = nullptr;
+  float* d_sig = nullptr;
+  int n_pick = 0;
 };
 

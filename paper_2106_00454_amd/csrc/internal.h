@@ -80,10 +80,18 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
 // writes each reference's eigenvectors, columns in descending eigenvalue
 // order, column-major as floats into the reference's work-space, then
 // H Q0 of every warm item, column-major FP32, into the item's x32 (min_n,
-// max_n: the warm items' smallest and largest n).
-hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, int n_refs, const int32_t* warm,
-                                   int n_warm, const int32_t* ref, int min_n, int max_n, const GridDev* grids,
-                                   const double* v64, float* x32, double* work, hipStream_t s);
+// max_n: the warm items' smallest and largest n).  Before that, each pick
+// task (jlist offset, count, candidate offset, count; n_pick of them) sets
+// ref[] of up to kWarmPick warm items of one group to the candidate whose V
+// is nearest to theirs on a strided sample of kWarmSig entries (sig: kWarmSig
+// floats per item of the batch, n_items of them).
+constexpr int kWarmPick = 16;
+constexpr int kWarmSig = 1024;
+hipError_t launch_jacobi_warm_prep(const ItemDev* items, int n_items, const int32_t* refs, int n_refs,
+                                   const int32_t* warm, int n_warm, int32_t* ref, int min_n, int max_n,
+                                   const int32_t* jlist, const int32_t* pick, int n_pick, const int32_t* cand,
+                                   float* sig, const GridDev* grids, const double* v64, float* x32, double* work,
+                                   hipStream_t s);
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,

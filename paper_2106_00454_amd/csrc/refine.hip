@@ -964,6 +964,101 @@ __global__ __launch_bounds__(kBlock) void warm_q0_kernel(const ItemDev* __restri
   }
 }
 
+// Reference choice of the warm starts.  The iteration from W = B Q0 needs
+// fewer sweeps the closer the reference's H is to the item's (a NumPy model
+// of the coupled batch: 3.1 instead of 3.8 sweeps when the nearest of 64
+// cold items in Frobenius norm replaces the first one), and a strided sample
+// of kWarmSig entries of V picks the same nearest item there.
+// Sample of V per item: entry s * stride, stride = n^2 / min(n^2, kWarmSig)
+// (all entries of small items; zero-filled to kWarmSig).  One work-group per
+// item of the batch.
+__global__ __launch_bounds__(kBlock) void warm_sig_kernel(const ItemDev* __restrict__ items,
+                                                         const double* __restrict__ v64, float* __restrict__ sig) {
+  const ItemDev it = items[blockIdx.x];
+  const int64_t nn = (int64_t)it.n * it.n;
+  const int cnt = nn < kWarmSig ? (int)nn : kWarmSig;
+  const int64_t stride = nn / cnt;
+  float* out = sig + (int64_t)blockIdx.x * kWarmSig;
+  for (int q = threadIdx.x; q < kWarmSig; q += kBlock) out[q] = q < cnt ? (float)v64[it.v_off + q * stride] : 0.0f;
+}
+
+// One work-group per pick task: the task's warm items' samples in LDS, the
+// threads over the group's candidates, squared distances of the samples; the
+// nearest candidate (ties: the earlier in the list) becomes the reference.
+__global__ __launch_bounds__(kBlock) void warm_pick_kernel(const int32_t* __restrict__ pick,
+                                                          const int32_t* __restrict__ jlist,
+                                                          const int32_t* __restrict__ cand,
+                                                          const float* __restrict__ sig, int32_t* __restrict__ ref) {
+  __shared__ float4 ws[kWarmPick][kWarmSig / 4];
+  __shared__ float rd[kBlock / 64][kWarmPick];
+  __shared__ int ri[kBlock / 64][kWarmPick];
+  const int woff = pick[4 * blockIdx.x], wcnt = pick[4 * blockIdx.x + 1];
+  const int coff = pick[4 * blockIdx.x + 2], ccnt = pick[4 * blockIdx.x + 3];
+  for (int e = threadIdx.x; e < kWarmPick * kWarmSig / 4; e += kBlock) {
+    const int w = e / (kWarmSig / 4), q = e - w * (kWarmSig / 4);
+    ws[w][q] = w < wcnt ? reinterpret_cast<const float4*>(sig + (int64_t)jlist[woff + w] * kWarmSig)[q]
+                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  __syncthreads();
+  float best[kWarmPick];
+  int bi[kWarmPick];
+#pragma unroll
+  for (int w = 0; w < kWarmPick; ++w) {
+    best[w] = INFINITY;
+    bi[w] = 0x7fffffff;
+  }
+  for (int c = threadIdx.x; c < ccnt; c += kBlock) {
+    const float4* sc = reinterpret_cast<const float4*>(sig + (int64_t)cand[coff + c] * kWarmSig);
+    float d[kWarmPick];
+#pragma unroll
+    for (int w = 0; w < kWarmPick; ++w) d[w] = 0.0f;
+    for (int q4 = 0; q4 < kWarmSig / 4; ++q4) {
+      const float4 x = sc[q4];
+#pragma unroll
+      for (int w = 0; w < kWarmPick; ++w) {
+        const float4 y = ws[w][q4];
+        const float a = y.x - x.x, b = y.y - x.y, cc = y.z - x.z, dd = y.w - x.w;
+        d[w] = fmaf(a, a, fmaf(b, b, fmaf(cc, cc, fmaf(dd, dd, d[w]))));
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < kWarmPick; ++w)
+      if (d[w] < best[w]) {  // c grows per thread: ties keep the earlier candidate
+        best[w] = d[w];
+        bi[w] = c;
+      }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int w = 0; w < kWarmPick; ++w) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const float od = __shfl_xor(best[w], off, 64);
+      const int oi = __shfl_xor(bi[w], off, 64);
+      if (od < best[w] || (od == best[w] && oi < bi[w])) {
+        best[w] = od;
+        bi[w] = oi;
+      }
+    }
+    if (lane == 0) {
+      rd[wave][w] = best[w];
+      ri[wave][w] = bi[w];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < wcnt) {
+    const int w = threadIdx.x;
+    float bd = rd[0][w];
+    int bx = ri[0][w];
+    for (int v = 1; v < kBlock / 64; ++v)
+      if (rd[v][w] < bd || (rd[v][w] == bd && ri[v][w] < bx)) {
+        bd = rd[v][w];
+        bx = ri[v][w];
+      }
+    if (bx < ccnt) ref[jlist[woff + w]] = cand[coff + bx];
+  }
+}
+
 // H Q0 for every warm item (its reference's Q0), column-major FP32 into the
 // item's x32, where the Jacobi kernel reads it as the start of W.  The result
 // only seeds an FP32 iteration, so the product runs on the FP32 matrix cores
@@ -1542,11 +1637,17 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
 
 namespace wpcd {
 
-hipError_t launch_jacobi_warm_prep(const ItemDev* items, const int32_t* refs, int n_refs, const int32_t* warm,
-                                   int n_warm, const int32_t* ref, int min_n, int max_n, const GridDev* grids,
-                                   const double* v64, float* x32, double* work, hipStream_t s) {
+hipError_t launch_jacobi_warm_prep(const ItemDev* items, int n_items, const int32_t* refs, int n_refs,
+                                   const int32_t* warm, int n_warm, int32_t* ref, int min_n, int max_n,
+                                   const int32_t* jlist, const int32_t* pick, int n_pick, const int32_t* cand,
+                                   float* sig, const GridDev* grids, const double* v64, float* x32, double* work,
+                                   hipStream_t s) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
   if (n_refs == 0 || n_warm == 0) return hipSuccess;
+  if (n_pick > 0) {
+    hipLaunchKernelGGL(warm_sig_kernel, dim3(n_items), dim3(kBlock), 0, s, items, v64, sig);
+    hipLaunchKernelGGL(warm_pick_kernel, dim3(n_pick), dim3(kBlock), 0, s, pick, jlist, cand, (const float*)sig, ref);
+  }
   hipLaunchKernelGGL(warm_q0_kernel, dim3(n_refs), dim3(kBlock), 0, s, items, refs, x32, work);
   if (min_n >= kINMin && max_n <= kIN) {  // whole-item products, one work-group per CU
     int dev = 0, cus = 0;
