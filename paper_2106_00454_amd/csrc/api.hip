@@ -142,9 +142,12 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   ctx->cfg = c;
   hipError_t e = hipMalloc((void**)&ctx->d_counters, 4 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(ctx->d_counters, 0, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
   if (e != hipSuccess) {
     wpcd_destroy(ctx);
-    return hip_fail(e, "wpcd_create: counters");
+    return hip_fail(e, "wpcd_create: counters, side stream, events");
   }
   *out = ctx;
   return WPCD_OK;
@@ -161,6 +164,12 @@ void wpcd_destroy(wpcd_ctx ctx) {
   for (auto& g : ctx->grids) hipFree(g.dbuf);
   for (auto& bs : ctx->bases) hipFree(bs.dbuf);
   hipFree(ctx->d_counters);
+  if (ctx->side) {
+    hipStreamSynchronize(ctx->side);
+    hipStreamDestroy(ctx->side);
+  }
+  if (ctx->fork) hipEventDestroy(ctx->fork);
+  if (ctx->join) hipEventDestroy(ctx->join);
   delete ctx;
 }
 
@@ -653,7 +662,8 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                      return launch_refine(b->d_items, b->n_items, b->min_n, b->max_n, b->d_grids, v64, b->d_x32,
                                           evec, eval,
                                           b->d_lam, b->d_work, b->d_cl, status, c.refine_steps,
-                                          c.refine_close_log10, c.refine_gemm, stream);
+                                          c.refine_close_log10, c.refine_gemm, stream, b->ctx->side,
+                                          b->ctx->fork, b->ctx->join);
                    }),
              "wpcd_eigh: FP64 refinement launch");
   } else {

@@ -40,6 +40,9 @@ struct wpcd_context {
   double stage_ms[WPCD_N_STAGES] = {0};
   int64_t stage_launches[WPCD_N_STAGES] = {0};
   unsigned long long* d_counters = nullptr;  // LDS Jacobi work counters (while profiling)
+  // second stream of the refinement (default priority) and its fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct wpcd_batch_s {

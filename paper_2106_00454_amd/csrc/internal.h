@@ -103,11 +103,13 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
                                const double* v64, double* work, double* evec, double* eval, int32_t* status,
                                hipStream_t s);
 // gemm: 0 = whole-item products when every item has 193..208 rows, else
-// 64 x 64 tiles; 1 = tiles
+// 64 x 64 tiles; 1 = tiles.  side (with two events, or nullptr): a second
+// stream on which part of each step runs concurrently; the work on s waits
+// for it before going on.
 hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n, const GridDev* grids,
                          const double* v64, const float* x32, double* evec, double* eval, double* lam_pre,
                          double* work, int32_t* cl, int32_t* status, int steps, int close_log10, int gemm,
-                         hipStream_t s);
+                         hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join);
 hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                           const double* eval, const double* evec, int mode, double* t, int32_t* status,
                           hipStream_t s);

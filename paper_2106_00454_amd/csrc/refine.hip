@@ -370,39 +370,44 @@ __global__ __launch_bounds__(T64::NT) void gemm_sg_kernel(const ItemDev* __restr
   });
 }
 
-// M = I + E except chain columns (cl[j] >= 0), which are column cl[j] of
-// P Q (n x T in W6), written row-major to W5.  lam_pre holds the Rayleigh
-// quotients E was built from.  Grid: x = blocks of 64 rows, y = item.
+// Columns of M = I + E outside chains, row-major into W6 (the chain kernel
+// writes the chain columns, possibly at the same time on another stream).
+// cl holds reach[p] from refine_reach_kernel: column j lies in a chain iff
+// some interval [p, reach[p]] with reach[p] > p covers it, i.e. reach[j] > j
+// or max_{p<j} reach[p] >= j.  lam_pre holds the Rayleigh quotients E was
+// built from.  Grid: x = blocks of 64 rows, y = item.
 __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restrict__ items, int item0,
                                                         const double* __restrict__ lam_pre, double* work,
                                                         const int32_t* __restrict__ cl, double closec) {
   __shared__ double lam[kMaxN];
-  __shared__ int cpos[kMaxN];
-  __shared__ int s_T;
+  __shared__ int rch[kMaxN];
+  __shared__ unsigned char inch[kMaxN];
   const ItemDev it = items[item0 + blockIdx.y];
   const int n = it.n;
   const int r0 = blockIdx.x * kTM;
   if (r0 >= n) return;
   const WS ws(work, it);
-  if (threadIdx.x == 0) s_T = 0;
-  __syncthreads();
   for (int i = threadIdx.x; i < n; i += kBlock) {
     lam[i] = lam_pre[it.e_off + i];
-    cpos[i] = cl[it.e_off + i];
-    if (cpos[i] >= 0) atomicMax(&s_T, cpos[i] + 1);
+    rch[i] = cl[it.e_off + i];
   }
   __syncthreads();
-  const int T = s_T;
+  if (threadIdx.x == 0) {
+    int cover = -1;
+    for (int j = 0; j < n; ++j) {
+      inch[j] = (rch[j] > j || cover >= j) ? 1 : 0;
+      cover = rch[j] > cover ? rch[j] : cover;
+    }
+  }
+  __syncthreads();
   const int r1 = min(n, r0 + kTM);
   for (int64_t e = threadIdx.x; e < (int64_t)(r1 - r0) * n; e += kBlock) {
     const int k = r0 + (int)(e / n), j = (int)(e % n);
-    const int q = cpos[j];
-    ws.W5[(int64_t)k * n + j] =
-        q >= 0 ? ws.W6[(int64_t)k * T + q] : (k == j ? 1.0 : 0.0) + newton_e(ws.S, ws.G, lam, n, k, j, closec);
+    if (!inch[j]) ws.W6[(int64_t)k * n + j] = (k == j ? 1.0 : 0.0) + newton_e(ws.S, ws.G, lam, n, k, j, closec);
   }
 }
 
-// X' = X M with M from form_m_kernel (W5).
+// X' = X M with M in W6 (form_m_kernel and refine_chain_kernel).
 template <typename XT>
 __global__ __launch_bounds__(T64::NT, 3) void gemm_xm_kernel(const ItemDev* __restrict__ items, int n_items,
                                                          const XT* xin, int xin_ws, double* evec, int xout_ws,
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(T64::NT, 3) void gemm_xm_kernel(const ItemDev* __re
   const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
   double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
   d4 acc[2][2];
-  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, row_view(X, n, n), col_view<double>(ws.W5, n, n), acc);
+  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, row_view(X, n, n), col_view<double>(ws.W6, n, n), acc);
   tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
 }
 
@@ -533,12 +538,12 @@ __device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short
 // are processed in batches of whole chains with at most kMaxChain columns;
 // for a batch with columns cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb),
 // P^T S P -> LDS (kept block-diagonal, one block per chain), one-sided Jacobi,
-// Q -> LDS, and P Q -> columns [pos, pos + Tb) of the n x Ttot matrix in W6.
+// Q -> LDS, and P Q -> the batch's columns of M (n x n, W6).
 // Longer chains (dense parts of the spectrum of large items) are solved one
 // at a time in device memory: P -> W5, S P -> Y, P^T S P -> W7 (m x m), FP64
-// one-sided Jacobi on W7, the sorted Q -> Y, P Q -> W6.  Writes the quotients
-// to lam_pre, the refined eigenvalues to eval, and cl[j] = position of column
-// j among all chain columns, or -1.
+// one-sided Jacobi on W7, the sorted Q -> Y, P Q -> their columns of M.
+// Writes the refined eigenvalues to eval (the Rayleigh quotients outside
+// chains); the other columns of M come from form_m_kernel.
 __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* __restrict__ items,
                                                               double* __restrict__ lam_pre,
                                                               double* __restrict__ eval, double* work,
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   __shared__ short big_start[kMaxBig], big_len[kMaxBig], big_pos[kMaxBig];
   __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
   __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
-  __shared__ int s_Ttot, s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail, s_nbig, s_nbt;
+  __shared__ int s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail, s_nbig, s_nbt;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
   const WS ws(work, it);
@@ -601,8 +606,10 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
         big_len[nbig] = (short)m;
         ++nbig;
       } else {
-        if (m > kMaxChain) fail = 1;  // more long chains than the list holds
-        for (int t = 0; t < m; ++t) reach[i + t] = -1;
+        // a single column, or a long chain beyond the list (-2: its columns
+        // get I + E below, the item is flagged)
+        if (m > kMaxChain) fail = 1;
+        for (int t = 0; t < m; ++t) reach[i + t] = m > kMaxChain ? -2 : -1;
       }
       i = j + 1;
     }
@@ -613,7 +620,6 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       for (int t = 0; t < big_len[b]; ++t) reach[big_start[b] + t] = T + t;
       T += big_len[b];
     }
-    s_Ttot = T;
     s_nch = nch;
     s_nbig = nbig;
     s_fail = fail;
@@ -621,13 +627,18 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     s_pos = 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kBlock) cl[it.e_off + i] = reach[i];
-  const int Ttot = s_Ttot;
+  // columns of chains beyond the list: M = I + E (form_m_kernel takes them
+  // for chain columns)
+  if (s_fail)
+    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kBlock) {
+      const int k = (int)(e / n), j = (int)(e - (int64_t)k * n);
+      if (reach[j] == -2) ws.W6[e] = (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j, closec);
+    }
   const int nch = s_nch;
   const int nt = (n + kTM - 1) / kTM;
   double* P = ws.W5;   // n x Tb
   double* SP = ws.Y;   // n x Tb
-  double* MC = ws.W6;  // n x Ttot
+  double* M = ws.W6;  // n x n update matrix (chain columns)
   double* QB = ws.W7;  // Tb x Tb sorted Q of a batch (W7 holds a long chain's matrix later)
   d4 acc[2][2];
   while (true) {
@@ -719,10 +730,10 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       eval[it.e_off + cols[rank]] = lj;
     }
     __syncthreads();
-    // P Q -> chain columns [pos, pos + Tb) of MC
+    // P Q -> the batch's columns of M
     for (int tm = 0; tm < nt; ++tm) {
       gemm_tile<T64>(As, Bs, tm * kTM, 0, n, Tb, Tb, row_view<double>(P, n, Tb), col_view<double>(QB, Tb, Tb), acc);
-      tile_store<T64>(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
+      tile_store<T64>(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { M[(int64_t)r * n + cols[cc]] = v; });
     }
     __syncthreads();
     if (threadIdx.x == 0) s_pos = pos + Tb;
@@ -808,7 +819,7 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       for (int tc = 0; tc < mt; ++tc) {
         gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, n, m, m, row_view<double>(P, n, m), col_view<double>(Q, m, m), acc);
         tile_store<T64>(tm * kTM, tc * kTM, n, m, acc,
-                   [&](int r, int cc, double v) { MC[(int64_t)r * Ttot + pos + cc] = v; });
+                   [&](int r, int cc, double v) { M[(int64_t)r * n + i0 + cc] = v; });
       }
     __syncthreads();
   }
@@ -1472,7 +1483,7 @@ struct IgSG {
   template <int PS>
   __device__ void store(const ItemDev&, int, bool, int, int, double) const {}
 };
-// X' = X M (M from form_m_kernel in W5)
+// X' = X M (M in W6)
 template <typename XT>
 struct IgXM {
   using TA = XT;
@@ -1491,7 +1502,7 @@ struct IgXM {
     return row_view(X, it.n, it.n);
   }
   template <int PS>
-  __device__ Mat<double> viewB(const ItemDev& it, int) const { return col_view<double>(WS(work, it).W5, it.n, it.n); }
+  __device__ Mat<double> viewB(const ItemDev& it, int) const { return col_view<double>(WS(work, it).W6, it.n, it.n); }
   __device__ double diag(const ItemDev&, int) const { return 0.0; }
   template <int PS>
   __device__ __amdgpu_buffer_rsrc_t out(const ItemDev& it, int) const {
@@ -1538,7 +1549,7 @@ struct IgWarm {
 hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n, const GridDev* grids,
                          const double* v64, const float* x32, double* evec, double* eval, double* lam_pre,
                          double* work, int32_t* cl, int32_t* status, int steps, int close_log10, int gemm,
-                         hipStream_t s) {
+                         hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
   const int nt = (max_n + kTM - 1) / kTM;  // 64-row blocks of form_m
   const int nt2 = (max_n + T64::TM - 1) / T64::TM;  // GEMM tiles
@@ -1588,13 +1599,27 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
       hipLaunchKernelGGL(refine_reach_kernel, dim3((max_n + kReachRows - 1) / kReachRows, gy),
                          dim3(64 * kReachRows), 0, s, items + i0, lam_pre, work, cl, closec);
     }
+    // M: the columns outside chains (form_m, streaming S and G) on the side
+    // stream while the chain kernel (latency-bound) writes the chain columns
+    hipStream_t sm = s;
+    if (side != nullptr) {
+      err = hipEventRecord(fork, s);
+      if (err == hipSuccess) err = hipStreamWaitEvent(side, fork, 0);
+      if (err != hipSuccess) return err;
+      sm = side;
+    }
+    for (int i0 = 0; i0 < n_items; i0 += 65535) {
+      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+      hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, sm, items, i0, lam_pre, work, cl, closec);
+    }
     hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
                        status, closec);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    for (int i0 = 0; i0 < n_items; i0 += 65535) {
-      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
-      hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work, cl, closec);
+    if (side != nullptr) {
+      err = hipEventRecord(join, side);
+      if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
+      if (err != hipSuccess) return err;
     }
     if (whole) {
       if (st == 0)

@@ -300,7 +300,8 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
   }
   if (e == hipSuccess)
     e = launch_refine(d_items, n, min_n, max_n, d_grids, d_v64, d_x32, d_evec, d_eval, d_lam, d_work, d_cl, d_est,
-                      std::max(1, c.refine_steps), c.refine_close_log10, c.refine_gemm, s.stream);
+                      std::max(1, c.refine_steps), c.refine_close_log10, c.refine_gemm, s.stream, nullptr, nullptr,
+                      nullptr);
   if (e == hipSuccess)
     e = launch_tmatrix(d_items, n, max_n, d_grids, d_v64, d_eval, d_evec, WPCD_MIXED, d_t, d_tst, s.stream);
   if (e == hipSuccess) e = launch_observables(d_items, n, max_nbins, d_grids, d_t, d_delta, d_mix, d_sdev, s.stream);
