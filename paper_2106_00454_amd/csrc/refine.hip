@@ -880,6 +880,36 @@ __global__ __launch_bounds__(kBlock) void refine_finish_kernel(const ItemDev* __
   if (threadIdx.x == 0 && s_bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
+// Ranks of the refined eigenvalues (ties by index) -> cl, eval sorted in
+// place, a non-finite eigenvalue flagged; the last step's X M then writes
+// every eigenvector straight to its sorted column (whole-item products).
+__global__ __launch_bounds__(kBlock) void refine_rank_kernel(const ItemDev* __restrict__ items,
+                                                             double* __restrict__ eval, int32_t* __restrict__ cl,
+                                                             int32_t* __restrict__ status) {
+  __shared__ double lam[kMaxN];
+  __shared__ int rank[kMaxN];
+  __shared__ int s_bad;
+  const ItemDev it = items[blockIdx.x];
+  const int n = it.n;
+  double* ev = eval + it.e_off;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    lam[i] = ev[i];
+    if (!isfinite(lam[i])) atomicOr(&s_bad, 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    int r = 0;
+    for (int q = 0; q < n; ++q) r += (lam[q] < lam[i] || (lam[q] == lam[i] && q < i)) ? 1 : 0;
+    rank[i] = r;
+    cl[it.e_off + i] = r;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) ev[rank[i]] = lam[i];
+  if (threadIdx.x == 0 && s_bad && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
+}
+
 // ------------------------------------------------- FP64 Jacobi epilogue
 // Y = H X for the normalised columns of the device-memory FP64 Jacobi (column
 // c of X contiguous at ws.P1 + c n, as the iteration stores W); Y column-major
@@ -1294,7 +1324,8 @@ __device__ __forceinline__ void ifetch_pass(typename Mat<typename P::TA>::raw_t 
 
 template <class P, int PS>
 __device__ __forceinline__ void ipass(const P& p, const ItemDev* __restrict__ items, const int32_t* sel,
-                                      int n_items, int i, int item, const ItemDev& it, double (*lds)[2][kIPanelLds], double* dg, int& buf,
+                                      int n_items, int i, int item, const ItemDev& it,
+                                      double (*lds)[2][kIPanelLds], double* dg, int* pm, int& buf,
                                       typename Mat<typename P::TA>::raw_t (&ra)[kIStage],
                                       typename Mat<typename P::TB>::raw_t (&rb)[kIStage]) {
   using B = IBlocks<P::set(PS)>;
@@ -1320,6 +1351,15 @@ __device__ __forceinline__ void ipass(const P& p, const ItemDev* __restrict__ it
     // barrier of the previous item, so none still stages from the old table
     if (PS == 0) {
       for (int i = threadIdx.x; i < n; i += kIT) dg[i] = p.diag(it, i);
+      __syncthreads();
+    }
+  }
+  if constexpr (P::PERM) {
+    // output column permutation (read in the epilogues: wait until the
+    // previous item's are done)
+    if (PS == 0 && p.perm != nullptr) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += kIT) pm[i] = p.perm[it.e_off + i];
       __syncthreads();
     }
   }
@@ -1365,7 +1405,10 @@ __device__ __forceinline__ void ipass(const P& p, const ItemDev* __restrict__ it
       // both are dropped
       constexpr unsigned SZ = P::OUT == kOutF64 ? 8u : 4u;
       const __amdgpu_buffer_rsrc_t o = p.template out<PS>(it, item);
-      const unsigned vo = col < n ? (unsigned)((br * 16 + lk) * n + col) * SZ : kOob;
+      int pc = col;
+      if constexpr (P::PERM)
+        if (p.perm != nullptr && col < n) pc = pm[col];
+      const unsigned vo = col < n ? (unsigned)((br * 16 + lk) * n + pc) * SZ : kOob;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if constexpr (P::OUT == kOutF64)
@@ -1410,6 +1453,7 @@ __global__ __launch_bounds__(kIT, 1) void igemm_kernel(const ItemDev* __restrict
                                                        const int32_t* __restrict__ sel, int n_items, P p) {
   __shared__ double lds[2][2][kIPanelLds];
   __shared__ double dg[P::DIAG_A || P::DIAG_B ? kIN : 1];
+  __shared__ int pm[P::PERM ? kIN : 1];
   if ((int)blockIdx.x >= n_items) return;
   typename Mat<typename P::TA>::raw_t ra[kIStage];
   typename Mat<typename P::TB>::raw_t rb[kIStage];
@@ -1421,8 +1465,8 @@ __global__ __launch_bounds__(kIT, 1) void igemm_kernel(const ItemDev* __restrict
   for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
     const int item = sel ? sel[i] : i;
     const ItemDev it = items[item];
-    ipass<P, 0>(p, items, sel, n_items, i, item, it, lds, dg, buf, ra, rb);
-    ipass<P, 1>(p, items, sel, n_items, i, item, it, lds, dg, buf, ra, rb);
+    ipass<P, 0>(p, items, sel, n_items, i, item, it, lds, dg, pm, buf, ra, rb);
+    ipass<P, 1>(p, items, sel, n_items, i, item, it, lds, dg, pm, buf, ra, rb);
   }
 }
 
@@ -1431,7 +1475,7 @@ template <typename XT>
 struct IgY {
   using TA = double;
   using TB = XT;
-  static constexpr bool KA = true, KB = true, DIAG_A = true, DIAG_B = false;
+  static constexpr bool KA = true, KB = true, DIAG_A = true, DIAG_B = false, PERM = false;
   static constexpr int OUT = kOutF64, NPASS = 2;
   static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
   static constexpr bool same_panel(int) { return false; }
@@ -1461,7 +1505,7 @@ template <typename XT>
 struct IgSG {
   using TA = XT;
   using TB = double;
-  static constexpr bool KA = true, KB = true, DIAG_A = false, DIAG_B = false;
+  static constexpr bool KA = true, KB = true, DIAG_A = false, DIAG_B = false, PERM = false;
   static constexpr int OUT = kOutSym, NPASS = 2;
   static constexpr int set(int) { return kSetSym; }
   static constexpr bool same_panel(int ps) { return ps == 1; }
@@ -1488,7 +1532,7 @@ template <typename XT>
 struct IgXM {
   using TA = XT;
   using TB = double;
-  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = false;
+  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = false, PERM = true;
   static constexpr int OUT = kOutF64, NPASS = 2;
   static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
   static constexpr bool same_panel(int) { return false; }
@@ -1497,6 +1541,7 @@ struct IgXM {
   double* evec;
   int xout_ws;
   double* work;
+  const int32_t* perm;  // column c of the result goes to column perm[e_off + c] (or nullptr)
   __device__ Mat<XT> viewA(const ItemDev& it, int) const {
     const XT* X = xin_ws ? reinterpret_cast<const XT*>(WS(work, it).P1) : (xin + it.v_off);
     return row_view(X, it.n, it.n);
@@ -1520,7 +1565,7 @@ struct IgXM {
 struct IgWarm {
   using TA = float;
   using TB = double;
-  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = true;
+  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = true, PERM = false;
   static constexpr int OUT = kOutF32, NPASS = 2;
   static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
   static constexpr bool same_panel(int) { return false; }
@@ -1566,7 +1611,10 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
   }
   int cur_ws = 0;  // X in the caller's evec (0) or in the work-space P1 (1); step 0 reads x32
   for (int st = 0; st < steps; ++st) {
-    const int out_ws = (st == 0) ? 0 : 1 - cur_ws;
+    // whole-item products: the last step's X M goes to evec already sorted
+    // (refine_rank_kernel), the earlier ones alternate so that it reads P1
+    const bool last = st == steps - 1;
+    const int out_ws = whole ? ((steps - 1 - st) % 2 == 0 ? 0 : 1) : (st == 0 ? 0 : 1 - cur_ws);
     double closec = 1.0;
     for (int q = 0; q < close_log10 + st; ++q) closec *= 10.0;
     if (whole) {
@@ -1621,13 +1669,15 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
       if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
       if (err != hipSuccess) return err;
     }
+    if (whole && last)
+      hipLaunchKernelGGL(refine_rank_kernel, dim3(n_items), dim3(kBlock), 0, s, items, eval, cl, status);
     if (whole) {
       if (st == 0)
         hipLaunchKernelGGL(igemm_kernel<IgXM<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
-                           IgXM<float>{x32, 0, evec, out_ws, work});
+                           IgXM<float>{x32, 0, evec, out_ws, work, last ? cl : nullptr});
       else
         hipLaunchKernelGGL(igemm_kernel<IgXM<double>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
-                           IgXM<double>{(const double*)evec, cur_ws, evec, out_ws, work});
+                           IgXM<double>{(const double*)evec, cur_ws, evec, out_ws, work, last ? cl : nullptr});
     } else if (st == 0)
       hipLaunchKernelGGL(gemm_xm_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
                          x32, 0, evec, out_ws, work, tiles);
@@ -1638,8 +1688,9 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
     if (err != hipSuccess) return err;
     cur_ws = out_ws;
   }
-  hipLaunchKernelGGL(refine_finish_kernel, dim3(n_items), dim3(kBlock), 0, s, items, evec, cur_ws, work, eval,
-                     status);
+  if (!whole)
+    hipLaunchKernelGGL(refine_finish_kernel, dim3(n_items), dim3(kBlock), 0, s, items, evec, cur_ws, work, eval,
+                       status);
   return hipGetLastError();
 }
 
