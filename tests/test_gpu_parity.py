@@ -275,3 +275,38 @@ def test_whole_item_products_match_tiles_and_oracle():
             assert np.abs(it["evals"] - iw["evals"]).max() <= 1e-10 * np.abs(iw["evals"]).max()
             check_item(f"refine products={tag} s={s} n={it['v'].shape[0]}", it, ref, k, wp.MIXED, J, sig_ref,
                        host["sigma"][s])
+
+
+# ------------------------------------- warm start from the nearest cold item
+def test_warm_start_picks_the_nearest_cold_item():
+    # one cold item per compute unit (lambda in [0.5, 2]), then warm items
+    # whose potentials equal those of cold items 7 and 150 exactly: the
+    # reference choice (nearest V on a strided sample) must pick those twins,
+    # whose eigenvectors already diagonalise the warm items, so the Jacobi
+    # stops after its first sweep; warm items far from every cold item
+    # (lambda 0.05 ... 3.3) need more; all match the oracle
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    k = configs.grid("yamaguchi_s")
+    c = wp.Context(0)
+    g = c.grid(k, configs.N_GAUSS)
+    lams = [configs.yamaguchi_lambda(s) for s in range(n_cu)]
+    twins = {n_cu: 7, n_cu + 1: 150}
+    lams += [lams[7], lams[150]] + [0.05, 0.1, 0.2, 3.0, 3.3]
+    mats = [potentials.yamaguchi(g.nodes, g.nodes, lam, configs.YAMAGUCHI_BETA) for lam in lams]
+    b, host = run_items(c, [(g, 1, 0, s) for s in range(len(lams))], mats, wp.MIXED)
+    sw = host["eig_status"]
+    print("sweeps: cold mean", sw[:n_cu].mean(), "twins", [int(sw[i]) for i in twins], "others",
+          [int(x) for x in sw[n_cu + 2:]], flush=True)
+    assert (sw > 0).all() and (host["t_status"] == 0).all()
+    for i, j in twins.items():
+        assert sw[i] == 1, (i, j, sw[i])
+        assert np.abs(item_view(b, host, i)["evals"] - item_view(b, host, j)["evals"]).max() <= 1e-12 * np.abs(
+            item_view(b, host, j)["evals"]).max()
+    assert sw[n_cu + 2:].min() >= 2
+    xo, _ = ow.gauss_nodes(k, configs.N_GAUSS)
+    _, kbar, _ = ow.bins(k)
+    for s in list(twins) + [len(lams) - 1]:
+        ref = oracle_item(k, potentials.yamaguchi(xo, xo, lams[s], configs.YAMAGUCHI_BETA), 1)
+        sig_ref = oo.sigma_tot([(0, ref["delta"], None)], kbar, TLAB, k[-1])
+        check_item(f"nearest-reference warm start s={s}", item_view(b, host, s), ref, k, wp.MIXED, 0, sig_ref,
+                   host["sigma"][s])
