@@ -640,9 +640,20 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
         });
       };
       // cold starts (each group's reference among them), then the warm starts
-      // from the references' eigenvectors
-      for (int k = 0; k < L; ++k) WPCD_HIP(solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
+      // from the references' eigenvectors; the choice of references (V only)
+      // runs on the side stream beside the cold Jacobi
       const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
+      const bool side_pick = n_warm > 0 && b->n_pick > 0;
+      if (side_pick) {
+        WPCD_HIP(hipEventRecord(b->ctx->fork, stream), "wpcd_eigh: fork");
+        WPCD_HIP(hipStreamWaitEvent(b->ctx->side, b->ctx->fork, 0), "wpcd_eigh: fork");
+        WPCD_HIP(launch_warm_pick(b->d_items, b->n_items, b->d_jlist, b->d_pick, b->n_pick, b->d_cand, b->d_sig, v64,
+                                  b->d_ref, b->ctx->side),
+                 "wpcd_eigh: reference choice launch");
+        WPCD_HIP(hipEventRecord(b->ctx->join, b->ctx->side), "wpcd_eigh: join");
+      }
+      for (int k = 0; k < L; ++k) WPCD_HIP(solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
+      if (side_pick) WPCD_HIP(hipStreamWaitEvent(stream, b->ctx->join, 0), "wpcd_eigh: join");
       if (n_warm > 0) {
         WPCD_HIP(timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
                        [&] {
@@ -650,8 +661,8 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                                                         b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L],
                                                         b->d_jlist + b->jl_ptr[L], n_warm, b->d_ref,
                                                         b->warm_min_n, b->warm_max_n, b->d_jlist, b->d_pick,
-                                                        b->n_pick, b->d_cand, b->d_sig, b->d_grids, v64, b->d_x32,
-                                                        b->d_work, stream);
+                                                        side_pick ? 0 : b->n_pick, b->d_cand, b->d_sig, b->d_grids,
+                                                        v64, b->d_x32, b->d_work, stream);
                        }),
                  "wpcd_eigh: warm-start preparation launch");
       }

@@ -87,6 +87,10 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
 // floats per item of the batch, n_items of them).
 constexpr int kWarmPick = 16;
 constexpr int kWarmSig = 1024;
+// The reference choice alone (it needs V only, not the cold solutions): the
+// caller may run it beside the cold Jacobi and pass n_pick = 0 below.
+hipError_t launch_warm_pick(const ItemDev* items, int n_items, const int32_t* jlist, const int32_t* pick, int n_pick,
+                            const int32_t* cand, float* sig, const double* v64, int32_t* ref, hipStream_t s);
 hipError_t launch_jacobi_warm_prep(const ItemDev* items, int n_items, const int32_t* refs, int n_refs,
                                    const int32_t* warm, int n_warm, int32_t* ref, int min_n, int max_n,
                                    const int32_t* jlist, const int32_t* pick, int n_pick, const int32_t* cand,

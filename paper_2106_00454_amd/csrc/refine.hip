@@ -1713,6 +1713,14 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
 
 namespace wpcd {
 
+hipError_t launch_warm_pick(const ItemDev* items, int n_items, const int32_t* jlist, const int32_t* pick, int n_pick,
+                            const int32_t* cand, float* sig, const double* v64, int32_t* ref, hipStream_t s) {
+  if (n_pick == 0) return hipSuccess;
+  hipLaunchKernelGGL(warm_sig_kernel, dim3(n_items), dim3(kBlock), 0, s, items, v64, sig);
+  hipLaunchKernelGGL(warm_pick_kernel, dim3(n_pick), dim3(kBlock), 0, s, pick, jlist, cand, (const float*)sig, ref);
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobi_warm_prep(const ItemDev* items, int n_items, const int32_t* refs, int n_refs,
                                    const int32_t* warm, int n_warm, int32_t* ref, int min_n, int max_n,
                                    const int32_t* jlist, const int32_t* pick, int n_pick, const int32_t* cand,
@@ -1721,8 +1729,8 @@ hipError_t launch_jacobi_warm_prep(const ItemDev* items, int n_items, const int3
   if (max_n > kMaxN) return hipErrorInvalidValue;
   if (n_refs == 0 || n_warm == 0) return hipSuccess;
   if (n_pick > 0) {
-    hipLaunchKernelGGL(warm_sig_kernel, dim3(n_items), dim3(kBlock), 0, s, items, v64, sig);
-    hipLaunchKernelGGL(warm_pick_kernel, dim3(n_pick), dim3(kBlock), 0, s, pick, jlist, cand, (const float*)sig, ref);
+    hipError_t e = launch_warm_pick(items, n_items, jlist, pick, n_pick, cand, sig, v64, ref, s);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(warm_q0_kernel, dim3(n_refs), dim3(kBlock), 0, s, items, refs, x32, work);
   if (min_n >= kINMin && max_n <= kIN) {  // whole-item products, one work-group per CU
