@@ -310,8 +310,8 @@ def main() -> int:
     ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals after warm-up")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: items are independent and this build has no multi-GPU path "
-              "(sharding by parameter sample is described in DESIGN.md); run with --gpus 1", flush=True)
+        print("bench.py measures one GPU: items are independent and the library has no multi-GPU path "
+              "(batches would shard by parameter sample, one process per GPU); run with --gpus 1", flush=True)
         return 2
 
     if args.workload != "coupled":

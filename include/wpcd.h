@@ -67,7 +67,7 @@ enum {
   WPCD_ERR_NUMERIC = -7,     /* per item: NaN/Inf, zero eigenvalue, a
                                 scattering family with < 2 members, unsorted
                                 or zero-width scattering bins               */
-  WPCD_ERR_UNSUPPORTED = -8  /* size or mode not supported by this build     */
+  WPCD_ERR_UNSUPPORTED = -8  /* size or mode the library does not support    */
 };
 
 /* Arithmetic of the eigensolver and T contraction.

@@ -57,7 +57,7 @@ constexpr int kMaxLdsN = 200;
 // larger (device memory).
 constexpr int kNumClasses = 4;
 inline int size_class(int n) { return n <= 64 ? 0 : (n <= 128 ? 1 : (n <= kMaxLdsN ? 2 : 3)); }
-// Largest item the library accepts in this build.
+// Largest item the library accepts.
 constexpr int kMaxN = 1200;
 
 // Kernel launchers (each returns hipSuccess or the launch error).

@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped, not failed, where no GPU is visible (e.g. CPU-only CI);
-    # on a GPU machine a missing library is a hard failure inside the tests themselves.
+    # on a machine with a GPU a missing library is a hard failure inside the tests.
     try:
         import torch
         has_gpu = torch.cuda.is_available()

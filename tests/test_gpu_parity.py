@@ -1,6 +1,6 @@
 """GPU path vs the FP64 oracle, element by element, through the C ABI.
 
-Bars (BASELINE the benchmark spec): phase shifts and mixing angles within 0.01 deg and
+Bars: phase shifts and mixing angles within 0.01 deg and
 total cross sections within 0.01 mb of the oracle; intermediate quantities are
 checked with bounds derived from the arithmetic (stated per check).
 """
