@@ -568,10 +568,10 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   __shared__ int blk[kMaxChain];
   __shared__ int rot_flag[64];
   __shared__ double bnrm[kMaxN];
-  __shared__ short big_start[kMaxBig], big_len[kMaxBig], big_pos[kMaxBig];
+  __shared__ short big_start[kMaxBig], big_len[kMaxBig];
   __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
   __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
-  __shared__ int s_nch, s_c0, s_c1, s_Tb, s_pos, s_fail, s_nbig, s_nbt;
+  __shared__ int s_nch, s_c1, s_Tb, s_fail, s_nbig, s_nbt;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
   const WS ws(work, it);
@@ -613,10 +613,8 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       }
       i = j + 1;
     }
-    // the short chains' columns come first in the chain matrix (in the order
-    // their batches are processed), the long chains' after them
+    // chain columns are marked >= 0 (their position among all chain columns)
     for (int b = 0; b < nbig; ++b) {
-      big_pos[b] = (short)T;
       for (int t = 0; t < big_len[b]; ++t) reach[big_start[b] + t] = T + t;
       T += big_len[b];
     }
@@ -624,7 +622,6 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     s_nbig = nbig;
     s_fail = fail;
     s_c1 = 0;
-    s_pos = 0;
   }
   __syncthreads();
   // columns of chains beyond the list: M = I + E (form_m_kernel takes them
@@ -659,7 +656,6 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
         Tb += ch_len[c1];
         ++c1;
       }
-      s_c0 = c0;
       s_c1 = c1;
       s_Tb = Tb;
       s_nbt = nbt;
@@ -667,7 +663,6 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     const int Tb = s_Tb;
     if (Tb == 0) break;
-    const int pos = s_pos;
     for (int64_t e = threadIdx.x; e < (int64_t)n * Tb; e += kBlock) {
       const int k = (int)(e / Tb), t = (int)(e - (int64_t)k * Tb);
       const int j = cols[t];
@@ -736,15 +731,13 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       tile_store<T64>(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { M[(int64_t)r * n + cols[cc]] = v; });
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_pos = pos + Tb;
-    __syncthreads();
   }
   // long chains, one at a time in device memory
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* C = ws.W7;
   double* Q = ws.Y;
   for (int b = 0; b < s_nbig; ++b) {
-    const int i0 = big_start[b], m = big_len[b], pos = big_pos[b];
+    const int i0 = big_start[b], m = big_len[b];
     const int mt = (m + kTM - 1) / kTM;
     for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += kBlock) {
       const int k = (int)(e / m), t = (int)(e - (int64_t)k * m);
@@ -1087,7 +1080,7 @@ __global__ __launch_bounds__(kBlock) void warm_pick_kernel(const int32_t* __rest
     }
   }
   __syncthreads();
-  if (threadIdx.x < wcnt) {
+  if ((int)threadIdx.x < wcnt) {
     const int w = threadIdx.x;
     float bd = rd[0][w];
     int bx = ri[0][w];
