@@ -143,12 +143,9 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   ctx->cfg = c;
   hipError_t e = hipMalloc((void**)&ctx->d_counters, 4 * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(ctx->d_counters, 0, 4 * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
   if (e != hipSuccess) {
     wpcd_destroy(ctx);
-    return hip_fail(e, "wpcd_create: counters, side stream, events");
+    return hip_fail(e, "wpcd_create: counters");
   }
   *out = ctx;
   return WPCD_OK;
@@ -619,6 +616,14 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
   if (mode == WPCD_MIXED) {
     if (c.refine_steps < 1)
       return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED needs refine_steps >= 1");
+    // the second stream of the batch path, created on first use (the request
+    // loop never needs it, and every stream takes a share of the hardware
+    // queues its own streams use)
+    if (b->ctx->side == nullptr) {
+      WPCD_HIP(hipStreamCreateWithFlags(&b->ctx->side, hipStreamNonBlocking), "wpcd_eigh: side stream");
+      WPCD_HIP(hipEventCreateWithFlags(&b->ctx->fork, hipEventDisableTiming), "wpcd_eigh: events");
+      WPCD_HIP(hipEventCreateWithFlags(&b->ctx->join, hipEventDisableTiming), "wpcd_eigh: events");
+    }
     // one FP32 Jacobi launch per size class: LDS-resident up to n = kMaxLdsN,
     // device memory above
     {
