@@ -108,7 +108,12 @@ __global__ __launch_bounds__(BLOCK) void gjac_init_kernel(const ItemDev* __restr
     }
     return;
   }
-  for (int c = threadIdx.x; c < n; c += BLOCK) key[c] = key[c] + sigma * (T(2) * dg[c] + sigma);
+  // a NaN key (NaN in V) ranks last, so the ranks stay a permutation (the
+  // item is flagged by the finish kernel)
+  for (int c = threadIdx.x; c < n; c += BLOCK) {
+    const T kc = key[c] + sigma * (T(2) * dg[c] + sigma);
+    key[c] = kc == kc ? kc : T(-INFINITY);
+  }
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += BLOCK) {
     const T kc = key[c];

@@ -99,8 +99,14 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
       for (int r = threadIdx.x; r < rows; r += BLOCK) W[n * ld + r] = 0.f;
     __syncthreads();
   } else if constexpr (kSorted) {
-    // |B e_c|^2 = |H e_c|^2 + 2 sigma H_cc + sigma^2; rank by descending norm
-    for (int c = threadIdx.x; c < n; c += BLOCK) diag[c] = nrm[c] + sigma * (2.f * diag[c] + sigma);
+    // |B e_c|^2 = |H e_c|^2 + 2 sigma H_cc + sigma^2; rank by descending norm.
+    // A NaN key (NaN in V) ranks last: every comparison with NaN is false, so
+    // without this two columns could take one rank and leave a slot of perm
+    // unwritten; the item is flagged after the sweeps (its norms are NaN).
+    for (int c = threadIdx.x; c < n; c += BLOCK) {
+      const float key = nrm[c] + sigma * (2.f * diag[c] + sigma);
+      diag[c] = key == key ? key : -INFINITY;
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += BLOCK) {
       const float kc = diag[c];

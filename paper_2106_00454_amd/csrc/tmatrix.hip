@@ -167,6 +167,9 @@ __global__ __launch_bounds__(kBlock) void tmatrix_kernel(const ItemDev* __restri
   }
   __syncthreads();
   if (s_bad) {
+    // flagged items get NaN T (so their phase shifts and cross sections are NaN too)
+    double* tt = t + it.t_off;
+    for (int e = threadIdx.x; e < 2 * N * K * K; e += kBlock) tt[e] = NAN;
     if (threadIdx.x == 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
     return;
   }

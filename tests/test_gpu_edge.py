@@ -1,0 +1,130 @@
+"""Degenerate and failing items on the GPU, through the C ABI.
+
+* A weak tensor coupling (C_t -> 0, down to exactly 0): the two orbital
+  channels' spectra interleave with near-degenerate pairs (gaps ~1e-11 fm^-2),
+  which the refinement must resolve the same way as LAPACK does; the mixing
+  angle must follow C_t to zero.  Against the oracle, both modes.
+* Per-item status codes of the documented failure cases, with healthy items
+  of the same batch unaffected:
+  - NaN in the potential            -> WPCD_ERR_NUMERIC;
+  - max_sweeps = 1 on n = 200 items -> WPCD_ERR_NOCONV (results still written);
+  - a scattering family with fewer than two members (N_WP = 2, one bound
+    state, one scattering state)   -> WPCD_ERR_NUMERIC from wpcd_tmatrix.
+"""
+import numpy as np
+import pytest
+
+import paper_2106_00454_amd as wp
+from oracle import observables as oo
+from oracle import wpcd as ow
+from synth import configs, grids, potentials
+from tests.gpu_util import TLAB, check_item, item_view, run_items
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def coupled():
+    k = configs.grid("coupled_yukawa")
+    xo, _ = ow.gauss_nodes(k, configs.N_GAUSS)
+    return k, configs.coupled_yukawa_terms(xo)
+
+
+@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
+def test_weak_tensor_coupling(coupled, mode):
+    k, t_or = coupled
+    ctx = wp.Context(0)
+    g = ctx.grid(k, configs.N_GAUSS)
+    t_lib = configs.coupled_yukawa_terms(g.nodes)
+    base = configs.yukawa_coefficients(3)
+    scales = (1e-2, 1e-4, 1e-6, 0.0)
+    coeffs = []
+    for sc in scales:
+        c = base.copy()
+        c[3] *= sc
+        coeffs.append(c)
+    items = [(g, 2, 1, i) for i in range(len(scales))]
+    b, host = run_items(ctx, items, [sum(ci * t for ci, t in zip(c, t_lib)) for c in coeffs], mode)
+    _, kbar, _ = ow.bins(k)
+    for i, (sc, c) in enumerate(zip(scales, coeffs)):
+        ref = ow.solve_channel(k, configs.N_GAUSS, sum(ci * t for ci, t in zip(c, t_or)), 2)
+        it = item_view(b, host, i)
+        sig_ref = oo.sigma_tot([(1, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
+        print(f"weak tensor C_t scale {sc:g}: min eigenvalue gap {np.diff(ref['evals']).min():.2e}, "
+              f"max |eps| oracle {np.abs(ref['mix']).max():.3e} gpu {np.abs(it['mix']).max():.3e}", flush=True)
+        check_item(f"weak tensor mode={mode} scale={sc:g}", it, ref, k, mode, 1, sig_ref, host["sigma"][i])
+        if sc == 0.0:
+            # decoupled blocks: no rotation ever mixes the two orbital channels
+            assert np.abs(it["mix"]).max() <= 1e-9
+
+
+@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
+def test_nan_potential_is_flagged_and_isolated(mode):
+    ctx = wp.Context(0)
+    k = grids.tan2_bounded(40)
+    g = ctx.grid(k, 8)
+    xo, _ = ow.gauss_nodes(k, 8)
+    lams = (0.8, 1.3, 1.9)
+    mats = [potentials.yamaguchi(g.nodes, g.nodes, lam, 1.4) for lam in lams]
+    mats[1] = mats[1].copy()
+    mats[1][17, 5] = np.nan
+    mats[1][5, 17] = np.nan
+    b, host = run_items(ctx, [(g, 1, 0, i) for i in range(3)], mats, mode)
+    bad = item_view(b, host, 1)
+    print(f"NaN item: eig status {bad['eig_status']}, T status {bad['t_status']}", flush=True)
+    assert bad["eig_status"] == wp.WPCD_ERR_NUMERIC
+    assert bad["t_status"] == wp.WPCD_ERR_NUMERIC
+    _, kbar, _ = ow.bins(k)
+    for i in (0, 2):
+        ref = ow.solve_channel(k, 8, potentials.yamaguchi(xo, xo, lams[i], 1.4), 1)
+        sig_ref = oo.sigma_tot([(0, ref["delta"], None)], kbar, TLAB, k[-1])
+        check_item(f"NaN batch mode={mode} healthy item {i}", item_view(b, host, i), ref, k, mode, 0, sig_ref,
+                   host["sigma"][i])
+
+
+@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
+def test_sweep_cap_reports_noconv(coupled, mode):
+    k, _ = coupled
+    ctx = wp.Context(0, max_sweeps=1)
+    g = ctx.grid(k, configs.N_GAUSS)
+    g3 = ctx.grid(grids.tan2_bounded(120), configs.N_GAUSS)       # n = 240: device-memory Jacobi
+    t_lib = configs.coupled_yukawa_terms(g.nodes)
+    t3 = configs.coupled_yukawa_terms(g3.nodes)
+    cs = [configs.yukawa_coefficients(s) for s in range(3)]
+    items = [(g, 2, 1, 0), (g, 2, 1, 1), (g3, 2, 1, 2)]
+    mats = [sum(ci * t for ci, t in zip(cs[0], t_lib)), sum(ci * t for ci, t in zip(cs[1], t_lib)),
+            sum(ci * t for ci, t in zip(cs[2], t3))]
+    b, host = run_items(ctx, items, mats, mode)
+    st = host["eig_status"]
+    print(f"max_sweeps=1 mode={mode}: eig status {st.tolist()}, T status {host['t_status'].tolist()}", flush=True)
+    assert (st == wp.WPCD_ERR_NOCONV).all()
+    for i in range(3):   # the results are still written
+        assert np.isfinite(item_view(b, host, i)["evals"]).all()
+
+
+@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
+def test_family_with_one_member_is_flagged(mode):
+    # N_WP = 2 with a deep Yamaguchi well: eigenvalues about -1.36 and +1.55
+    # fm^-2, one scattering state, so the family has one member (the oracle
+    # raises for the same input); a healthy N_WP = 30 item rides along
+    ctx = wp.Context(0)
+    k2, k30 = grids.tan2_bounded(2), grids.tan2_bounded(30)
+    g2, g30 = ctx.grid(k2, 8), ctx.grid(k30, 8)
+    x2, _ = ow.gauss_nodes(k2, 8)
+    with pytest.raises(ow.WPCDError):
+        ow.solve_channel(k2, 8, potentials.yamaguchi(x2, x2, 20.0, 1.4), 1)
+    items = [(g2, 1, 0, 0), (g30, 1, 0, 1)]
+    mats = [potentials.yamaguchi(g2.nodes, g2.nodes, 20.0, 1.4), potentials.yamaguchi(g30.nodes, g30.nodes, 1.5, 1.4)]
+    b, host = run_items(ctx, items, mats, mode)
+    bad = item_view(b, host, 0)
+    print(f"one-member family mode={mode}: eig status {bad['eig_status']}, T status {bad['t_status']}, "
+          f"eigenvalues {bad['evals']}", flush=True)
+    assert bad["eig_status"] > 0
+    assert bad["t_status"] == wp.WPCD_ERR_NUMERIC
+    assert (bad["evals"][0] < 0) and (bad["evals"][1] > 0)
+    x30, _ = ow.gauss_nodes(k30, 8)
+    ref = ow.solve_channel(k30, 8, potentials.yamaguchi(x30, x30, 1.5, 1.4), 1)
+    _, kbar, _ = ow.bins(k30)
+    sig_ref = oo.sigma_tot([(0, ref["delta"], None)], kbar, TLAB, k30[-1])
+    check_item(f"one-member batch mode={mode} healthy item", item_view(b, host, 1), ref, k30, mode, 0, sig_ref,
+               host["sigma"][1])

@@ -1,4 +1,4 @@
-"""Large-mesh coupled items beyond LDS (n = 2 N_WP = 600) against the FP64 oracle.
+"""Large-mesh coupled items beyond LDS (n = 2 N_WP = 600 and 1200) against the FP64 oracle.
 
 The eigenpairs of such items come from the device-memory FP32 Jacobi plus the
 FP64 refinement (WPCD_MIXED) or the device-memory FP64 Jacobi (WPCD_F64); the
@@ -38,6 +38,7 @@ def setup():
     return ctx, k, specs, coefs, refs
 
 
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
 def test_large_mesh_matches_oracle(setup, mode):
     ctx, k, specs, coefs, refs = setup
@@ -83,3 +84,45 @@ def test_warm_started_device_memory_jacobi():
     assert np.abs(((hw["delta"] - hc["delta"] + 90.0) % 180.0) - 90.0).max() <= 1e-6
     for i, ref in enumerate(refs):
         check_item(f"warm device-memory item={i} n={2 * n_wp}", item_view(bw, hw, i), ref, k, wp.MIXED, J)
+
+
+# ------------------------------------------------ N_WP = 600 (n = 1200)
+N_WP_XL = 600
+
+
+@pytest.fixture(scope="module")
+def setup_xl():
+    # two samples of 3S1-3D1 at N_WP = 600: the largest items the library
+    # takes (1200 x 1200 H; FP32 block Jacobi with 16-column blocks, FP64
+    # with 8-column blocks, two staged blocks filling 152 KiB of LDS); the
+    # second sample warm-starts from the first in the mixed path.  The term
+    # caches (several GB) are dropped once used.
+    chan = 14
+    ctx = wp.Context(0)
+    k = sweep.grid_bounds(N_WP_XL)
+    g = ctx.grid(k, sweep.N_GAUSS)
+    bs = ctx.basis(g, 2, sweep.TermCache().terms(("lib", N_WP_XL), g.nodes, chan))
+    J = sweep.CHANNELS[chan][2]
+    specs = [(g, 2, J, i, bs) for i in range(2)]
+    coefs = [sweep.coefficients(s, chan) for s in (5, 6)]
+    xo, _ = ow.gauss_nodes(k, sweep.N_GAUSS)
+    terms = sweep.TermCache().terms(("or", N_WP_XL), xo, chan)
+    refs = []
+    for cf in coefs:
+        refs.append(ow.solve_channel(k, sweep.N_GAUSS, sum(ci * t for ci, t in zip(cf, terms)), 2))
+    del terms
+    return ctx, k, J, specs, coefs, refs
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
+def test_largest_mesh_matches_oracle(setup_xl, mode):
+    ctx, k, J, specs, coefs, refs = setup_xl
+    b, host = run_items(ctx, specs, None, mode, tlab=sweep.TLAB, coef=coefs)
+    assert b.layout["max_n"] == 2 * N_WP_XL
+    _, kbar, _ = ow.bins(k)
+    for i, ref in enumerate(refs):
+        it = item_view(b, host, i)
+        sig_ref = oo.sigma_tot([(J, ref["delta"], ref["mix"])], kbar, sweep.TLAB, k[-1])
+        check_item(f"largest mesh mode={mode} item={i} n={2 * N_WP_XL}", it, ref, k, mode, J, sig_ref,
+                   host["sigma"][i])

@@ -2,9 +2,14 @@
 
 A reference request is solved alone, then again in the middle of a mix of
 other requests submitted in waves while earlier ones are still on the device
-(continuous batching): its results must be the same in both runs (each item's
-arithmetic is independent of its batch, so they agree bit for bit), and they
-must match the FP64 oracle within 0.01 deg and 0.01 mb.
+(continuous batching).  Its channels span every eigensolver size class (n from
+50 to 400, the device-memory Jacobi included), and so do the other requests'.
+The kernels a batch takes depend on its size mix (the device-memory Jacobi's
+block width on the largest n of its class, the refinement's product kernels on
+the smallest and largest n of the batch), which changes the rounding order but
+not the solved problem: the two runs must agree within 1e-7 deg and 1e-6 mb,
+far below the oracle bars, and both must match the FP64 oracle within 0.01 deg
+and 0.01 mb.
 """
 import time
 
@@ -20,11 +25,12 @@ from tests.gpu_util import DELTA_TOL, SIGMA_TOL, dmod180
 pytestmark = pytest.mark.gpu
 
 CHANNELS = (0, 7, 14, 16)          # 1S0, 3P0, 3S1-3D1, 3D3-3G3
-NWP = (50, 100)
+NWP = (50, 100, 150, 200)
 
 
 @pytest.fixture(scope="module")
 def setup():
+    # (CHANNELS x NWP bases; the coupled N_WP = 200 terms alone are 1.3 GB)
     ctx = wp.Context(0)
     cache = sweep.TermCache()
     grids = {N: ctx.grid(sweep.grid_bounds(N), sweep.N_GAUSS) for N in NWP}
@@ -52,9 +58,10 @@ def wait(srv, tickets, timeout=60.0):
         time.sleep(1e-4)
 
 
-REF_SPEC = [(0, 50), (14, 100), (16, 50)]
+REF_SPEC = [(0, 50), (14, 100), (16, 50), (7, 150), (16, 200)]
 
 
+@pytest.mark.timeout(300)
 def test_request_alone_and_in_the_mix(setup):
     ctx, bases, srv = setup
     ref = srv.submit(request(bases, 0, REF_SPEC), sweep.TLAB, want_phases=True)
@@ -80,7 +87,7 @@ def test_request_alone_and_in_the_mix(setup):
     dd = np.abs(again.delta - ref.delta).max()
     dm = np.abs(again.mix - ref.mix).max()
     print(f"alone vs mix: dsigma={ds:.3e} ddelta={dd:.3e} dmix={dm:.3e}", flush=True)
-    assert ds <= 1e-9 and dd <= 1e-9 and dm <= 1e-9
+    assert ds <= 1e-6 and dd <= 1e-7 and dm <= 1e-7
     # the reference request against the oracle
     cache = sweep.TermCache()
     chans, off, moff = [], 0, 0

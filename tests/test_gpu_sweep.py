@@ -10,12 +10,13 @@ all 20 channels within 0.01 mb.
 """
 import numpy as np
 import pytest
+import torch
 
 import paper_2106_00454_amd as wp
 from oracle import observables as oo
 from oracle import wpcd as ow
 from synth import sweep
-from tests.gpu_util import SIGMA_TOL, check_item, item_view, run_items
+from tests.gpu_util import SIGMA_TOL, check_item, dmod180, item_view, run_items
 
 pytestmark = pytest.mark.gpu
 
@@ -25,33 +26,43 @@ N_SAMPLES = 2
 @pytest.fixture(scope="module")
 def setup():
     ctx = wp.Context(0)
-    items = sweep.items(N_SAMPLES)
     grids = {N: ctx.grid(sweep.grid_bounds(N), sweep.N_GAUSS) for N in sweep.N_WP_CHOICES}
     lib_terms, or_terms = sweep.TermCache(), sweep.TermCache()
     bases = {}
-    specs, coefs, refs = [], [], []
+    for N in sweep.N_WP_CHOICES:
+        g = grids[N]
+        for c in range(len(sweep.CHANNELS)):
+            bases[(c, N)] = ctx.basis(g, sweep.CHANNELS[c][1], lib_terms.terms(("lib", N), g.nodes, c))
+    return ctx, bases, or_terms, lib_terms
+
+
+def _batch(bases, items):
+    specs, coefs = [], []
     for s, c, N in items:
         _, n_ch, J, _, _ = sweep.CHANNELS[c]
-        g = grids[N]
-        if (c, N) not in bases:
-            bases[(c, N)] = ctx.basis(g, n_ch, lib_terms.terms(("lib", N), g.nodes, c))
-        specs.append((g, n_ch, J, s, bases[(c, N)]))
+        specs.append((bases[(c, N)].grid, n_ch, J, s, bases[(c, N)]))
         coefs.append(sweep.coefficients(s, c))
-    for s, c, N in items:
-        k = sweep.grid_bounds(N)
-        xo, _ = ow.gauss_nodes(k, sweep.N_GAUSS)
-        u = sum(ci * t for ci, t in zip(sweep.coefficients(s, c), or_terms.terms(("or", N), xo, c)))
-        refs.append((k, ow.solve_channel(k, sweep.N_GAUSS, u, sweep.CHANNELS[c][1])))
-    return ctx, items, specs, coefs, refs
+    return specs, coefs
 
 
+def _oracle(or_terms, s, c, N):
+    k = sweep.grid_bounds(N)
+    xo, _ = ow.gauss_nodes(k, sweep.N_GAUSS)
+    u = sum(ci * t for ci, t in zip(sweep.coefficients(s, c), or_terms.terms(("or", N), xo, c)))
+    return k, ow.solve_channel(k, sweep.N_GAUSS, u, sweep.CHANNELS[c][1])
+
+
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
 def test_sweep_matches_oracle(setup, mode):
-    ctx, items, specs, coefs, refs = setup
+    ctx, bases, or_terms, _ = setup
+    items = sweep.items(N_SAMPLES)
+    specs, coefs = _batch(bases, items)
     b, host = run_items(ctx, specs, None, mode, tlab=sweep.TLAB, coef=coefs)
     assert b.layout["u_elems"] == 0 and b.layout["max_n"] == max(sp[1] * sp[0].n_wp for sp in specs)
     per_sample = {}
-    for i, ((s, c, N), (k, ref)) in enumerate(zip(items, refs)):
+    for i, (s, c, N) in enumerate(items):
+        k, ref = _oracle(or_terms, s, c, N)
         it = item_view(b, host, i)
         J = sweep.CHANNELS[c][2]
         assert np.abs(it["v"] - ref["v"]).max() <= 1e-12 * np.abs(ref["v"]).max()
@@ -63,6 +74,59 @@ def test_sweep_matches_oracle(setup, mode):
         ds = np.abs(host["sigma"][s] - want).max()
         print(f"sweep mode={mode} sample={s}: dsigma={ds:.3e} mb (sigma at 1 MeV {want[0]:.1f} mb)", flush=True)
         assert ds <= SIGMA_TOL
+
+
+@pytest.mark.timeout(300)
+def test_sweep_warm_starts_in_every_size_class(setup):
+    # 48 samples = 960 items: more items than compute units in every LDS size
+    # class (341 of them with 129 <= n <= 200), so each class launches cold
+    # items first and then warm ones from the nearest cold item of their
+    # (channel, N_WP) group, and the n = 300 class warm-starts its device-
+    # memory Jacobi from each group's first item.  The last two samples hold
+    # warm items of every class: all 40 of their items and both cross sections
+    # against the oracle, the whole batch against cold starts only.
+    ctx, bases, or_terms, lib_terms = setup
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    items = sweep.items(48)
+    ns = np.array([sweep.CHANNELS[c][1] * N for _, c, N in items])
+    assert ((ns > 128) & (ns <= 200)).sum() > n_cu
+    specs, coefs = _batch(bases, items)
+    bw, hw = run_items(ctx, specs, None, wp.MIXED, tlab=sweep.TLAB, coef=coefs)
+    cctx = wp.Context(0, jacobi_start=1)
+    cgrids = {N: cctx.grid(sweep.grid_bounds(N), sweep.N_GAUSS) for N in sweep.N_WP_CHOICES}
+    cb = {}
+    for (c, N), bs in bases.items():
+        # the same library nodes (same host computation), so the same cached terms
+        assert np.array_equal(cgrids[N].nodes, bs.grid.nodes)
+        cb[(c, N)] = cctx.basis(cgrids[N], sweep.CHANNELS[c][1], lib_terms.terms(("lib", N), bs.grid.nodes, c))
+    cspecs, _ = _batch(cb, items)
+    bc, hc = run_items(cctx, cspecs, None, wp.MIXED, tlab=sweep.TLAB, coef=coefs)
+    for h in (hw, hc):
+        assert (h["eig_status"] > 0).all() and (h["t_status"] == 0).all()
+    for lo_, hi_ in ((0, 64), (65, 128), (129, 200), (201, 300)):
+        sel = (ns >= lo_) & (ns <= hi_)
+        print(f"n in [{lo_}, {hi_}]: {sel.sum()} items, mean sweeps warm-start run {hw['eig_status'][sel].mean():.2f}, "
+              f"cold-start run {hc['eig_status'][sel].mean():.2f}", flush=True)
+    dd = dmod180(hw["delta"], hc["delta"]).max()
+    dm = np.abs(hw["mix"] - hc["mix"]).max()
+    ds = np.abs(hw["sigma"] - hc["sigma"]).max()
+    print(f"sweep warm vs cold: ddelta={dd:.3e} dmix={dm:.3e} dsigma={ds:.3e}", flush=True)
+    assert dd <= 1e-6 and dm <= 1e-6 and ds <= 1e-6
+    for s in (46, 47):
+        chans = []
+        for i, (si, c, N) in enumerate(items):
+            if si != s:
+                continue
+            k, ref = _oracle(or_terms, s, c, N)
+            J = sweep.CHANNELS[c][2]
+            check_item(f"sweep48 sample={s} {sweep.CHANNELS[c][0]} N={N} n={ns[i]}", item_view(bw, hw, i), ref, k,
+                       wp.MIXED, J)
+            _, kbar, _ = ow.bins(k)
+            chans.append((J, ref["delta"], ref["mix"], kbar, k[-1]))
+        want = oo.sigma_tot(chans, None, sweep.TLAB, None)
+        dsig = np.abs(hw["sigma"][s] - want).max()
+        print(f"sweep48 sample={s}: dsigma={dsig:.3e} mb", flush=True)
+        assert dsig <= SIGMA_TOL
 
 
 def test_basis_errors(setup):

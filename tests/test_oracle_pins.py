@@ -302,6 +302,47 @@ def test_sigma_single_channel_textbook_and_coupled_reduction():
     assert np.allclose(sig2, ref, rtol=1e-12)
 
 
+def test_sigma_coupled_mixing_branch_against_closed_form():
+    # A coupled channel whose Stapp parameters are linear in q, so mid-point
+    # interpolation is exact: delta_-(q), delta_+(q) cross +-90 degrees at
+    # different momenta (each wrapped phase picks up its own 180-degree
+    # jumps) and eps(q) != 0 moves through both signs.  S is built from the
+    # parameters at the bin midpoints (App. A, Stapp form), the principal
+    # values are re-extracted from it, and sigma_tot must equal the partial-
+    # wave optical theorem evaluated directly from the unwrapped parameters:
+    #   sigma(p) = 10 pi/(2 p^2) (2J+1) (2 - cos 2eps (cos 2d_- + cos 2d_+)).
+    # A wrong sign rule for eps under odd shift parity, cos(eps) for cos(2 eps)
+    # or a dropped mixing factor all move this by far more than 1e-9.
+    kbar = np.linspace(0.04, 2.9, 55)
+    dm_true = 120.0 * kbar - 20.0           # crosses +90 and +270 degrees
+    dp_true = -51.0 * kbar + 10.0           # crosses -90 degrees
+    ep_true = 24.0 * kbar - 30.0            # mixing angle from -29 to +40 degrees
+    s = observables.stapp_s(dm_true, dp_true, ep_true)
+    ph = observables.phase_shifts(s)
+    wrapped_m, wrapped_p = ph["delta"][:, 0], ph["delta"][:, 1]
+    # the extraction really wraps: some bins differ from the truth by 180 deg,
+    # with odd total shift parity somewhere (so the extracted eps flips sign)
+    km = np.round((dm_true - wrapped_m) / 180.0)
+    kp = np.round((dp_true - wrapped_p) / 180.0)
+    assert np.abs(km).max() >= 1 and np.abs(kp).max() >= 1
+    odd = ((km + kp) % 2) != 0
+    assert odd.any() and (~odd).any()
+    assert np.allclose(ph["mix"][odd], -ep_true[odd], atol=1e-9)
+    assert np.allclose(ph["mix"][~odd], ep_true[~odd], atol=1e-9)
+    J = 3
+    p = np.linspace(kbar[0] * 1.01, kbar[-1] * 0.999, 400)
+    tl = 2.0 * (observables.HBARC_MEV_FM * p) ** 2 / observables.M_N_MEV
+    got = observables.sigma_tot([(J, np.stack([wrapped_m, wrapped_p], axis=1), ph["mix"])], kbar, tl, 4.0)
+    slope = lambda y: np.interp(p, kbar, y)        # exact for data linear in q
+    e2, m2, p2 = (2.0 * np.radians(slope(y)) for y in (ep_true, dm_true, dp_true))
+    want = 10.0 * np.pi / (2.0 * p * p) * (2 * J + 1) * (2.0 - np.cos(e2) * (np.cos(m2) + np.cos(p2)))
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+    # the intervals whose end bins have opposite shift parity are where the
+    # sign rule matters; the check above covers p in such intervals
+    i = np.clip(np.searchsorted(kbar, p, side="right"), 1, kbar.size - 1)
+    assert (odd[i] != odd[i - 1]).any()
+
+
 def test_tlab_kinematics():
     # E_cm = T_lab/2 = (hbar c p)^2/m_N for equal masses
     p = observables.tlab_to_p([1.0, 40.0, 350.0])
