@@ -32,7 +32,8 @@ METRIC = "channel-solves/sec (coupled, N_WP=100, all bin energies) batched vs pl
 N_WP = 100
 N_CH = 2
 N_TLAB = 30
-PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # TFLOP/s, non-packed FP32 FMA
+PEAK_FP32_PUBLISHED = 157.3                         # TFLOP/s, published FP32 vector peak (packed FMA)
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # TFLOP/s, non-packed FP32 FMA (packed FP32 is off)
 PEAK_FP64_MFMA = 78.6                               # TFLOP/s, published dense FP64 matrix peak
 
 
@@ -59,7 +60,7 @@ def measured_traffic(kernel: str):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_sha256"):
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    return float(rec["traffic_bytes_per_launch"]), path
 
 
 # ----------------------------------------------------------------- CPU oracle
@@ -88,21 +89,33 @@ def _worker_item(sid: int) -> float:
     return time.perf_counter() - t0
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seconds: float) -> dict:
     """The oracle as it stands, one item per task, on all host cores."""
     cores = os.cpu_count() or 1
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[v] = "1"
     ctx = mp.get_context("spawn")
+    per_item = []
     with cf.ProcessPoolExecutor(max_workers=cores, mp_context=ctx, initializer=_worker_init) as ex:
         list(ex.map(_worker_item, range(cores)))          # warm every worker
         done, t0 = 0, time.perf_counter()
         chunk = 4 * cores
         while time.perf_counter() - t0 < seconds:
-            list(ex.map(_worker_item, range(done, done + chunk)))
+            per_item += list(ex.map(_worker_item, range(done, done + chunk)))
             done += chunk
         wall = time.perf_counter() - t0
     return {"value": done / wall, "unit": "channel-solves/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "per_item_p50_ms": float(np.percentile(per_item, 50) * 1e3),
             "sample": f"{done} coupled N_WP=100 items (a1-a9 incl. sigma_tot), FP64 NumPy/LAPACK, "
                       f"one single-threaded process per core, {wall:.1f} s wall"}
 
@@ -215,6 +228,54 @@ def run_large(args) -> dict:
     return out
 
 
+def run_mi(args) -> dict:
+    """The matrix-inversion solver on the coupled workload: args.batch coupled
+    N_WP-independent items (the same Yukawa + tensor samples), N_Q nodes on
+    [0, 4] fm^-1, the 30 T_lab energies of sigma_tot, one FP64 LU per item and
+    energy, phase shifts, mixing angles and sigma_tot."""
+    import torch
+    import paper_2106_00454_amd as wp
+    from synth import configs
+    ctx = wp.Context(0)
+    B, nq = args.batch, args.mi_nq
+    tl = np.linspace(1.0, 350.0, N_TLAB)
+    s = wp.MiSolver(ctx, [(2, 1, i) for i in range(B)], nq, 4.0, tl)
+    pts = s.points
+    coeffs = np.array([configs.yukawa_coefficients(i) for i in range(B)])
+    terms = configs.coupled_yukawa_terms(pts)
+    t = torch.from_numpy(np.stack([x.ravel() for x in terms])).cuda()
+    c = torch.as_tensor(coeffs, dtype=torch.float64, device="cuda")
+    u = (c @ t).reshape(-1).contiguous()
+    assert u.numel() == s.layout["u_elems"]
+    bufs = s.alloc()
+    for _ in range(args.warmup):
+        s.solve(u, bufs)
+    torch.cuda.synchronize()
+    st = bufs["status"].cpu().numpy()
+    if (st != 0).any():
+        log(f"mi: {int((st != 0).sum())} items flagged")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.solve(u, bufs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = B * args.steps / wall
+    m = 2 * (nq + 1)
+    flop = B * N_TLAB * (2.0 / 3.0 * m ** 3 + 2.0 * 2 * m * m)     # LU of [A | 2 right-hand sides]
+    log(f"mi: {value:.0f} channel-solves/s ({value * N_TLAB:.0f} energy-solves/s), {wall / args.steps * 1e3:.2f} ms/step")
+    return {"metric": f"channel-solves/sec (coupled, matrix inversion, N_Q={nq}, {N_TLAB} energies)",
+            "value": value, "unit": "channel-solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"matrix inversion (K-matrix route): {B} coupled S-D Yukawa+tensor items, "
+                                   f"N_Q={nq} Gauss nodes on [0,4] fm^-1, sigma_tot at {N_TLAB} T_lab",
+                       "items_per_step": B, "energies": N_TLAB, "system_size": m},
+            "roofline": {"bound": "alu", "achieved": flop * args.steps / wall / 1e12, "peak": 78.6,
+                         "unit": "TFLOP/s", "frac": flop * args.steps / wall / 1e12 / 78.6,
+                         "kernel": "mi_solve_kernel (FP64 VALU elimination in LDS)", "traffic": None},
+            "cpu_baseline": None}
+
+
 def run_serve(args) -> dict:
     """Poisson arrivals of parameter-vector requests with random channel subsets."""
     import paper_2106_00454_amd as wp
@@ -295,6 +356,7 @@ def main() -> int:
     ap.add_argument("--plain-items", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cold", action="store_true", help="skip the cold-start comparison run")
     ap.add_argument("--jacobi-block", type=int, default=0, help="LDS Jacobi variant (wpcd_config.jacobi_block; 0: default)")
     ap.add_argument("--jacobi-start", type=int, default=0, help="LDS Jacobi start (wpcd_config.jacobi_start; 0: warm, 1: cold)")
     ap.add_argument("--refine-gemm", type=int, default=0,
@@ -302,10 +364,11 @@ def main() -> int:
     ap.add_argument("--refine-steps", type=int, default=2, help="FP64 refinement steps (wpcd_config.refine_steps)")
     ap.add_argument("--refine-close", type=int, default=0, help="wpcd_config.refine_close_log10 (0: default)")
     ap.add_argument("--jacobi-stop", type=float, default=0.0, help="FP32 Jacobi stopping threshold (wpcd_config.jacobi_stop_f32; 0: default)")
-    ap.add_argument("--workload", choices=("coupled", "sweep", "large", "serve"), default="coupled",
+    ap.add_argument("--workload", choices=("coupled", "sweep", "large", "serve", "mi"), default="coupled",
                     help="coupled: the headline line; sweep / large / serve: the other workloads")
     ap.add_argument("--samples", type=int, default=512, help="sweep: parameter samples per step")
     ap.add_argument("--large-nwp", type=int, default=300, help="large: N_WP of the coupled items")
+    ap.add_argument("--mi-nq", type=int, default=48, help="mi: Gauss nodes of the matrix-inversion solver")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals after warm-up")
     args = ap.parse_args()
@@ -315,7 +378,7 @@ def main() -> int:
         return 2
 
     if args.workload != "coupled":
-        out = {"sweep": run_sweep, "large": run_large, "serve": run_serve}[args.workload](args)
+        out = {"sweep": run_sweep, "large": run_large, "serve": run_serve, "mi": run_mi}[args.workload](args)
         print(json.dumps(out), flush=True)
         return 0
 
@@ -382,7 +445,7 @@ def main() -> int:
     ref_flops = B * 2 * 6.0 * n ** 3
     cand = {
         "jacobi_f32_lds_kernel": {"bound": "alu", "achieved": jac_flops / (jac_ms * 1e-3) / 1e12,
-                       "peak": PEAK_FP32_VALU, "unit": "TFLOP/s"},
+                       "peak": PEAK_FP32_PUBLISHED, "unit": "TFLOP/s"},
         "refine": {"bound": "mfma", "achieved": ref_flops / (avg["refine"] * 1e-3) / 1e12,
                    "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s"},
     }
@@ -392,13 +455,52 @@ def main() -> int:
     dom = "jacobi_f32_lds_kernel"
     roof = dict(cand[dom])
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom) if B == 4096 else None
+    tr = measured_traffic(dom) if B == 4096 else None
+    roof["traffic"] = tr[0] if tr else None
+    roof["traffic_source"] = (f"stored rocprofv3 FETCH_SIZE/WRITE_SIZE summary of the same kernel sources "
+                              f"({os.path.relpath(tr[1], ROOT)})" if tr else
+                              "none: no counter summary of the current kernel sources")
+    roof["peak_nonpacked"] = PEAK_FP32_VALU
+    roof["frac_nonpacked"] = roof["achieved"] / PEAK_FP32_VALU
     roof["kernel"] = dom
+    roof["flop_per_item"] = jac_flops / (B * args.steps)
     roof["avg_launch_ms"] = jac_ms / jac_launches
     roof["launches_per_step"] = jac_launches / args.steps
     ref_roof = dict(cand["refine"])
     ref_roof["frac"] = ref_roof["achieved"] / ref_roof["peak"]
     ref_roof["kernel"] = "refinement stage (gemm_y, gemm_sg, refine_reach, refine_chain, gemm_xm x 2 steps, finish)"
+
+    # the paper's sequential operation count per channel (dense eigensolver
+    # 8/3 n^3 + 2 n^3 - n^2, T at n_E = N energies 6 N n_E) at this rate
+    paper_flop = 8.0 / 3.0 * n ** 3 + 2.0 * n ** 3 - n ** 2 + 6.0 * N_WP * N_WP
+    paper_model = {"flop_per_item": paper_flop, "achieved": value * paper_flop / 1e12, "unit": "TFLOP/s",
+                   "peak": PEAK_FP32_PUBLISHED, "frac": value * paper_flop / 1e12 / PEAK_FP32_PUBLISHED}
+
+    cold = None
+    if not args.no_cold:
+        # the same batch with every item started cold (wpcd_config.jacobi_start = 1)
+        del b, bufs
+        torch.cuda.synchronize()
+        cctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop, jacobi_start=1,
+                          refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
+                          refine_close_log10=args.refine_close)
+        cg = cctx.grid(k, configs.N_GAUSS)
+        cb = cctx.batch([(cg, N_CH, 1, s) for s in range(B)])
+        cbufs = cb.alloc()
+        cb.run(u, cbufs, wp.MIXED, tlab, sigma)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        for _ in range(args.steps):
+            cb.run(u, cbufs, wp.MIXED, tlab, sigma)
+        torch.cuda.synchronize()
+        cwall = time.perf_counter() - tc0
+        cst = cbufs["eig_status"].cpu().numpy()
+        cold = {"value": B * args.steps / cwall, "unit": "channel-solves/s", "ms_per_step": cwall / args.steps * 1e3,
+                "jacobi_sweeps_mean": float(cst[cst > 0].mean()) if (cst > 0).any() else None,
+                "note": "same batch and steps, every item started cold (wpcd_config.jacobi_start = 1)"}
+        log(f"cold starts: {cold['value']:.0f} channel-solves/s, {cold['ms_per_step']:.2f} ms/step")
+        del cb, cbufs
+        torch.cuda.synchronize()
 
     # plain FP64 path: one item per launch sequence, synchronised per item
     P = args.plain_items
@@ -451,7 +553,9 @@ def main() -> int:
         "jacobi_sweeps_mean": float(sweeps.mean()) if sweeps.size else None,
         "jacobi_rotated_fraction": counts["rotations"] / max(1, counts["pair_visits"]),
         "stages_ms_per_step": {s: ms / args.steps for s, (ms, cnt) in stages.items() if cnt},
+        "cold_start": cold,
         "roofline": roof,
+        "paper_model_rate": paper_model,
         "roofline_refine_stage": ref_roof,
         "cpu_baseline": cpu,
     }

@@ -38,10 +38,16 @@
  * Errors
  *   Every call returns a status: WPCD_OK or a negative WPCD_ERR_*.  Argument
  *   checks happen before any launch and return WPCD_ERR_INVALID with nothing
- *   enqueued.  A failed HIP call returns WPCD_ERR_DEVICE.  wpcd_last_error()
- *   returns a thread-local message describing the last failure of this thread.
+ *   enqueued.  A failed HIP call returns WPCD_ERR_DEVICE (WPCD_ERR_NOMEM for a
+ *   failed allocation).  WPCD_ERR_DEVICE from a compute call (wpcd_project*,
+ *   wpcd_eigh*, wpcd_tmatrix, wpcd_observables, wpcd_sigma_tot) is sticky:
+ *   every later compute call on the same context returns it too, with the
+ *   first failure's message, until wpcd_destroy.  wpcd_last_error() returns a
+ *   thread-local message describing the last failure of this thread.
  *   Per-item numerical failures are written to caller-provided int32 status
- *   arrays (one entry per item) instead of failing the whole call.
+ *   arrays (one entry per item) instead of failing the whole call; the
+ *   outputs of an item that wpcd_tmatrix flags are NaN (T, and from it the
+ *   phase shifts, mixing angles and its sample's cross sections).
  *
  * Threading: one context per device; calls on one context must not run
  * concurrently from several host threads.
@@ -60,10 +66,11 @@ enum {
   WPCD_OK = 0,
   WPCD_ERR_INVALID = -1,     /* bad argument, detected before any launch     */
   WPCD_ERR_NOMEM = -2,       /* device allocation failed                     */
-  WPCD_ERR_DEVICE = -3,      /* a HIP runtime call failed                    */
+  WPCD_ERR_DEVICE = -3,      /* a HIP runtime call failed; sticky for the
+                                compute calls of the context (below)        */
   WPCD_ERR_NOCONV = -4,      /* per item: Jacobi sweep cap reached           */
-  WPCD_ERR_AGAIN = -5,       /* reserved (asynchronous completion pending)   */
-  WPCD_ERR_BUSY = -6,        /* reserved (admission queue full)              */
+  WPCD_ERR_AGAIN = -5,       /* wpcd_poll: the request is still pending      */
+  WPCD_ERR_BUSY = -6,        /* wpcd_submit: the admission queue is full     */
   WPCD_ERR_NUMERIC = -7,     /* per item: NaN/Inf, zero eigenvalue, a
                                 scattering family with < 2 members, unsorted
                                 or zero-width scattering bins               */
@@ -179,6 +186,11 @@ typedef struct {
                        (wpcd_project_affine), which must match grid_id and
                        n_ch.  Such items take no space in u_fine and
                        n_terms entries in the packed coefficient array.   */
+  int32_t S;        /* total spin 0 or 1, or -1 (not given; only
+                       wpcd_saclay needs it)                               */
+  int32_t l;        /* orbital momentum of the first channel: l = J for
+                       uncoupled items (or 1 for 3P0, J = 0), J - 1 for
+                       coupled ones (S = 1); ignored when S = -1          */
 } wpcd_item;
 
 typedef struct {
@@ -263,6 +275,74 @@ int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* m
 int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev,
                    int n_tlab, double* sigma_mb, hipStream_t stream);
 
+/* ------------------------------------------------------ matrix inversion ----
+ * The paper's comparison method (Sec. 2.1, the wave-matrix form of the
+ * discretised LS equation and its K-matrix variant; Sec. 4.1, one LU
+ * factorisation per energy), batched over (item, energy) on the same device.
+ * For on-shell momentum p, the K-matrix equation with N_Q Gauss-Legendre
+ * nodes q_j, weights w_j on [0, L] (L = cutoff) and the pole subtracted,
+ *   (1 - U diag(D)) K = U,  D_j = w_j q_j^2/(p^2 - q_j^2)  (j < N_Q),
+ *   D_NQ = -p^2 sum_j w_j/(p^2 - q_j^2) + (p/2) ln((L + p)/(L - p)),
+ * over the nodes with p appended, is solved by Gaussian elimination with
+ * partial pivoting in FP64, one work-group per (item, energy).  The on-shell
+ * K_ab(p) gives S = (1 - i pi p K/2)(1 + i pi p K/2)^-1 (unitary), phase
+ * shifts and Stapp mixing angles (App. A), and the total cross section at p
+ * from the optical theorem in partial waves (no interpolation: every energy is
+ * solved exactly).  Energies come as T_lab values (p = sqrt(m_N T_lab/2)/hbar c,
+ * 0 < p < cutoff).  Sizes: n_ch (N_Q + 1) unknowns must fit the LDS as an
+ * augmented FP64 system: N_Q <= 140 uncoupled, <= 69 when any item is coupled
+ * (else WPCD_ERR_UNSUPPORTED).
+ * Per item (n_ch = K, P = N_Q + N_E points: the N_Q nodes, then the N_E
+ * on-shell momenta, from wpcd_mi_points):
+ *   u     : (K P)^2 doubles, U at the point set, row-major, channel-major rows
+ *           and columns (row a*P + i), symmetric; DEVICE, caller-owned
+ *   kmat  : N_E K^2 doubles, K_ab(p_e) at e*K*K + a*K + b
+ *   delta : N_E K phase shifts (deg, index e*K + a), mix: N_E mixing angles
+ *           (0 for uncoupled items)
+ *   sigma : n_samples x N_E total cross sections in mb (index s*N_E + e)
+ * status[i] = 0, or WPCD_ERR_NUMERIC (a zero or non-finite pivot; that item's
+ * outputs are NaN).                                                         */
+typedef struct wpcd_mi_s* wpcd_mi;
+typedef struct {
+  int32_t n_ch, J, sample_id, pad;
+} wpcd_mi_item;
+typedef struct {
+  int64_t u_elems, kmat_elems, delta_elems, mix_elems;
+  int32_t n_items, n_samples, n_q, n_e;
+} wpcd_mi_layout;
+int wpcd_mi_create(wpcd_ctx ctx, const wpcd_mi_item* items_host, int n_items, int n_q, double cutoff,
+                   const double* tlab_host, int n_e, wpcd_mi* out);
+void wpcd_mi_destroy(wpcd_mi m);
+/* the N_Q + N_E points (fm^-1) and the N_Q quadrature weights; either may be NULL */
+int wpcd_mi_points(wpcd_mi m, double* points_host, double* weights_host);
+/* sizes and per-item element offsets (host arrays of n_items; any may be NULL) */
+int wpcd_mi_layout_get(wpcd_mi m, wpcd_mi_layout* out, int64_t* u_off_host, int64_t* kmat_off_host,
+                       int64_t* delta_off_host, int64_t* mix_off_host);
+/* sigma_mb may be NULL (no cross sections) */
+int wpcd_mi_solve(wpcd_mi m, const double* u, double* kmat, double* delta_deg, double* mix_deg, double* sigma_mb,
+                  int32_t* status, hipStream_t stream);
+
+/* wpcd_saclay (App. A, spin-scattering matrix in partial waves, Saclay
+ * amplitudes, differential cross section): for every sample, T_lab energy e
+ * and c.m. scattering angle theta_j, the phases of each of the sample's items
+ * are interpolated at p as in wpcd_sigma_tot, S is rebuilt in the Stapp form,
+ * and the partial-wave sum
+ *   M^s_{ms,ms'} = (2 pi/(i p)) sum sqrt((2l+1)/(4 pi)) Y_{l'}^{ms-ms'}(theta, 0)
+ *                  <l' ms-ms', s ms'|J ms> <l 0, s ms|J ms> (S_{l'l} - delta_{l'l})
+ * (ms incoming, ms' outgoing spin projection; every (S, l, J) counted once,
+ * as for neutron-proton scattering) gives the Saclay amplitudes
+ *   a = (M11 + M00 - M1,-1)/2, b = (M11 + M^0_00 + M1,-1)/2,
+ *   c = (M11 - M^0_00 + M1,-1)/2, d = -(M10 + M01)/(sqrt2 sin theta)
+ *   (equivalently (M00 - a)/cos theta), e = i (M01 - M10)/sqrt2,
+ * and dsigma/dOmega = (|a|^2 + |b|^2 + |c|^2 + |d|^2 + |e|^2)/2.  Every item
+ * needs wpcd_item.S and .l.  tlab_mev (n_tlab) and theta_deg (n_theta) are
+ * DEVICE arrays, n_tlab * n_theta <= 1024; dsdo_mb: n_samples*n_tlab*n_theta
+ * (index (s*n_tlab + e)*n_theta + j) in mb/sr; amp (may be NULL): 10 doubles
+ * per (s, e, j), a..e as (re, im) in fm.  (2 pi/p) Im(a + b) at theta = 0 is
+ * the total cross section of wpcd_sigma_tot.                              */
+int wpcd_saclay(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev, int n_tlab,
+                const double* theta_deg, int n_theta, double* amp, double* dsdo_mb, hipStream_t stream);
+
 /* ---------------------------------------------------------------- serving --
  * A request loop over one context (the paper's posterior-sweep use case, Sec. 1
  * and Sec. 5: many independent parameter-vector solves).  A request is one
@@ -275,8 +355,12 @@ int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg,
  * one batch, and runs the whole path (affine projection, mixed-precision
  * eigensolver, T, phase shifts, cross sections) on that slot's stream, so
  * batches admitted while others run overlap on the device (continuous
- * batching).  Each item's arithmetic does not depend on the other items of its
- * batch.  Grids and bases stay resident; register all of them before
+ * batching).  An item's results depend on the other items of its batch only
+ * through rounding: the kernels a batch takes follow its size mix (the
+ * device-memory Jacobi's block width follows the largest n of its size class,
+ * the refinement's product kernels the smallest and largest n of the batch),
+ * and batches of the request loop always start cold.  Grids and bases stay
+ * resident; register all of them before
  * wpcd_server_create (the server snapshots the context's tables).  The
  * context must not be used for other compute calls while a server runs.
  *

@@ -131,6 +131,20 @@ def channel_loss(delta_deg: np.ndarray, eps_deg, kbar: np.ndarray, p, k_max: flo
     return total
 
 
+def sigma_from_s(channels, p) -> float:
+    """Total cross section in mb at momentum p from on-shell S matrices.
+
+    channels: iterable of (J, S) with S the K x K on-shell S-matrix of the
+    channel at p (App. A, optical theorem in partial waves, as in sigma_tot
+    but with no interpolation: the S matrices are those at p itself).
+    """
+    acc = 0.0
+    for J, s in channels:
+        s = np.atleast_2d(np.asarray(s))
+        acc += (2 * J + 1) * float(np.sum(1.0 - np.real(np.diag(s))))
+    return 10.0 * np.pi / (2.0 * p * p) * acc
+
+
 def sigma_tot(channels, kbar, tlab_mev, k_max) -> np.ndarray:
     """Total cross section in mb at the given T_lab values.
 

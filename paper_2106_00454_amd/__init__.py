@@ -36,9 +36,10 @@ DTYPE_F64 = 1
 EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wpcd_grid_create",
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
            "wpcd_batch_offsets", "wpcd_basis_register", "wpcd_project", "wpcd_project_affine", "wpcd_eigh",
-           "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_server_create", "wpcd_server_destroy",
+           "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_saclay", "wpcd_server_create", "wpcd_server_destroy",
            "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times",
-           "wpcd_jacobi_counts")
+           "wpcd_jacobi_counts", "wpcd_mi_create", "wpcd_mi_destroy", "wpcd_mi_points", "wpcd_mi_layout_get",
+           "wpcd_mi_solve")
 
 STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma", "warm_prep")
 
@@ -59,7 +60,8 @@ class _Config(ctypes.Structure):
 
 class _Item(ctypes.Structure):
     _fields_ = [("grid_id", ctypes.c_int32), ("n_ch", ctypes.c_int32), ("J", ctypes.c_int32),
-                ("sample_id", ctypes.c_int32), ("basis_id", ctypes.c_int32)]
+                ("sample_id", ctypes.c_int32), ("basis_id", ctypes.c_int32), ("S", ctypes.c_int32),
+                ("l", ctypes.c_int32)]
 
 
 class _Layout(ctypes.Structure):
@@ -67,6 +69,17 @@ class _Layout(ctypes.Structure):
                 ("t_doubles", ctypes.c_int64), ("delta_elems", ctypes.c_int64), ("mix_elems", ctypes.c_int64),
                 ("coef_elems", ctypes.c_int64), ("n_items", ctypes.c_int32), ("n_samples", ctypes.c_int32),
                 ("max_n", ctypes.c_int32), ("max_nbins", ctypes.c_int32)]
+
+
+class _MiItem(ctypes.Structure):
+    _fields_ = [("n_ch", ctypes.c_int32), ("J", ctypes.c_int32), ("sample_id", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class _MiLayout(ctypes.Structure):
+    _fields_ = [("u_elems", ctypes.c_int64), ("kmat_elems", ctypes.c_int64), ("delta_elems", ctypes.c_int64),
+                ("mix_elems", ctypes.c_int64), ("n_items", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("n_q", ctypes.c_int32), ("n_e", ctypes.c_int32)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -125,6 +138,7 @@ def lib() -> ctypes.CDLL:
         "wpcd_tmatrix": (i32, [vp, dp, dp, dp, i32, dp, dp, vp]),
         "wpcd_observables": (i32, [vp, dp, dp, dp, dp, vp]),
         "wpcd_sigma_tot": (i32, [vp, dp, dp, dp, i32, dp, vp]),
+        "wpcd_saclay": (i32, [vp, dp, dp, dp, i32, dp, i32, dp, dp, vp]),
         "wpcd_server_create": (i32, [vp, ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]),
         "wpcd_server_destroy": (None, [vp]),
         "wpcd_submit": (i32, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -133,6 +147,12 @@ def lib() -> ctypes.CDLL:
         "wpcd_profile_enable": (i32, [vp, i32]),
         "wpcd_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "wpcd_jacobi_counts": (i32, [vp, ctypes.POINTER(i64)]),
+        "wpcd_mi_create": (i32, [vp, ctypes.POINTER(_MiItem), i32, i32, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(vp)]),
+        "wpcd_mi_destroy": (None, [vp]),
+        "wpcd_mi_points": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "wpcd_mi_layout_get": (i32, [vp, ctypes.POINTER(_MiLayout)] + [ctypes.POINTER(i64)] * 4),
+        "wpcd_mi_solve": (i32, [vp, dp, dp, dp, dp, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -260,7 +280,9 @@ class Context:
         return Basis(bid.value, grid, n_ch, n_terms)
 
     def batch(self, items) -> "Batch":
-        """items: iterable of (grid, n_ch, J, sample_id) or (grid, n_ch, J, sample_id, basis)."""
+        """items: iterable of (grid, n_ch, J, sample_id[, basis[, S, l]]) (basis None:
+        fine-mesh input; S, l: total spin and first orbital momentum, needed by
+        Batch.saclay only)."""
         return Batch(self, list(items))
 
 
@@ -281,7 +303,8 @@ class Batch:
         for i, spec in enumerate(items):
             g, n_ch, J, sid = spec[:4]
             basis = spec[4] if len(spec) > 4 else None
-            arr[i] = _Item(g.id, n_ch, J, sid, -1 if basis is None else basis.id)
+            S, l = (spec[5], spec[6]) if len(spec) > 6 else (-1, -1)
+            arr[i] = _Item(g.id, n_ch, J, sid, -1 if basis is None else basis.id, S, l)
             self.grids.append(g)
             self.items.append((g, n_ch, J, sid))
         self.bases = [spec[4] if len(spec) > 4 else None for spec in items]
@@ -373,6 +396,19 @@ class Batch:
                                     _ptr(sigma, torch.float64, L["n_samples"] * n_tlab, "sigma"),
                                     _stream(stream)))
 
+    def saclay(self, delta, mix, tlab, theta_deg, amp, dsdo, stream=None):
+        """wpcd_saclay: Saclay amplitudes (amp: 10 doubles per sample, energy and
+        angle, or None) and dsigma/dOmega (mb/sr) at the T_lab values and c.m.
+        angles (degrees) given as device tensors."""
+        import torch
+        L = self.layout
+        nt, nth = tlab.numel(), theta_deg.numel()
+        ap = _ptr(amp, torch.float64, L["n_samples"] * nt * nth * 10, "amp") if amp is not None else ctypes.c_void_p(0)
+        _check(lib().wpcd_saclay(self._h, _ptr(delta, torch.float64, L["delta_elems"], "delta"),
+                                 _ptr(mix, torch.float64, L["mix_elems"], "mix"), _ptr(tlab, torch.float64, nt, "tlab"),
+                                 nt, _ptr(theta_deg, torch.float64, nth, "theta"), nth, ap,
+                                 _ptr(dsdo, torch.float64, L["n_samples"] * nt * nth, "dsdo"), _stream(stream)))
+
     def run(self, u, bufs, mode, tlab=None, sigma=None, stream=None, coef=None):
         """The whole path for this batch on one stream: fine-mesh items
         projected from `u`, basis items from `coef`, then eigenpairs, T,
@@ -386,6 +422,64 @@ class Batch:
         self.observables(bufs["t"], bufs["delta"], bufs["mix"], bufs["s_dev"], stream)
         if tlab is not None:
             self.sigma_tot(bufs["delta"], bufs["mix"], tlab, sigma, stream)
+
+
+# ---------------------------------------------------------------- matrix inversion
+class MiSolver:
+    """Batched matrix-inversion (K-matrix) solver: items (n_ch, J, sample_id)
+    solved at every T_lab of the list with n_q Gauss nodes on [0, cutoff]."""
+
+    def __init__(self, ctx: Context, items, n_q: int, cutoff: float, tlab):
+        arr = (_MiItem * len(items))()
+        for i, (n_ch, J, sid) in enumerate(items):
+            arr[i] = _MiItem(n_ch, J, sid, 0)
+        tl = np.ascontiguousarray(tlab, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().wpcd_mi_create(ctx._h, arr, len(items), n_q, cutoff,
+                                    tl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tl.size, ctypes.byref(h)))
+        self._h = h
+        self.ctx = ctx
+        self.items = list(items)
+        self.n_q, self.n_e = n_q, tl.size
+        pts, w = np.empty(n_q + tl.size), np.empty(n_q)
+        _check(lib().wpcd_mi_points(h, pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self.points, self.weights = pts, w
+        lay = _MiLayout()
+        offs = [np.zeros(len(items), dtype=np.int64) for _ in range(4)]
+        _check(lib().wpcd_mi_layout_get(h, ctypes.byref(lay),
+                                        *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) for o in offs]))
+        self.layout = {f: getattr(lay, f) for f, _ in _MiLayout._fields_}
+        self.u_off, self.k_off, self.delta_off, self.mix_off = offs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wpcd_mi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self, device="cuda"):
+        import torch
+        L = self.layout
+        f64 = dict(dtype=torch.float64, device=device)
+        return {"kmat": torch.empty(L["kmat_elems"], **f64), "delta": torch.empty(L["delta_elems"], **f64),
+                "mix": torch.empty(L["mix_elems"], **f64), "sigma": torch.empty(L["n_samples"] * L["n_e"], **f64),
+                "status": torch.empty(L["n_items"], dtype=torch.int32, device=device)}
+
+    def solve(self, u, bufs, stream=None, sigma=True):
+        import torch
+        L = self.layout
+        sg = _ptr(bufs["sigma"], torch.float64, L["n_samples"] * L["n_e"], "sigma") if sigma else ctypes.c_void_p(0)
+        _check(lib().wpcd_mi_solve(self._h, _ptr(u, torch.float64, L["u_elems"], "u"),
+                                   _ptr(bufs["kmat"], torch.float64, L["kmat_elems"], "kmat"),
+                                   _ptr(bufs["delta"], torch.float64, L["delta_elems"], "delta"),
+                                   _ptr(bufs["mix"], torch.float64, L["mix_elems"], "mix"), sg,
+                                   _ptr(bufs["status"], torch.int32, L["n_items"], "status"), _stream(stream)))
 
 
 # ---------------------------------------------------------------- serving

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwpcd.so")
-SOURCES = ["api.hip", "project.hip", "jacobi_lds.hip", "jacobi_dev.hip", "refine.hip", "tmatrix.hip", "observables.hip", "serve.cpp"]
+SOURCES = ["api.hip", "project.hip", "jacobi_lds.hip", "jacobi_dev.hip", "refine.hip", "tmatrix.hip", "observables.hip", "mi.hip",
+           "serve.cpp"]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for all device code
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

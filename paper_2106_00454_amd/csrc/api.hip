@@ -42,6 +42,32 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// A failed HIP call inside a compute call leaves the context's device state
+// unknown: the first such failure is recorded, and every later compute call
+// on the context returns WPCD_ERR_DEVICE with its message (allocation
+// failures are not recorded: they leave nothing half done).
+int dev_fail(wpcd_ctx ctx, hipError_t e, const char* what) {
+  const int code = hip_fail(e, what);
+  if (code == WPCD_ERR_DEVICE && !ctx->sticky) {
+    ctx->sticky = true;
+    ctx->sticky_msg = g_err;
+  }
+  return code;
+}
+
+#define WPCD_HIPX(ctx, call, what)                       \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return dev_fail(ctx, e_, what); \
+  } while (0)
+
+// Entry check of the compute calls: a recorded device failure is sticky.
+#define WPCD_STICKY(ctx)                                                                                  \
+  do {                                                                                                    \
+    if ((ctx)->sticky)                                                                                    \
+      return fail(WPCD_ERR_DEVICE, "an earlier call failed on the device: %s", (ctx)->sticky_msg.c_str()); \
+  } while (0)
+
 // Runs `launch` (returning hipError_t) between two events on `stream` when the
 // context's stage timers are on.
 template <class F>
@@ -308,6 +334,22 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     d.J = in.J;
     d.sample = in.sample_id;
     d.basis = in.basis_id;
+    // spin and orbital momenta (needed by wpcd_saclay only): S = -1 leaves them unset
+    if (in.S != -1) {
+      const bool ok = in.n_ch == 2 ? (in.S == 1 && in.l == in.J - 1)
+                                   : ((in.S == 0 && in.l == in.J) || (in.S == 1 && in.l >= 0 && (in.l == in.J ||
+                                       (in.J == 0 && in.l == 1))));
+      if (!ok) {
+        delete b;
+        return fail(WPCD_ERR_INVALID, "item %d: (S, l, J) = (%d, %d, %d) is not a channel of a spin-1/2 pair "
+                                      "(uncoupled: l = J, or 3P0; coupled: S = 1, l = J - 1)", i, in.S, in.l, in.J);
+      }
+      d.spin = in.S;
+      d.l0 = in.l;
+    } else {
+      d.spin = -1;
+      d.l0 = -1;
+    }
     const int64_t M = in.basis_id >= 0 ? 0 : (int64_t)n * g.ng;
     d.u_off = b->u_elems;
     d.c_off = b->coef_elems;
@@ -530,12 +572,13 @@ int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hip
   if (!b || !u_fine || !v64) return fail(WPCD_ERR_INVALID, "wpcd_project: NULL argument");
   if (u_dtype != WPCD_DTYPE_F32 && u_dtype != WPCD_DTYPE_F64)
     return fail(WPCD_ERR_INVALID, "wpcd_project: unknown u_dtype %d", u_dtype);
-  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
   if (b->n_fine == 0) return WPCD_OK;
   const int elem = u_dtype == WPCD_DTYPE_F32 ? 4 : 8;
   bool generic = false;
   for (const ItemDev& it : b->h_items) generic = generic || (it.basis < 0 && !project_tiled(it, u_fine, elem));
-  WPCD_HIP(timed(b->ctx, WPCD_STAGE_PROJECT, stream,
+  WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_PROJECT, stream,
                  [&] { return launch_project(b->d_items, b->n_items, b->max_n, b->d_grids, u_fine, u_dtype, v64,
                                        generic, stream); }),
            "wpcd_project launch");
@@ -544,9 +587,10 @@ int wpcd_project(wpcd_batch b, const void* u_fine, int u_dtype, double* v64, hip
 
 int wpcd_project_affine(wpcd_batch b, const double* coef, double* v64, hipStream_t stream) {
   if (!b || !v64 || (!coef && b->coef_elems > 0)) return fail(WPCD_ERR_INVALID, "wpcd_project_affine: NULL argument");
-  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
   if (b->n_affine == 0) return WPCD_OK;
-  WPCD_HIP(timed(b->ctx, WPCD_STAGE_PROJECT, stream,
+  WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_PROJECT, stream,
                  [&] {
                    return launch_project_affine(b->d_items, b->n_items, b->max_n, b->d_bases, coef, v64, stream);
                  }),
@@ -611,7 +655,8 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
               hipStream_t stream) {
   if (!b || !v64 || !eval || !evec || !status) return fail(WPCD_ERR_INVALID, "wpcd_eigh: NULL argument");
   if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_eigh: unknown mode %d", mode);
-  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
   const wpcd_config& c = b->ctx->cfg;
   if (mode == WPCD_MIXED) {
     if (c.refine_steps < 1)
@@ -620,9 +665,21 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
     // loop never needs it, and every stream takes a share of the hardware
     // queues its own streams use)
     if (b->ctx->side == nullptr) {
-      WPCD_HIP(hipStreamCreateWithFlags(&b->ctx->side, hipStreamNonBlocking), "wpcd_eigh: side stream");
-      WPCD_HIP(hipEventCreateWithFlags(&b->ctx->fork, hipEventDisableTiming), "wpcd_eigh: events");
-      WPCD_HIP(hipEventCreateWithFlags(&b->ctx->join, hipEventDisableTiming), "wpcd_eigh: events");
+      // all three or none: a partial set would pass null events to later calls
+      hipStream_t side = nullptr;
+      hipEvent_t fork = nullptr, join = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        if (join) hipEventDestroy(join);
+        if (fork) hipEventDestroy(fork);
+        if (side) hipStreamDestroy(side);
+        return dev_fail(b->ctx, e, "wpcd_eigh: second stream and its events");
+      }
+      b->ctx->side = side;
+      b->ctx->fork = fork;
+      b->ctx->join = join;
     }
     // one FP32 Jacobi launch per size class: LDS-resident up to n = kMaxLdsN,
     // device memory above
@@ -651,17 +708,17 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
       const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
       const bool side_pick = n_warm > 0 && b->n_pick > 0;
       if (side_pick) {
-        WPCD_HIP(hipEventRecord(b->ctx->fork, stream), "wpcd_eigh: fork");
-        WPCD_HIP(hipStreamWaitEvent(b->ctx->side, b->ctx->fork, 0), "wpcd_eigh: fork");
-        WPCD_HIP(launch_warm_pick(b->d_items, b->n_items, b->d_jlist, b->d_pick, b->n_pick, b->d_cand, b->d_sig, v64,
+        WPCD_HIPX(b->ctx, hipEventRecord(b->ctx->fork, stream), "wpcd_eigh: fork");
+        WPCD_HIPX(b->ctx, hipStreamWaitEvent(b->ctx->side, b->ctx->fork, 0), "wpcd_eigh: fork");
+        WPCD_HIPX(b->ctx, launch_warm_pick(b->d_items, b->n_items, b->d_jlist, b->d_pick, b->n_pick, b->d_cand, b->d_sig, v64,
                                   b->d_ref, b->ctx->side),
                  "wpcd_eigh: reference choice launch");
-        WPCD_HIP(hipEventRecord(b->ctx->join, b->ctx->side), "wpcd_eigh: join");
+        WPCD_HIPX(b->ctx, hipEventRecord(b->ctx->join, b->ctx->side), "wpcd_eigh: join");
       }
-      for (int k = 0; k < L; ++k) WPCD_HIP(solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
-      if (side_pick) WPCD_HIP(hipStreamWaitEvent(stream, b->ctx->join, 0), "wpcd_eigh: join");
+      for (int k = 0; k < L; ++k) WPCD_HIPX(b->ctx, solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
+      if (side_pick) WPCD_HIPX(b->ctx, hipStreamWaitEvent(stream, b->ctx->join, 0), "wpcd_eigh: join");
       if (n_warm > 0) {
-        WPCD_HIP(timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
+        WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
                        [&] {
                          return launch_jacobi_warm_prep(b->d_items, b->n_items, b->d_jlist + b->jl_ptr[2 * L],
                                                         b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L],
@@ -672,9 +729,9 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                        }),
                  "wpcd_eigh: warm-start preparation launch");
       }
-      for (int k = 0; k < L; ++k) WPCD_HIP(solve(L + k, k, b->d_ref), "wpcd_eigh: FP32 Jacobi launch");
+      for (int k = 0; k < L; ++k) WPCD_HIPX(b->ctx, solve(L + k, k, b->d_ref), "wpcd_eigh: FP32 Jacobi launch");
     }
-    WPCD_HIP(timed(b->ctx, WPCD_STAGE_REFINE, stream,
+    WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_REFINE, stream,
                    [&] {
                      return launch_refine(b->d_items, b->n_items, b->min_n, b->max_n, b->d_grids, v64, b->d_x32,
                                           evec, eval,
@@ -684,7 +741,7 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                    }),
              "wpcd_eigh: FP64 refinement launch");
   } else {
-    WPCD_HIP(timed(b->ctx, WPCD_STAGE_JACOBI_F64, stream,
+    WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_JACOBI_F64, stream,
                    [&] {
                      return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids, v64,
                                                  b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
@@ -699,8 +756,9 @@ int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const doub
                  int32_t* status, hipStream_t stream) {
   if (!b || !v64 || !eval || !evec || !t || !status) return fail(WPCD_ERR_INVALID, "wpcd_tmatrix: NULL argument");
   if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_tmatrix: unknown mode %d", mode);
-  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(timed(b->ctx, WPCD_STAGE_TMATRIX, stream,
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_TMATRIX, stream,
                  [&] {
                    return launch_tmatrix(b->d_items, b->n_items, b->max_n, b->d_grids, v64, eval, evec, mode, t, status,
                                          stream);
@@ -712,13 +770,37 @@ int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const doub
 int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* mix_deg, double* s_dev,
                      hipStream_t stream) {
   if (!b || !t || !delta_deg || !mix_deg) return fail(WPCD_ERR_INVALID, "wpcd_observables: NULL argument");
-  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(timed(b->ctx, WPCD_STAGE_OBSERVABLES, stream,
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_OBSERVABLES, stream,
                  [&] {
                    return launch_observables(b->d_items, b->n_items, b->max_nbins, b->d_grids, t, delta_deg, mix_deg,
                                              s_dev, stream);
                  }),
            "wpcd_observables launch");
+  return WPCD_OK;
+}
+
+int wpcd_saclay(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev, int n_tlab,
+                const double* theta_deg, int n_theta, double* amp, double* dsdo_mb, hipStream_t stream) {
+  if (!b || !delta_deg || !mix_deg || !tlab_mev || !theta_deg || !dsdo_mb)
+    return fail(WPCD_ERR_INVALID, "wpcd_saclay: NULL argument");
+  if (n_tlab < 1 || n_theta < 1 || (int64_t)n_tlab * n_theta > 1024)
+    return fail(WPCD_ERR_INVALID, "wpcd_saclay: need n_tlab, n_theta >= 1 and n_tlab * n_theta <= 1024");
+  if (b->max_nbins > 1200) return fail(WPCD_ERR_UNSUPPORTED, "wpcd_saclay: more than 1200 bins");
+  for (int i = 0; i < b->n_items; ++i)
+    if (b->h_items[i].spin < 0)
+      return fail(WPCD_ERR_INVALID, "wpcd_saclay: item %d has no spin and orbital momentum (wpcd_item.S, .l)", i);
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  WPCD_HIPX(b->ctx,
+            timed(b->ctx, WPCD_STAGE_SIGMA, stream,
+                  [&] {
+                    return launch_saclay(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples, b->d_grids,
+                                         delta_deg, mix_deg, tlab_mev, n_tlab, theta_deg, n_theta, amp, dsdo_mb,
+                                         stream);
+                  }),
+            "wpcd_saclay launch");
   return WPCD_OK;
 }
 
@@ -728,13 +810,174 @@ int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg,
     return fail(WPCD_ERR_INVALID, "wpcd_sigma_tot: NULL argument");
   if (n_tlab < 1 || n_tlab > 1024) return fail(WPCD_ERR_INVALID, "wpcd_sigma_tot: n_tlab must be in [1, 1024]");
   if (b->max_nbins > 1200) return fail(WPCD_ERR_UNSUPPORTED, "wpcd_sigma_tot: more than 1200 bins");
-  WPCD_HIP(hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_HIP(timed(b->ctx, WPCD_STAGE_SIGMA, stream,
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_SIGMA, stream,
                  [&] {
                    return launch_sigma(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples, b->d_grids,
                                        delta_deg, mix_deg, tlab_mev, nullptr, n_tlab, sigma_mb, stream);
                  }),
            "wpcd_sigma_tot launch");
+  return WPCD_OK;
+}
+
+// ------------------------------------------------------- matrix inversion
+void wpcd_mi_destroy(wpcd_mi m) {
+  if (!m) return;
+  hipSetDevice(m->ctx->device);
+  hipFree(m->d_items);
+  hipFree(m->d_pts);
+  hipFree(m->d_qw);
+  hipFree(m->d_loss);
+  hipFree(m->d_sample_ptr);
+  hipFree(m->d_sample_items);
+  delete m;
+}
+
+int wpcd_mi_create(wpcd_ctx ctx, const wpcd_mi_item* items_host, int n_items, int n_q, double cutoff,
+                   const double* tlab_host, int n_e, wpcd_mi* out) {
+  if (!ctx || !items_host || !tlab_host || !out) return fail(WPCD_ERR_INVALID, "wpcd_mi_create: NULL argument");
+  *out = nullptr;
+  if (n_items < 1 || n_items > 65535) return fail(WPCD_ERR_INVALID, "wpcd_mi_create: n_items must be in [1, 65535]");
+  if (n_e < 1 || n_e > 4096) return fail(WPCD_ERR_INVALID, "wpcd_mi_create: n_e must be in [1, 4096]");
+  if (n_q < 2) return fail(WPCD_ERR_INVALID, "wpcd_mi_create: n_q must be >= 2");
+  if (!(cutoff > 0.0) || !isfinite(cutoff)) return fail(WPCD_ERR_INVALID, "wpcd_mi_create: cutoff must be > 0");
+  wpcd_mi_s* m = new (std::nothrow) wpcd_mi_s;
+  if (!m) return fail(WPCD_ERR_NOMEM, "wpcd_mi_create: host allocation");
+  m->ctx = ctx;
+  m->n_items = n_items;
+  m->nq = n_q;
+  m->ne = n_e;
+  m->cutoff = cutoff;
+  int max_sample = -1;
+  m->h_items.resize(n_items);
+  for (int i = 0; i < n_items; ++i) {
+    const wpcd_mi_item& in = items_host[i];
+    if ((in.n_ch != 1 && in.n_ch != 2) || in.J < 0 || (in.n_ch == 2 && in.J < 1) || in.sample_id < 0) {
+      delete m;
+      return fail(WPCD_ERR_INVALID, "wpcd_mi_create: item %d: need n_ch 1 or 2, J >= 0 (>= 1 if coupled), "
+                                    "sample_id >= 0", i);
+    }
+    MiItemDev& d = m->h_items[i];
+    const int K = in.n_ch;
+    d.nch = K;
+    d.J = in.J;
+    d.sample = in.sample_id;
+    d.pad = 0;
+    d.u_off = m->u_elems;
+    d.k_off = m->k_elems;
+    d.d_off = m->d_elems;
+    d.m_off = m->m_elems;
+    const int64_t lu = (int64_t)K * (n_q + n_e);
+    m->u_elems += lu * lu;
+    m->k_elems += (int64_t)n_e * K * K;
+    m->d_elems += (int64_t)n_e * K;
+    m->m_elems += n_e;
+    m->max_nch = std::max(m->max_nch, K);
+    max_sample = std::max(max_sample, in.sample_id);
+  }
+  m->n_samples = max_sample + 1;
+  if (n_q > kMaxMiNq || mi_lds_bytes(n_q, m->max_nch) > 160 * 1024 - 4096) {
+    delete m;
+    return fail(WPCD_ERR_UNSUPPORTED, "wpcd_mi_create: n_q = %d too large for %s items (the system must fit the LDS)",
+                n_q, m->max_nch == 2 ? "coupled" : "uncoupled");
+  }
+  // Gauss-Legendre nodes on [0, cutoff], then the on-shell momenta
+  std::vector<double> x, w;
+  gauss_legendre(n_q, x, w);
+  m->pts.resize(n_q + n_e);
+  m->wts.resize(n_q);
+  for (int j = 0; j < n_q; ++j) {
+    m->pts[j] = 0.5 * cutoff * (x[j] + 1.0);
+    m->wts[j] = 0.5 * cutoff * w[j];
+  }
+  for (int e = 0; e < n_e; ++e) {
+    const double t = tlab_host[e];
+    const double p = sqrt(938.918 * t / 2.0) / 197.327;
+    if (!(t > 0.0) || !(p < cutoff)) {
+      delete m;
+      return fail(WPCD_ERR_INVALID, "wpcd_mi_create: T_lab[%d] = %g gives p outside (0, cutoff)", e, t);
+    }
+    for (int j = 0; j < n_q; ++j)
+      if (m->pts[j] == p) {
+        delete m;
+        return fail(WPCD_ERR_INVALID, "wpcd_mi_create: T_lab[%d] puts p on a quadrature node", e);
+      }
+    m->pts[n_q + e] = p;
+  }
+  std::vector<int32_t> sptr(m->n_samples + 1, 0), sitems(n_items);
+  for (int i = 0; i < n_items; ++i) sptr[items_host[i].sample_id + 1]++;
+  for (int s = 0; s < m->n_samples; ++s) sptr[s + 1] += sptr[s];
+  {
+    std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+    for (int i = 0; i < n_items; ++i) sitems[fill[items_host[i].sample_id]++] = i;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  auto alloc = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes > 0 ? bytes : 1);
+  };
+  alloc((void**)&m->d_items, sizeof(MiItemDev) * n_items);
+  alloc((void**)&m->d_pts, sizeof(double) * m->pts.size());
+  alloc((void**)&m->d_qw, sizeof(double) * n_q);
+  alloc((void**)&m->d_loss, sizeof(double) * (size_t)n_items * n_e);
+  alloc((void**)&m->d_sample_ptr, sizeof(int32_t) * sptr.size());
+  alloc((void**)&m->d_sample_items, sizeof(int32_t) * sitems.size());
+  if (e == hipSuccess) e = hipMemcpy(m->d_items, m->h_items.data(), sizeof(MiItemDev) * n_items, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->d_pts, m->pts.data(), sizeof(double) * m->pts.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->d_qw, m->wts.data(), sizeof(double) * n_q, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->d_sample_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->d_sample_items, sitems.data(), sizeof(int32_t) * sitems.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    wpcd_mi_destroy(m);
+    return hip_fail(e, "wpcd_mi_create");
+  }
+  *out = m;
+  return WPCD_OK;
+}
+
+int wpcd_mi_points(wpcd_mi m, double* points_host, double* weights_host) {
+  if (!m) return fail(WPCD_ERR_INVALID, "wpcd_mi_points: NULL solver");
+  if (points_host) std::copy(m->pts.begin(), m->pts.end(), points_host);
+  if (weights_host) std::copy(m->wts.begin(), m->wts.end(), weights_host);
+  return WPCD_OK;
+}
+
+int wpcd_mi_layout_get(wpcd_mi m, wpcd_mi_layout* out, int64_t* u_off_host, int64_t* k_off_host,
+                       int64_t* delta_off_host, int64_t* mix_off_host) {
+  if (!m) return fail(WPCD_ERR_INVALID, "wpcd_mi_layout_get: NULL solver");
+  if (out) {
+    out->u_elems = m->u_elems;
+    out->kmat_elems = m->k_elems;
+    out->delta_elems = m->d_elems;
+    out->mix_elems = m->m_elems;
+    out->n_items = m->n_items;
+    out->n_samples = m->n_samples;
+    out->n_q = m->nq;
+    out->n_e = m->ne;
+  }
+  for (int i = 0; i < m->n_items; ++i) {
+    const MiItemDev& d = m->h_items[i];
+    if (u_off_host) u_off_host[i] = d.u_off;
+    if (k_off_host) k_off_host[i] = d.k_off;
+    if (delta_off_host) delta_off_host[i] = d.d_off;
+    if (mix_off_host) mix_off_host[i] = d.m_off;
+  }
+  return WPCD_OK;
+}
+
+int wpcd_mi_solve(wpcd_mi m, const double* u, double* kmat, double* delta_deg, double* mix_deg, double* sigma_mb,
+                  int32_t* status, hipStream_t stream) {
+  if (!m || !u || !kmat || !delta_deg || !mix_deg || !status)
+    return fail(WPCD_ERR_INVALID, "wpcd_mi_solve: NULL argument");
+  WPCD_HIPX(m->ctx, hipSetDevice(m->ctx->device), "hipSetDevice");
+  WPCD_STICKY(m->ctx);
+  WPCD_HIPX(m->ctx,
+            launch_mi_solve(m->d_items, m->n_items, m->nq, m->ne, m->max_nch, m->d_qw, m->d_pts, m->cutoff, u, kmat,
+                            delta_deg, mix_deg, m->d_loss, m->d_sample_ptr, m->d_sample_items,
+                            sigma_mb ? m->n_samples : 0, sigma_mb, status, stream),
+            "wpcd_mi_solve launch");
   return WPCD_OK;
 }
 

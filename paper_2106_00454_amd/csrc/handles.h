@@ -1,6 +1,7 @@
 // Host-side handle types of the C ABI (shared by the library's host sources).
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -43,6 +44,10 @@ struct wpcd_context {
   // second stream of the refinement (default priority) and its fork/join events
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // first failed HIP call of a compute call (then every compute call returns
+  // WPCD_ERR_DEVICE)
+  bool sticky = false;
+  std::string sticky_msg;
 };
 
 struct wpcd_batch_s {
@@ -85,3 +90,17 @@ struct wpcd_batch_s {
   int n_pick = 0;
 };
 
+struct wpcd_mi_s {
+  wpcd_ctx ctx = nullptr;
+  int n_items = 0, n_samples = 0, nq = 0, ne = 0, max_nch = 0;
+  double cutoff = 0.0;
+  std::vector<wpcd::MiItemDev> h_items;
+  std::vector<double> pts, wts;  // N_Q nodes then the N_E on-shell momenta; N_Q weights
+  int64_t u_elems = 0, k_elems = 0, d_elems = 0, m_elems = 0;
+  wpcd::MiItemDev* d_items = nullptr;
+  double* d_pts = nullptr;   // N_Q + N_E points
+  double* d_qw = nullptr;    // N_Q weights
+  double* d_loss = nullptr;  // per (item, energy): (2J+1) sum_a (1 - Re S_aa)
+  int32_t* d_sample_ptr = nullptr;
+  int32_t* d_sample_items = nullptr;
+};

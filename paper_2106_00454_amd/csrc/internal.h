@@ -33,6 +33,8 @@ struct ItemDev {
   int32_t J;
   int32_t sample;
   int32_t basis;   // -1: fine-mesh potential; >= 0: index into the basis table
+  int32_t spin;    // total spin S (0 or 1), -1 if not given
+  int32_t l0;      // orbital l of the first channel (J - 1 for coupled items), -1 if not given
   int64_t u_off;   // elements into u_fine
   int64_t v_off;   // elements into v64 / evec (n*n)
   int64_t e_off;   // elements into eval (n)
@@ -119,9 +121,34 @@ hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const Gr
                           hipStream_t s);
 hipError_t launch_observables(const ItemDev* items, int n_items, int max_nbins, const GridDev* grids,
                               const double* t, double* delta, double* mix, double* s_dev, hipStream_t s);
+hipError_t launch_saclay(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
+                         int n_samples, const GridDev* grids, const double* delta, const double* mix,
+                         const double* tlab, int n_tlab, const double* theta_deg, int n_theta, double* amp,
+                         double* dsdo, hipStream_t s);
 hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
                         int n_samples, const GridDev* grids, const double* delta, const double* mix,
                         const double* tlab, const int32_t* tlab_off, int n_tlab, double* sigma, hipStream_t s);
+
+// Matrix-inversion solver (the paper's comparison method): one item = one
+// channel of one sample, solved at every energy of the solver object.
+struct MiItemDev {
+  int32_t nch;     // 1 or 2
+  int32_t J;
+  int32_t sample;
+  int32_t pad;
+  int64_t u_off;   // elements into u: (nch (N_Q + N_E))^2, channel-major
+  int64_t k_off;   // elements into kmat: N_E nch^2
+  int64_t d_off;   // elements into delta: N_E nch
+  int64_t m_off;   // elements into mix: N_E
+};
+// Largest quadrature mesh of the MI solver (the augmented FP64 system of an
+// uncoupled item, 141 x 142 doubles, fills the LDS; coupled items: 69).
+constexpr int kMaxMiNq = 140;
+size_t mi_lds_bytes(int nq, int K);
+hipError_t launch_mi_solve(const MiItemDev* items, int n_items, int nq, int ne, int max_nch, const double* qw,
+                           const double* pts, double cutoff, const double* u, double* kmat, double* delta,
+                           double* mix, double* loss, const int32_t* sample_ptr, const int32_t* sample_items,
+                           int n_samples, double* sigma, int32_t* status, hipStream_t s);
 
 // Per-item device work-space (doubles) of the eigensolvers for an n x n item:
 // P1 | Y | S | G | W5 | W6 | W7 for the refinement; the device-memory Jacobi

@@ -585,7 +585,9 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   __syncthreads();
   // chains = unions of overlapping [p, reach[p]] with at least two columns;
   // one thread walks the reach list in LDS and overwrites it in place with
-  // each column's chain position (or -1), then all threads copy it to cl
+  // each column's chain position (or -1).  The positions stay in LDS: cl is
+  // read-only here, because form_m_kernel reads the same reach list from cl
+  // at the same time on the side stream
   if (threadIdx.x == 0) {
     int T = 0, fail = 0, i = 0, nch = 0, nbig = 0;
     while (i < n) {

@@ -222,6 +222,8 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
         it.J = ch.J;
         it.sample = (int32_t)r;
         it.basis = ch.basis;
+        it.spin = -1;
+        it.l0 = -1;
         it.u_off = 0;
         it.v_off = v;
         it.e_off = e;

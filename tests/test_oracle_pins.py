@@ -343,6 +343,17 @@ def test_sigma_coupled_mixing_branch_against_closed_form():
     assert (odd[i] != odd[i - 1]).any()
 
 
+def test_sigma_from_s_textbook_forms():
+    # single wave: S = exp(2 i d) -> (pi/p^2)(2J+1) sin^2 d / 2 ... per partial wave
+    # (np-like weights): 10 pi/(2 p^2) (2J+1) (1 - cos 2d) = 10 pi/p^2 (2J+1) sin^2 d
+    p, d = 0.7, np.radians(37.0)
+    assert abs(observables.sigma_from_s([(2, np.exp(2j * d))], p) - 10 * np.pi / p ** 2 * 5 * np.sin(d) ** 2) < 1e-12
+    # coupled Stapp S: (2J+1)(2 - cos 2e (cos 2d- + cos 2d+))
+    s = observables.stapp_s(20.0, -35.0, 7.0)
+    want = 10 * np.pi / (2 * p * p) * 3 * (2 - np.cos(np.radians(14)) * (np.cos(np.radians(40)) + np.cos(np.radians(-70))))
+    assert abs(observables.sigma_from_s([(1, s)], p) - want) < 1e-12
+
+
 def test_tlab_kinematics():
     # E_cm = T_lab/2 = (hbar c p)^2/m_N for equal masses
     p = observables.tlab_to_p([1.0, 40.0, 350.0])
