@@ -4,9 +4,10 @@ Conventions:
 * on-shell S = 1 - i pi p t(p,p) for reduced t (App. A, the S-T relation,
   with the phase-space factor of the <k'|k> = delta/(k'k) normalisation);
   uncoupled S = exp(2 i delta) (App. A);
-* the packet T-matrix maps to the continuum as t(q,q) = T_kk/(dk_k q^2) at
-  the bin midpoint q = kbar_k (Sec. 3.1, operator transfer between the packet
-  and continuum bases; Sec. 3.2, choice of on-shell q);
+* the packet T-matrix maps to the continuum as t(q,q) = f(q)^2 T_kk/(N_k q^2)
+  (Sec. 3.1, operator transfer between the packet and continuum bases): for
+  momentum packets T_kk/(dk_k q^2) at the bin midpoint q = kbar_k (Sec. 3.2,
+  choice of on-shell q);
 * Stapp parametrisation of the coupled 2x2 S (App. A): S_11 = cos(2 eps)
   exp(2 i delta_-), S_22 = cos(2 eps) exp(2 i delta_+),
   S_12 = S_21 = i sin(2 eps) exp(i (delta_- + delta_+));
@@ -34,11 +35,15 @@ def tlab_to_p(tlab_mev):
     return np.sqrt(M_N_MEV * np.asarray(tlab_mev, dtype=np.float64) / 2.0) / HBARC_MEV_FM
 
 
-def s_matrix(t_wp: np.ndarray, dk: np.ndarray, kbar: np.ndarray) -> np.ndarray:
-    """S(kbar_k) = 1 - i pi kbar t,  t = T/(dk kbar^2), for T of shape (N, K, K)."""
+def s_matrix(t_wp: np.ndarray, norm: np.ndarray, q: np.ndarray, f2=None) -> np.ndarray:
+    """S(q_k) = 1 - i pi q t,  t = f(q)^2 T/(N_k q^2), for T of shape (N, K, K).
+
+    norm: the packet normalisation N_k (dk_k for momentum packets), q: the
+    on-shell momenta, f2: f(q)^2 (None: 1, momentum packets)."""
     n_ch = t_wp.shape[1]
-    t = t_wp / (dk * kbar * kbar)[:, None, None]
-    return np.eye(n_ch)[None, :, :] - 1j * np.pi * kbar[:, None, None] * t
+    f2 = np.ones_like(q) if f2 is None else np.asarray(f2, dtype=np.float64)
+    t = t_wp * (f2 / (norm * q * q))[:, None, None]
+    return np.eye(n_ch)[None, :, :] - 1j * np.pi * q[:, None, None] * t
 
 
 def s_from_t_continuum(t: np.ndarray, p) -> np.ndarray:
@@ -103,6 +108,30 @@ def interpolate(kbar: np.ndarray, y: np.ndarray, p, k_max: float):
     x0, x1 = kbar[i - 1], kbar[i]
     y0, y1 = y[i - 1], y[i]
     return y0 + (y1 - y0) * (p - x0) / (x1 - x0)
+
+
+def interpolation_points(k_bounds, frac: float):
+    """Abscissae q_i = k_{i-1} + frac (k_i - k_{i-1}) to which the bin values
+    are assigned before interpolating (Sec. 5.1.1, the interpolation point
+    n/m of a bin; frac = n/m = 1/2 is the midpoint)."""
+    k = np.asarray(k_bounds, dtype=np.float64)
+    if not (0.0 <= frac <= 1.0):
+        raise ValueError("frac must lie in [0, 1]")
+    return k[:-1] + frac * np.diff(k)
+
+
+def sigma_band(channels, tlab_mev, fracs):
+    """Lowest and highest total cross section (mb) over interpolation points.
+
+    channels: iterable of (J, delta_deg (N, K), eps_deg (N,) or None,
+    k_bounds); for every frac in fracs the bin phases are placed at
+    interpolation_points(k_bounds, frac) and sigma_tot is evaluated; returns
+    (min, max) over fracs per T_lab (Sec. 5.1.1: the bands of varying the
+    interpolation point, m = 10 and n = 0.1, 1, 2, ..., 9, 9.9 there)."""
+    chans = [(J, d, e, np.asarray(k, dtype=np.float64)) for J, d, e, k in channels]
+    sig = np.stack([sigma_tot([(J, d, e, interpolation_points(k, f), k[-1]) for J, d, e, k in chans], None,
+                              tlab_mev, None) for f in fracs])
+    return sig.min(axis=0), sig.max(axis=0)
 
 
 def channel_loss(delta_deg: np.ndarray, eps_deg, kbar: np.ndarray, p, k_max: float):

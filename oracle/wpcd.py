@@ -3,8 +3,11 @@
 Conventions (read from Sec. 2 and Sec. 3 of the paper):
 * partial-wave states <k'|k> = delta(k'-k)/(k'k); reduced units, energies are
   E = k^2 in fm^-2 and the potential U is in fm (no 2/pi in the LS kernel);
-* momentum wave packets, f(k) = 1 and N_i = dk_i (Sec. 3.1, definition of the
-  free wave packet and the normalisation stated after the eigenvalue equations);
+* momentum wave packets, f(k) = 1 and N_i = dk_i, or energy wave packets,
+  f(k) = sqrt(k/mu) and N_i = dE_i (Sec. 3.1, definition of the free wave
+  packet and the normalisation stated after its eigenvalue equations).  In
+  the reduced units used here E = k^2, i.e. hbar^2/(2 mu) = 1, so
+  f(k)^2 dk = dE: f(k) = sqrt(2k) and N_i = k_i^2 - k_{i-1}^2;
 * coupled channels use K = 2 degenerate copies of the free basis, one per
   orbital l, ordered channel-major: row (a, i) -> a*N + i (Sec. 3.1, coupled
   channels paragraph).
@@ -50,52 +53,96 @@ def gauss_nodes(k_bounds, n_gauss: int):
     return nodes.ravel(), weights.ravel()
 
 
-def h0_diagonal(k_bounds):
-    """e_i = <x_i|k^2|x_i> = (1/dk_i) int_{D_i} k^2 dk for a momentum packet.
+PACKETS = ("momentum", "energy")
+
+
+def _check_packet(packet: str):
+    if packet not in PACKETS:
+        raise WPCDError(f"packet must be one of {PACKETS}, got {packet!r}")
+
+
+def h0_diagonal(k_bounds, packet: str = "momentum"):
+    """e_i = <x_i|k^2|x_i> = (1/N_i) int_{D_i} k^2 f(k)^2 dk.
 
     The free Hamiltonian is diagonal in the packet basis because bins do not
-    overlap; the diagonal is the bin average of k^2, i.e.
-    (k_{i-1}^2 + k_{i-1} k_i + k_i^2)/3 (Sec. 3.1, free wave packets and their
-    free-Hamiltonian eigenvalue; see the reading list for the choice of <k^2>).
+    overlap (Sec. 3.1, free wave packets and their free-Hamiltonian
+    eigenvalue).  Momentum packets: the bin average of k^2 over k,
+    (k_{i-1}^2 + k_{i-1} k_i + k_i^2)/3 (see the reading list for the choice
+    of <k^2>); energy packets: the bin average of E over E, i.e. the energy
+    midpoint E_{i-1} + dE_i/2 = (k_{i-1}^2 + k_i^2)/2, the eigenvalue the
+    paper states for them.
     """
+    _check_packet(packet)
     k = np.asarray(k_bounds, dtype=np.float64)
     a, b = k[:-1], k[1:]
+    if packet == "energy":
+        return 0.5 * (a * a + b * b)
     return (a * a + a * b + b * b) / 3.0
 
 
-# ------------------------------------------------------- step 1b: projection
-def projection_matrix(k_bounds, n_gauss: int, n_ch: int) -> np.ndarray:
-    """P with V = P^T U P: P[(a,alpha),(a,i)] = w_alpha k_alpha / sqrt(dk_i).
+def packet_weight(k, packet: str = "momentum"):
+    """f(k) of the free packet definition: 1 (momentum) or sqrt(2k) (energy)."""
+    _check_packet(packet)
+    k = np.asarray(k, dtype=np.float64)
+    return np.ones_like(k) if packet == "momentum" else np.sqrt(2.0 * k)
 
-    From the double-bin-integral definition of <x_i|v|x_j> with f = 1 and
-    N_i = dk_i (Sec. 3.2, wave-packet potential matrix), evaluated with the
-    per-bin Gauss rule.
+
+def packet_norm(k_bounds, packet: str = "momentum"):
+    """N_i: dk_i (momentum packets) or dE_i = k_i^2 - k_{i-1}^2 (energy packets)."""
+    _check_packet(packet)
+    k = np.asarray(k_bounds, dtype=np.float64)
+    return np.diff(k) if packet == "momentum" else np.diff(k * k)
+
+
+def onshell_momenta(k_bounds, packet: str = "momentum"):
+    """The on-shell momentum q_k of each bin: the one whose energy is the
+    packet's free eigenvalue (Sec. 3.2, choice of q after the five steps):
+    the momentum midpoint kbar_k for momentum packets (their momentum
+    eigenvalue k_{k-1} + dk_k/2), sqrt(e_k) = sqrt((k_{k-1}^2 + k_k^2)/2) for
+    energy packets (their energy eigenvalue E_{k-1} + dE_k/2)."""
+    _check_packet(packet)
+    if packet == "momentum":
+        return bins(k_bounds)[1]
+    return np.sqrt(h0_diagonal(k_bounds, "energy"))
+
+
+# ------------------------------------------------------- step 1b: projection
+def projection_matrix(k_bounds, n_gauss: int, n_ch: int, packet: str = "momentum") -> np.ndarray:
+    """P with V = P^T U P: P[(a,alpha),(a,i)] = w_alpha k_alpha f(k_alpha) / sqrt(N_i).
+
+    From the double-bin-integral definition of <x_i|v|x_j> (Sec. 3.2,
+    wave-packet potential matrix), evaluated with the per-bin Gauss rule.
+    With one node per bin (n_gauss = 1: the midpoint kbar_i, weight dk_i) this
+    is the paper's midpoint approximation, which for momentum packets reads
+    V_ij = kbar_i kbar_j sqrt(dk_i dk_j) U(kbar_i, kbar_j).
     """
     k = np.asarray(k_bounds, dtype=np.float64)
     n = k.size - 1
     nodes, w = gauss_nodes(k, n_gauss)
-    dk = np.diff(k)
+    norm = packet_norm(k, packet)
+    f = packet_weight(nodes, packet)
     m = n * n_gauss
     p = np.zeros((n_ch * m, n_ch * n))
     for a in range(n_ch):
         for i in range(n):
+            sl = slice(i * n_gauss, (i + 1) * n_gauss)
             rows = slice(a * m + i * n_gauss, a * m + (i + 1) * n_gauss)
-            p[rows, a * n + i] = w[i * n_gauss:(i + 1) * n_gauss] * nodes[i * n_gauss:(i + 1) * n_gauss] / np.sqrt(dk[i])
+            p[rows, a * n + i] = w[sl] * nodes[sl] * f[sl] / np.sqrt(norm[i])
     return p
 
 
-def project(k_bounds, n_gauss: int, u_fine: np.ndarray, n_ch: int) -> np.ndarray:
+def project(k_bounds, n_gauss: int, u_fine: np.ndarray, n_ch: int, packet: str = "momentum") -> np.ndarray:
     """Wave-packet potential matrix V (n_ch*N square) from U at the Gauss nodes."""
-    p = projection_matrix(k_bounds, n_gauss, n_ch)
+    p = projection_matrix(k_bounds, n_gauss, n_ch, packet)
     u = np.asarray(u_fine, dtype=np.float64)
     if u.shape != (p.shape[0], p.shape[0]):
         raise WPCDError(f"u_fine must be {p.shape[0]} square, got {u.shape}")
     return p.T @ u @ p
 
 
-def hamiltonian(k_bounds, v: np.ndarray, n_ch: int) -> np.ndarray:
+def hamiltonian(k_bounds, v: np.ndarray, n_ch: int, packet: str = "momentum") -> np.ndarray:
     """H = H0 + V with H0 repeated once per coupled channel (Sec. 3.1)."""
-    e = np.tile(h0_diagonal(k_bounds), n_ch)
+    e = np.tile(h0_diagonal(k_bounds, packet), n_ch)
     return np.diag(e) + v
 
 
@@ -204,19 +251,22 @@ def tmatrix(v: np.ndarray, c: np.ndarray, gbar: np.ndarray, n_ch: int) -> np.nda
     return t
 
 
-def solve_channel(k_bounds, n_gauss: int, u_fine: np.ndarray, n_ch: int) -> dict:
-    """Steps 1-5 of the method plus S-matrix phase shifts for one channel."""
+def solve_channel(k_bounds, n_gauss: int, u_fine: np.ndarray, n_ch: int, packet: str = "momentum") -> dict:
+    """Steps 1-5 of the method plus S-matrix phase shifts for one channel.
+
+    packet selects momentum (default) or energy wave packets; "q" in the
+    result holds the on-shell momentum of every bin (onshell_momenta)."""
     from . import observables
 
-    dk, kbar, _ = bins(k_bounds)
-    v = project(k_bounds, n_gauss, u_fine, n_ch)
-    h = hamiltonian(k_bounds, v, n_ch)
+    q = onshell_momenta(k_bounds, packet)
+    v = project(k_bounds, n_gauss, u_fine, n_ch, packet)
+    h = hamiltonian(k_bounds, v, n_ch, packet)
     evals, c = diagonalise(h)
     lo, hi, bound = swp_bins(evals, n_ch, float(np.asarray(k_bounds)[-1]) ** 2)
     g = resolvent_table(k_bounds, evals, lo, hi, bound)
     t = tmatrix(v, c, g, n_ch)
-    s = observables.s_matrix(t, dk, kbar)
+    s = observables.s_matrix(t, packet_norm(k_bounds, packet), q, packet_weight(q, packet) ** 2)
     ph = observables.phase_shifts(s)
     return {"v": v, "h": h, "evals": evals, "evecs": c, "lo": lo, "hi": hi, "bound": bound,
             "gbar": g, "t": t, "s": s, "delta": ph["delta"], "mix": ph["mix"],
-            "s_dev": ph["s_dev"]}
+            "s_dev": ph["s_dev"], "q": q}
