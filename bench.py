@@ -188,7 +188,7 @@ def run_sweep(args) -> dict:
     from synth import sweep
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
                      jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
-                     refine_close_log10=args.refine_close)
+                     refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
     t0 = time.perf_counter()
     _, bases = _register_bases(ctx, sweep.TermCache(), sweep.N_WP_CHOICES, range(len(sweep.CHANNELS)))
     log(f"sweep: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
@@ -210,7 +210,7 @@ def run_large(args) -> dict:
     from synth import sweep
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
                      jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
-                     refine_close_log10=args.refine_close)
+                     refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
     coupled = [c for c in range(len(sweep.CHANNELS)) if sweep.CHANNELS[c][1] == 2]
     N = args.large_nwp
     t0 = time.perf_counter()
@@ -282,7 +282,7 @@ def run_serve(args) -> dict:
     from synth import sweep
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
                      jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
-                     refine_close_log10=args.refine_close)
+                     refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
     n_wps = (50, 100, 150, 200)
     t0 = time.perf_counter()
     _, bases = _register_bases(ctx, sweep.TermCache(), n_wps, range(len(sweep.CHANNELS)))
@@ -363,6 +363,8 @@ def main() -> int:
                     help="refinement products (wpcd_config.refine_gemm; 0: whole-item for n 193..208, 1: tiles)")
     ap.add_argument("--refine-steps", type=int, default=2, help="FP64 refinement steps (wpcd_config.refine_steps)")
     ap.add_argument("--refine-close", type=int, default=0, help="wpcd_config.refine_close_log10 (0: default)")
+    ap.add_argument("--refine-rr", type=int, default=0,
+                    help="wpcd_config.refine_rr_steps: trailing refinement steps with Rayleigh-Ritz (0: every step)")
     ap.add_argument("--jacobi-stop", type=float, default=0.0, help="FP32 Jacobi stopping threshold (wpcd_config.jacobi_stop_f32; 0: default)")
     ap.add_argument("--workload", choices=("coupled", "sweep", "large", "serve", "mi"), default="coupled",
                     help="coupled: the headline line; sweep / large / serve: the other workloads")
@@ -391,7 +393,7 @@ def main() -> int:
     torch.cuda.set_device(dev)
     ctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop,
                      jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
-                     refine_close_log10=args.refine_close)
+                     refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
     k = configs.grid("coupled_yukawa")
     g = ctx.grid(k, configs.N_GAUSS)
     B = args.batch
@@ -438,7 +440,7 @@ def main() -> int:
     # column-pair visit, per applied rotation 4n (scaled rotations, the
     # default variant: one FMA per element and column) or 6n (plain
     # rotations), 2 per norm multiply-add
-    rot_flops = 4.0 if args.jacobi_block == 0 else 6.0
+    rot_flops = 4.0 if args.jacobi_block in (0, 5, 6) else 6.0   # scaled rotations: one FMA per element and column
     jac_flops = (2.0 * n * counts["pair_visits"] + rot_flops * n * counts["rotations"]
                  + 2.0 * counts["norm_madds"])          # over all timed launches
     jac_ms, jac_launches = stages["jacobi_f32"]          # HIP events around each launch
@@ -483,7 +485,7 @@ def main() -> int:
         torch.cuda.synchronize()
         cctx = wp.Context(0, jacobi_block=args.jacobi_block, jacobi_stop_f32=args.jacobi_stop, jacobi_start=1,
                           refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
-                          refine_close_log10=args.refine_close)
+                          refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
         cg = cctx.grid(k, configs.N_GAUSS)
         cb = cctx.batch([(cg, N_CH, 1, s) for s in range(B)])
         cbufs = cb.alloc()

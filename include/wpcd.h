@@ -51,6 +51,12 @@
  *
  * Threading: one context per device; calls on one context must not run
  * concurrently from several host threads.
+ *
+ * Lifetimes: batches, matrix-inversion solvers, graphs and servers use their
+ * context in every call, so the context must outlive those calls; their
+ * destroy calls touch only their own resources and may come before or after
+ * wpcd_destroy of the context (e.g. in whatever order a garbage collector
+ * finalises the handles).
  */
 #ifndef WPCD_H
 #define WPCD_H
@@ -107,6 +113,10 @@ typedef struct {
                             lane group, three dot products per pair; 2 one pair
                             per group, tracked norms; 3 as 0 with plain
                             rotations; 4 blocks of 4 columns, tracked norms;
+                            5 blocks of 4 columns, scaled rotations, one
+                            16-lane row per block pair whose four quarters
+                            compute the four angles of a stage at once; 6
+                            the same with blocks of 2 columns (two halves);
                             other values: WPCD_ERR_INVALID                   */
   int32_t refine_close_log10; /* closeness constant of the first refinement
                             step, c = 10^k (pairs whose first-order update
@@ -138,6 +148,13 @@ typedef struct {
                             items) when every item of the batch has 193..208
                             rows, else 64 x 64 tiles; 1 always tiles.  Same
                             results up to rounding order.                    */
+  int32_t refine_rr_steps; /* refinement steps, counted from the last, that
+                            solve clusters of close eigenvalues by Rayleigh-
+                            Ritz; the earlier steps give a close pair the
+                            symmetric update R_ij/2 (the cluster's subspace
+                            is still corrected, its basis inside the cluster
+                            is left to the later Rayleigh-Ritz).  0 (default)
+                            = every step; 1..refine_steps                    */
 } wpcd_config;
 
 /* Create a context on HIP device `hip_device`; cfg may be NULL for defaults. */
@@ -154,6 +171,24 @@ const char* wpcd_version(void);
  * device the bin widths, midpoints, boundary energies, H0 diagonal, nodes and
  * weights.  Returns a grid id >= 0 in *grid_id.                              */
 int wpcd_grid_create(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_gauss, int* grid_id);
+
+/* Kind of free wave packet of a grid (Sec. 3.1, definition of the free
+ * packets and their normalisation).
+ * WPCD_PACKET_MOMENTUM: f(k) = 1, N_i = dk_i; H0 diagonal
+ *   (k_{i-1}^2 + k_{i-1} k_i + k_i^2)/3; on-shell momentum the bin midpoint
+ *   (what wpcd_grid_create registers).
+ * WPCD_PACKET_ENERGY: f(k) = sqrt(k/mu) = sqrt(2k) in these units, N_i =
+ *   dE_i = k_i^2 - k_{i-1}^2; H0 diagonal the energy midpoint
+ *   (k_{i-1}^2 + k_i^2)/2; on-shell momentum q_i = sqrt of that (Sec. 3.2,
+ *   choice of the on-shell point).
+ * The projection weights become w k f(k)/sqrt(N_i), the packet T-matrix maps
+ * to t(q,q) = f(q)^2 T_ii/(N_i q^2), and wpcd_sigma_tot interpolates between
+ * the on-shell momenta q_i; resolvent, scattering-packet bins and T are the
+ * same for both kinds.                                                      */
+enum { WPCD_PACKET_MOMENTUM = 0, WPCD_PACKET_ENERGY = 1 };
+/* wpcd_grid_create with a packet kind (WPCD_ERR_INVALID for other values). */
+int wpcd_grid_create_packets(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_gauss, int packet,
+                             int* grid_id);
 /* Copy the grid's Gauss nodes and weights (N*n_gauss each, bin-major) to host
  * memory, e.g. to evaluate a potential at exactly the nodes the library uses.  */
 int wpcd_grid_nodes(wpcd_ctx ctx, int grid_id, double* nodes_host, double* weights_host);
@@ -275,6 +310,19 @@ int wpcd_observables(wpcd_batch b, const double* t, double* delta_deg, double* m
 int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev,
                    int n_tlab, double* sigma_mb, hipStream_t stream);
 
+/* wpcd_sigma_band (Sec. 5.1.1, the spread of sigma_tot over the interpolation
+ * point of the bins): for every fraction f of `fracs` (DEVICE array of n_frac
+ * values in [0, 1], 1 <= n_frac <= 16) the phases of bin i are placed at
+ * q_i = k_{i-1} + f (k_i - k_{i-1}) and sigma_tot is evaluated as in
+ * wpcd_sigma_tot (unwrapping, linear interpolation in q, Stapp S, optical
+ * theorem); sigma_lo_mb / sigma_hi_mb (DEVICE, n_samples*n_tlab each, index
+ * s*n_tlab + j) receive the lowest and highest value over the fractions.
+ * 1 <= n_tlab <= 256; energies with p outside (0, k_N] give NaN.  The paper's
+ * band takes f = n/m with m = 10 and n = 0.1, 1, 2, ..., 9, 9.9.            */
+int wpcd_sigma_band(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev,
+                    int n_tlab, const double* fracs, int n_frac, double* sigma_lo_mb, double* sigma_hi_mb,
+                    hipStream_t stream);
+
 /* ------------------------------------------------------ matrix inversion ----
  * The paper's comparison method (Sec. 2.1, the wave-matrix form of the
  * discretised LS equation and its K-matrix variant; Sec. 4.1, one LU
@@ -342,6 +390,70 @@ int wpcd_mi_solve(wpcd_mi m, const double* u, double* kmat, double* delta_deg, d
  * the total cross section of wpcd_sigma_tot.                              */
 int wpcd_saclay(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev, int n_tlab,
                 const double* theta_deg, int n_theta, double* amp, double* dsdo_mb, hipStream_t stream);
+
+/* ------------------------------------------------------------ whole path --
+ * wpcd_run: the whole path of a batch on one stream, in the order of the
+ * method (Sec. 3.2, steps 1-5; App. A): wpcd_project for fine-mesh items
+ * (u_fine, u_dtype), wpcd_project_affine for basis items (coef), wpcd_eigh,
+ * wpcd_tmatrix, wpcd_observables and, when n_tlab > 0, wpcd_sigma_tot.
+ * Arguments and errors as for those calls (the first failing call's status
+ * is returned; later steps are not enqueued).  u_fine may be NULL for a batch
+ * without fine-mesh items, coef for one without basis items, s_dev always. */
+typedef struct {
+  const void* u_fine;
+  int32_t u_dtype;
+  int32_t n_tlab;
+  const double* coef;
+  double* v64;
+  double* eval;
+  double* evec;
+  int32_t* eig_status;
+  double* t;
+  int32_t* t_status;
+  double* delta_deg;
+  double* mix_deg;
+  double* s_dev;
+  const double* tlab_mev;
+  double* sigma_mb;
+} wpcd_path_args;
+int wpcd_run(wpcd_batch b, const wpcd_path_args* a, int mode, hipStream_t stream);
+
+/* Autotuner of the batch path's schedules: runs wpcd_run(b, a, mode) once
+ * per candidate schedule as a warm-up, then `reps` times under HIP events on
+ * a private stream, and keeps the fastest in the context's configuration
+ * (jacobi_block, refine_gemm; later calls on the context use it).  The
+ * candidates (WPCD_MIXED) are the LDS Jacobi with two-column blocks
+ * (jacobi_block 0) or four-column blocks and one angle per quarter row (5),
+ * each with whole-item or tiled refinement products (refine_gemm 0 / 1);
+ * WPCD_F64 has a single schedule.  All candidates give the same results up to
+ * rounding order.  cache_path (may be NULL): a text file with one line per
+ * tuned batch signature (mode and, per eigensolver size class, item count and
+ * largest n); a matching line is applied without timing (from_cache = 1), a
+ * new result is appended.  The outputs of `a` hold the last candidate's run.
+ * The stage timers must be off.                                             */
+typedef struct {
+  int32_t jacobi_block, refine_gemm; /* the chosen schedule                    */
+  int32_t from_cache, n_cand;        /* taken from the cache; candidates timed */
+  double best_ms;                    /* its time per run                       */
+  double cand_ms[4];                 /* per candidate: {0,0}, {5,0}, {0,1}, {5,1} */
+} wpcd_tune_result;
+int wpcd_autotune(wpcd_batch b, const wpcd_path_args* a, int mode, int reps, const char* cache_path,
+                  wpcd_tune_result* out);
+
+/* HIP graph of a batch's whole path: wpcd_graph_create captures the launches
+ * of wpcd_run(b, a, mode) (including the second stream of wpcd_eigh) into a
+ * graph and instantiates it; wpcd_graph_launch replays it on `stream` (the
+ * same kernels on the same buffers: change the inputs in place between
+ * replays).  Capturing enqueues no work.  The capture holds no memset node
+ * and allocates nothing.  The stage timers must be off (WPCD_ERR_INVALID
+ * otherwise: they cannot time replays).  The batch and every buffer of `a`
+ * must outlive the graph.  wpcd_graph_nodes returns the number of nodes
+ * (kernel launches and stream joins) one replay runs.                      */
+typedef struct wpcd_graph_s* wpcd_graph;
+int wpcd_graph_create(wpcd_batch b, const wpcd_path_args* a, int mode, wpcd_graph* out);
+int wpcd_graph_launch(wpcd_graph g, hipStream_t stream);
+int wpcd_graph_nodes(wpcd_graph g, int64_t* nodes);
+void wpcd_graph_destroy(wpcd_graph g);
 
 /* ---------------------------------------------------------------- serving --
  * A request loop over one context (the paper's posterior-sweep use case, Sec. 1

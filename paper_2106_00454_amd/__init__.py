@@ -31,9 +31,13 @@ MIXED = 0
 F64 = 1
 DTYPE_F32 = 0
 DTYPE_F64 = 1
+PACKET_MOMENTUM = 0
+PACKET_ENERGY = 1
 
 #: every symbol declared in include/wpcd.h
 EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wpcd_grid_create",
+           "wpcd_grid_create_packets", "wpcd_sigma_band", "wpcd_run", "wpcd_graph_create", "wpcd_graph_launch",
+           "wpcd_graph_nodes", "wpcd_graph_destroy", "wpcd_autotune",
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
            "wpcd_batch_offsets", "wpcd_basis_register", "wpcd_project", "wpcd_project_affine", "wpcd_eigh",
            "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_saclay", "wpcd_server_create", "wpcd_server_destroy",
@@ -55,7 +59,7 @@ class _Config(ctypes.Structure):
                 ("jacobi_tol_f32", ctypes.c_double), ("jacobi_tol_f64", ctypes.c_double),
                 ("jacobi_block", ctypes.c_int32), ("refine_close_log10", ctypes.c_int32),
                 ("jacobi_stop_f32", ctypes.c_double), ("jacobi_start", ctypes.c_int32),
-                ("refine_gemm", ctypes.c_int32)]
+                ("refine_gemm", ctypes.c_int32), ("refine_rr_steps", ctypes.c_int32)]
 
 
 class _Item(ctypes.Structure):
@@ -97,6 +101,19 @@ class _Request(ctypes.Structure):
                 ("delta_host", ctypes.c_void_p), ("mix_host", ctypes.c_void_p), ("status_host", ctypes.c_void_p)]
 
 
+class _PathArgs(ctypes.Structure):
+    _fields_ = [("u_fine", ctypes.c_void_p), ("u_dtype", ctypes.c_int32), ("n_tlab", ctypes.c_int32),
+                ("coef", ctypes.c_void_p), ("v64", ctypes.c_void_p), ("eval", ctypes.c_void_p),
+                ("evec", ctypes.c_void_p), ("eig_status", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("t_status", ctypes.c_void_p), ("delta_deg", ctypes.c_void_p), ("mix_deg", ctypes.c_void_p),
+                ("s_dev", ctypes.c_void_p), ("tlab_mev", ctypes.c_void_p), ("sigma_mb", ctypes.c_void_p)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("jacobi_block", ctypes.c_int32), ("refine_gemm", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("n_cand", ctypes.c_int32), ("best_ms", ctypes.c_double), ("cand_ms", ctypes.c_double * 4)]
+
+
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("items", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_int64), ("queued", ctypes.c_int32),
@@ -126,6 +143,15 @@ def lib() -> ctypes.CDLL:
         "wpcd_last_error": (ctypes.c_char_p, []),
         "wpcd_version": (ctypes.c_char_p, []),
         "wpcd_grid_create": (i32, [vp, ctypes.POINTER(ctypes.c_double), i32, i32, ctypes.POINTER(i32)]),
+        "wpcd_grid_create_packets": (i32, [vp, ctypes.POINTER(ctypes.c_double), i32, i32, i32, ctypes.POINTER(i32)]),
+        "wpcd_sigma_band": (i32, [vp, dp, dp, dp, i32, dp, i32, dp, dp, vp]),
+        "wpcd_run": (i32, [vp, ctypes.POINTER(_PathArgs), i32, vp]),
+        "wpcd_graph_create": (i32, [vp, ctypes.POINTER(_PathArgs), i32, ctypes.POINTER(vp)]),
+        "wpcd_graph_launch": (i32, [vp, vp]),
+        "wpcd_graph_nodes": (i32, [vp, ctypes.POINTER(i64)]),
+        "wpcd_graph_destroy": (None, [vp]),
+        "wpcd_autotune": (i32, [vp, ctypes.POINTER(_PathArgs), i32, i32, ctypes.c_char_p,
+                                ctypes.POINTER(_TuneResult)]),
         "wpcd_grid_nodes": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "wpcd_batch_create": (i32, [vp, ctypes.POINTER(_Item), i32, ctypes.POINTER(vp)]),
         "wpcd_batch_destroy": (None, [vp]),
@@ -208,10 +234,10 @@ class Context:
     def __init__(self, device: int = 0, max_sweeps: int = 30, refine_steps: int = 2,
                  jacobi_tol_f32: float = 2e-7, jacobi_tol_f64: float = 1e-15, jacobi_block: int = 0,
                  refine_close_log10: int = 0, jacobi_stop_f32: float = 0.0, jacobi_start: int = 0,
-                 refine_gemm: int = 0):
+                 refine_gemm: int = 0, refine_rr_steps: int = 0):
         L = lib()
         cfg = _Config(max_sweeps, refine_steps, jacobi_tol_f32, jacobi_tol_f64, jacobi_block, refine_close_log10,
-                      jacobi_stop_f32, jacobi_start, refine_gemm)
+                      jacobi_stop_f32, jacobi_start, refine_gemm, refine_rr_steps)
         h = ctypes.c_void_p()
         _check(L.wpcd_create(ctypes.byref(h), device, ctypes.byref(cfg)))
         self._h = h
@@ -228,11 +254,12 @@ class Context:
         except Exception:
             pass
 
-    def grid(self, k_bounds, n_gauss: int = 8) -> Grid:
+    def grid(self, k_bounds, n_gauss: int = 8, packet: int = PACKET_MOMENTUM) -> Grid:
+        """Register a bin grid of momentum (default) or energy wave packets."""
         k = np.ascontiguousarray(k_bounds, dtype=np.float64)
         gid = ctypes.c_int()
-        _check(lib().wpcd_grid_create(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k.size - 1,
-                                      n_gauss, ctypes.byref(gid)))
+        _check(lib().wpcd_grid_create_packets(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              k.size - 1, n_gauss, packet, ctypes.byref(gid)))
         m = (k.size - 1) * n_gauss
         nodes, weights = np.empty(m), np.empty(m)
         _check(lib().wpcd_grid_nodes(self._h, gid.value, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -347,6 +374,51 @@ class Batch:
             "t_status": torch.empty(L["n_items"], dtype=torch.int32, device=device),
         }
 
+    def path_args(self, u, bufs, tlab=None, sigma=None, coef=None):
+        """wpcd_path_args over the buffers of alloc() (u, coef: device tensors or None)."""
+        import torch
+        L = self.layout
+        a = _PathArgs()
+        if u is not None:
+            a.u_fine = _ptr(u, u.dtype, L["u_elems"], "u").value
+            a.u_dtype = DTYPE_F32 if u.dtype == torch.float32 else DTYPE_F64
+        if coef is not None:
+            a.coef = _ptr(coef, torch.float64, L["coef_elems"], "coef").value
+        for f, k, dt, n in (("v64", "v64", torch.float64, L["v_elems"]), ("eval", "eval", torch.float64, L["eval_elems"]),
+                            ("evec", "evec", torch.float64, L["v_elems"]),
+                            ("eig_status", "eig_status", torch.int32, L["n_items"]),
+                            ("t", "t", torch.float64, L["t_doubles"]), ("t_status", "t_status", torch.int32, L["n_items"]),
+                            ("delta_deg", "delta", torch.float64, L["delta_elems"]),
+                            ("mix_deg", "mix", torch.float64, L["mix_elems"]),
+                            ("s_dev", "s_dev", torch.float64, L["delta_elems"])):
+            setattr(a, f, _ptr(bufs[k], dt, n, k).value)
+        if tlab is not None:
+            a.n_tlab = tlab.numel()
+            a.tlab_mev = _ptr(tlab, torch.float64, a.n_tlab, "tlab").value
+            a.sigma_mb = _ptr(sigma, torch.float64, L["n_samples"] * a.n_tlab, "sigma").value
+        return a
+
+    def run_path(self, u, bufs, mode, tlab=None, sigma=None, stream=None, coef=None):
+        """The whole path in one library call (wpcd_run)."""
+        a = self.path_args(u, bufs, tlab, sigma, coef)
+        _check(lib().wpcd_run(self._h, ctypes.byref(a), mode, _stream(stream)))
+
+    def graph(self, u, bufs, mode, tlab=None, sigma=None, coef=None) -> "Graph":
+        """A HIP graph of the whole path on these buffers (wpcd_graph_create)."""
+        a = self.path_args(u, bufs, tlab, sigma, coef)
+        h = ctypes.c_void_p()
+        _check(lib().wpcd_graph_create(self._h, ctypes.byref(a), mode, ctypes.byref(h)))
+        return Graph(h, self)
+
+    def autotune(self, u, bufs, mode, tlab=None, sigma=None, coef=None, reps=2, cache_path=None) -> dict:
+        """wpcd_autotune: time the candidate schedules on this batch, keep the fastest in the context."""
+        a = self.path_args(u, bufs, tlab, sigma, coef)
+        r = _TuneResult()
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().wpcd_autotune(self._h, ctypes.byref(a), mode, reps, cp, ctypes.byref(r)))
+        return {"jacobi_block": r.jacobi_block, "refine_gemm": r.refine_gemm, "from_cache": bool(r.from_cache),
+                "best_ms": r.best_ms, "cand_ms": list(r.cand_ms)[:r.n_cand]}
+
     # ------------------------------------------------------------ steps
     def project(self, u, v64, stream=None):
         import torch
@@ -365,9 +437,9 @@ class Batch:
         import torch
         L = self.layout
         _check(lib().wpcd_eigh(self._h, _ptr(v64, torch.float64, L["v_elems"], "v64"), mode,
-                               _ptr(eval_, torch.float64, L["eval_elems"], "eval"),
-                               _ptr(evec, torch.float64, L["v_elems"], "evec"),
-                               _ptr(status, torch.int32, L["n_items"], "status"), _stream(stream)))
+                 _ptr(eval_, torch.float64, L["eval_elems"], "eval"),
+                 _ptr(evec, torch.float64, L["v_elems"], "evec"),
+                 _ptr(status, torch.int32, L["n_items"], "status"), _stream(stream)))
 
     def tmatrix(self, v64, eval_, evec, mode, t, status, stream=None):
         import torch
@@ -396,6 +468,19 @@ class Batch:
                                     _ptr(sigma, torch.float64, L["n_samples"] * n_tlab, "sigma"),
                                     _stream(stream)))
 
+    def sigma_band(self, delta, mix, tlab, fracs, sigma_lo, sigma_hi, stream=None):
+        """wpcd_sigma_band: lowest and highest sigma_tot over interpolation points."""
+        import torch
+        L = self.layout
+        n_tlab, n_frac = tlab.numel(), fracs.numel()
+        _check(lib().wpcd_sigma_band(self._h, _ptr(delta, torch.float64, L["delta_elems"], "delta"),
+                                     _ptr(mix, torch.float64, L["mix_elems"], "mix"),
+                                     _ptr(tlab, torch.float64, n_tlab, "tlab"), n_tlab,
+                                     _ptr(fracs, torch.float64, n_frac, "fracs"), n_frac,
+                                     _ptr(sigma_lo, torch.float64, L["n_samples"] * n_tlab, "sigma_lo"),
+                                     _ptr(sigma_hi, torch.float64, L["n_samples"] * n_tlab, "sigma_hi"),
+                                     _stream(stream)))
+
     def saclay(self, delta, mix, tlab, theta_deg, amp, dsdo, stream=None):
         """wpcd_saclay: Saclay amplitudes (amp: 10 doubles per sample, energy and
         angle, or None) and dsigma/dOmega (mb/sr) at the T_lab values and c.m.
@@ -422,6 +507,30 @@ class Batch:
         self.observables(bufs["t"], bufs["delta"], bufs["mix"], bufs["s_dev"], stream)
         if tlab is not None:
             self.sigma_tot(bufs["delta"], bufs["mix"], tlab, sigma, stream)
+
+
+class Graph:
+    """Instantiated HIP graph of a batch's whole path (keeps the batch alive)."""
+
+    def __init__(self, h, batch):
+        self._h, self.batch = h, batch
+        n = ctypes.c_int64()
+        _check(lib().wpcd_graph_nodes(h, ctypes.byref(n)))
+        self.nodes = n.value
+
+    def launch(self, stream=None):
+        _check(lib().wpcd_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().wpcd_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- matrix inversion

@@ -130,6 +130,7 @@ namespace wpcd {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace wpcd
 
+
 extern "C" {
 
 const char* wpcd_last_error(void) { return g_err.c_str(); }
@@ -142,7 +143,7 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   WPCD_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
   if (hip_device < 0 || hip_device >= ndev)
     return fail(WPCD_ERR_INVALID, "wpcd_create: device %d out of range (%d devices)", hip_device, ndev);
-  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0, 0.0, 0, 0};
+  wpcd_config c{30, 2, 2e-7, 1e-15, 0, 0, 0.0, 0, 0, 0};
   if (cfg) c = *cfg;
   if (c.refine_close_log10 == 0) c.refine_close_log10 = 3;
   // default stop 1e-4: rotations up to that size left in the FP32 vectors are
@@ -158,10 +159,12 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
     return fail(WPCD_ERR_INVALID, "jacobi_stop_f32 must be in (0, 1) (0 = default)");
   if (c.jacobi_start != 0 && c.jacobi_start != 1) return fail(WPCD_ERR_INVALID, "jacobi_start must be 0 or 1");
   if (c.refine_gemm != 0 && c.refine_gemm != 1) return fail(WPCD_ERR_INVALID, "refine_gemm must be 0 or 1");
-  if (c.jacobi_block < 0 || c.jacobi_block > 4)
-    return fail(WPCD_ERR_INVALID, "jacobi_block must be 0, 1, 2, 3 or 4");
+  if (c.jacobi_block < 0 || c.jacobi_block > 6)
+    return fail(WPCD_ERR_INVALID, "jacobi_block must be in [0, 6]");
   if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
     return fail(WPCD_ERR_INVALID, "refine_close_log10 must be in [1, 8] (0 = default)");
+  if (c.refine_rr_steps < 0 || c.refine_rr_steps > 4)
+    return fail(WPCD_ERR_INVALID, "refine_rr_steps must be in [0, 4] (0 = every step)");
   WPCD_HIP(hipSetDevice(hip_device), "hipSetDevice");
   wpcd_context* ctx = new (std::nothrow) wpcd_context;
   if (!ctx) return fail(WPCD_ERR_NOMEM, "wpcd_create: host allocation");
@@ -198,7 +201,14 @@ void wpcd_destroy(wpcd_ctx ctx) {
 }
 
 int wpcd_grid_create(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_gauss, int* grid_id) {
+  return wpcd_grid_create_packets(ctx, k_bounds_host, n_wp, n_gauss, WPCD_PACKET_MOMENTUM, grid_id);
+}
+
+int wpcd_grid_create_packets(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_gauss, int packet,
+                             int* grid_id) {
   if (!ctx || !k_bounds_host || !grid_id) return fail(WPCD_ERR_INVALID, "wpcd_grid_create: NULL argument");
+  if (packet != WPCD_PACKET_MOMENTUM && packet != WPCD_PACKET_ENERGY)
+    return fail(WPCD_ERR_INVALID, "wpcd_grid_create: unknown packet kind %d", packet);
   if (n_wp < 2 || n_wp > kMaxN) return fail(WPCD_ERR_INVALID, "n_wp must be in [2, %d]", kMaxN);
   if (n_gauss < 1 || n_gauss > 16) return fail(WPCD_ERR_INVALID, "n_gauss must be in [1, 16]");
   if (k_bounds_host[0] != 0.0) return fail(WPCD_ERR_INVALID, "k_bounds[0] must be 0");
@@ -213,22 +223,40 @@ int wpcd_grid_create(wpcd_ctx ctx, const double* k_bounds_host, int n_wp, int n_
   std::vector<double> x, w;
   gauss_legendre(n_gauss, x, w);
   const int N = n_wp, ng = n_gauss;
+  // Free packets (Sec. 3.1): momentum packets f(k) = 1, N_i = dk_i; energy
+  // packets f(k) = sqrt(k/mu), N_i = dE_i, which in these units (E = k^2,
+  // 2 mu = 1) is f(k) = sqrt(2k), N_i = k_i^2 - k_{i-1}^2.  Per bin the grid
+  // keeps H0's diagonal <x_i|k^2|x_i> (momentum: (a^2 + ab + b^2)/3; energy:
+  // the energy midpoint (a^2 + b^2)/2, the eigenvalue the paper gives), the
+  // on-shell momentum q_i whose energy is the packet's free eigenvalue
+  // (momentum: the midpoint; energy: sqrt of the energy midpoint), the
+  // projection weights w k f(k) and 1/sqrt(N_i), and N_i/f(q_i)^2, the factor
+  // of t(q,q) = f(q)^2 T_ii/(N_i q^2).
+  const bool energy = packet == WPCD_PACKET_ENERGY;
   std::vector<double> eb(N + 1), dk(N), kbar(N), e0(N), wk((size_t)N * ng), rsdk(N);
   g.nodes.resize((size_t)N * ng);
   g.weights.resize((size_t)N * ng);
   for (int j = 0; j <= N; ++j) eb[j] = g.kb[j] * g.kb[j];
   for (int i = 0; i < N; ++i) {
     const double a = g.kb[i], b = g.kb[i + 1];
-    dk[i] = b - a;
-    kbar[i] = 0.5 * (a + b);
-    e0[i] = (a * a + a * b + b * b) / 3.0;  // bin average of k^2
-    rsdk[i] = 1.0 / sqrt(dk[i]);
+    if (energy) {
+      const double dE = b * b - a * a;
+      e0[i] = 0.5 * (a * a + b * b);
+      kbar[i] = sqrt(e0[i]);
+      dk[i] = dE / (2.0 * kbar[i]);
+      rsdk[i] = 1.0 / sqrt(dE);
+    } else {
+      dk[i] = b - a;
+      kbar[i] = 0.5 * (a + b);
+      e0[i] = (a * a + a * b + b * b) / 3.0;  // bin average of k^2
+      rsdk[i] = 1.0 / sqrt(dk[i]);
+    }
     for (int q = 0; q < ng; ++q) {
       const double node = 0.5 * (b - a) * x[q] + 0.5 * (b + a);
       const double wt = 0.5 * (b - a) * w[q];
       g.nodes[(size_t)i * ng + q] = node;
       g.weights[(size_t)i * ng + q] = wt;
-      wk[(size_t)i * ng + q] = wt * node;
+      wk[(size_t)i * ng + q] = energy ? wt * node * sqrt(2.0 * node) : wt * node;
     }
   }
   const size_t total = (size_t)(N + 1) * 2 + (size_t)N * 4 + (size_t)N * ng;
@@ -266,7 +294,7 @@ int wpcd_grid_nodes(wpcd_ctx ctx, int grid_id, double* nodes_host, double* weigh
 
 void wpcd_batch_destroy(wpcd_batch b) {
   if (!b) return;
-  hipSetDevice(b->ctx->device);
+  hipSetDevice(b->device);
   hipFree(b->d_items);
   hipFree(b->d_grids);
   hipFree(b->d_sample_ptr);
@@ -293,6 +321,7 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
   wpcd_batch_s* b = new (std::nothrow) wpcd_batch_s;
   if (!b) return fail(WPCD_ERR_NOMEM, "wpcd_batch_create: host allocation");
   b->ctx = ctx;
+  b->device = ctx->device;
   b->n_items = n_items;
   b->h_items.resize(n_items);
   int max_sample = -1;
@@ -633,72 +662,103 @@ int wpcd_basis_register(wpcd_ctx ctx, int grid_id, int n_ch, int n_terms, const 
   bh.n_terms = n_terms;
   ItemDev* d_it = nullptr;
   GridDev* d_g = nullptr;
+  const char* what = "wpcd_basis_register: allocation";
   hipError_t e = hipMalloc((void**)&bh.dbuf, sizeof(double) * n_terms * (size_t)n * n);
   if (e == hipSuccess) e = hipMalloc((void**)&d_it, sizeof(ItemDev) * n_terms);
   if (e == hipSuccess) e = hipMalloc((void**)&d_g, sizeof(GridDev));
-  if (e == hipSuccess) e = hipMemcpy(d_it, it.data(), sizeof(ItemDev) * n_terms, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    what = "wpcd_basis_register: upload";
+    e = hipMemcpy(d_it, it.data(), sizeof(ItemDev) * n_terms, hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemcpy(d_g, &g.dev, sizeof(GridDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_project(d_it, n_terms, n, d_g, u_terms, u_dtype, bh.dbuf, true, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess) {
+    what = "wpcd_basis_register: projection launch";
+    e = launch_project(d_it, n_terms, n, d_g, u_terms, u_dtype, bh.dbuf, true, stream);
+  }
+  if (e == hipSuccess) {
+    what = "wpcd_basis_register: projection";
+    e = hipStreamSynchronize(stream);
+  }
   hipFree(d_it);
   hipFree(d_g);
   if (e != hipSuccess) {
     hipFree(bh.dbuf);
-    return hip_fail(e, "wpcd_basis_register");
+    return hip_fail(e, what);
   }
   ctx->bases.push_back(bh);
   *basis_id = (int)ctx->bases.size() - 1;
   return WPCD_OK;
 }
 
-int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
-              hipStream_t stream) {
-  if (!b || !v64 || !eval || !evec || !status) return fail(WPCD_ERR_INVALID, "wpcd_eigh: NULL argument");
-  if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_eigh: unknown mode %d", mode);
-  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
-  WPCD_STICKY(b->ctx);
+// The second stream of the batch path and its fork/join events, created on
+// first use (the request loop never needs them, and every stream takes a
+// share of the hardware queues its own streams use).  All three or none: a
+// partial set would pass null events to later calls.
+static int ensure_side(wpcd_ctx ctx) {
+  if (ctx->side != nullptr) return WPCD_OK;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (join) hipEventDestroy(join);
+    if (fork) hipEventDestroy(fork);
+    if (side) hipStreamDestroy(side);
+    return dev_fail(ctx, e, "wpcd_eigh: second stream and its events");
+  }
+  ctx->side = side;
+  ctx->fork = fork;
+  ctx->join = join;
+  return WPCD_OK;
+}
+
+// Eigensolver work-space of one call: FP32 eigenvectors (v_elems floats), the
+// per-item FP64 work-space (work_doubles), cluster lists and Rayleigh
+// quotients (eval_elems each) and the warm-start samples (kWarmSig floats per
+// item, when the batch has pick tasks).
+struct EighBufs {
+  float* x32;
+  double* work;
+  int32_t* cl;
+  double* lam;
+  float* sig;
+};
+
+// wpcd_eigh after its argument checks.  concurrent: the batch path proper
+// (second stream for the reference choice and part of the refinement, stage
+// timers); otherwise every launch goes to `stream` and nothing is timed, so
+// the call creates no stream, event or allocation.
+static int eigh_run(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
+                    hipStream_t stream, const EighBufs& w, bool concurrent) {
   const wpcd_config& c = b->ctx->cfg;
+  auto stage = [&](int st, auto launch) -> hipError_t {
+    return concurrent ? timed(b->ctx, st, stream, launch) : launch();
+  };
   if (mode == WPCD_MIXED) {
-    if (c.refine_steps < 1)
-      return fail(WPCD_ERR_UNSUPPORTED, "wpcd_eigh: WPCD_MIXED needs refine_steps >= 1");
-    // the second stream of the batch path, created on first use (the request
-    // loop never needs it, and every stream takes a share of the hardware
-    // queues its own streams use)
-    if (b->ctx->side == nullptr) {
-      // all three or none: a partial set would pass null events to later calls
-      hipStream_t side = nullptr;
-      hipEvent_t fork = nullptr, join = nullptr;
-      hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
-      if (e != hipSuccess) {
-        if (join) hipEventDestroy(join);
-        if (fork) hipEventDestroy(fork);
-        if (side) hipStreamDestroy(side);
-        return dev_fail(b->ctx, e, "wpcd_eigh: second stream and its events");
-      }
-      b->ctx->side = side;
-      b->ctx->fork = fork;
-      b->ctx->join = join;
+    if (concurrent) {
+      const int rc = ensure_side(b->ctx);
+      if (rc != WPCD_OK) return rc;
     }
+    hipStream_t side = concurrent ? b->ctx->side : nullptr;
     // one FP32 Jacobi launch per size class: LDS-resident up to n = kMaxLdsN,
     // device memory above
     {
       constexpr int L = wpcd_batch_s::kC;
-      unsigned long long* cnt = b->ctx->profiling ? b->ctx->d_counters : nullptr;
+      unsigned long long* cnt = (concurrent && b->ctx->profiling) ? b->ctx->d_counters : nullptr;
       // one timed group per launch of the LDS kernel (per launch sequence of
       // the device-memory Jacobi)
       auto solve = [&](int seg, int k, const int32_t* ref) -> hipError_t {
         const int n_sel = b->jl_ptr[seg + 1] - b->jl_ptr[seg];
         if (n_sel == 0) return hipSuccess;
         const int32_t* sel = b->d_jlist + b->jl_ptr[seg];
-        return timed(b->ctx, WPCD_STAGE_JACOBI_F32, stream, [&] {
+        return stage(WPCD_STAGE_JACOBI_F32, [&] {
           if (k < L - 1)
-            return launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, b->d_x32, eval,
+            return launch_jacobi_f32_lds(b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, w.x32, eval,
                                          status, c.max_sweeps, (float)c.jacobi_tol_f32, (float)c.jacobi_stop_f32,
-                                         c.jacobi_block, ref, b->d_work, cnt, stream);
-          return launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, b->d_work, evec,
-                                      b->d_x32, eval, status, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32, ref,
+                                         c.jacobi_block, ref, w.work, cnt, stream);
+          return launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, w.work, evec,
+                                      w.x32, eval, status, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32, ref,
                                       stream);
         });
       };
@@ -706,51 +766,71 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
       // from the references' eigenvectors; the choice of references (V only)
       // runs on the side stream beside the cold Jacobi
       const int n_warm = b->jl_ptr[2 * L] - b->jl_ptr[L];
-      const bool side_pick = n_warm > 0 && b->n_pick > 0;
+      const bool side_pick = side != nullptr && n_warm > 0 && b->n_pick > 0;
       if (side_pick) {
         WPCD_HIPX(b->ctx, hipEventRecord(b->ctx->fork, stream), "wpcd_eigh: fork");
-        WPCD_HIPX(b->ctx, hipStreamWaitEvent(b->ctx->side, b->ctx->fork, 0), "wpcd_eigh: fork");
-        WPCD_HIPX(b->ctx, launch_warm_pick(b->d_items, b->n_items, b->d_jlist, b->d_pick, b->n_pick, b->d_cand, b->d_sig, v64,
-                                  b->d_ref, b->ctx->side),
-                 "wpcd_eigh: reference choice launch");
-        WPCD_HIPX(b->ctx, hipEventRecord(b->ctx->join, b->ctx->side), "wpcd_eigh: join");
+        WPCD_HIPX(b->ctx, hipStreamWaitEvent(side, b->ctx->fork, 0), "wpcd_eigh: fork");
+        WPCD_HIPX(b->ctx, launch_warm_pick(b->d_items, b->n_items, b->d_jlist, b->d_pick, b->n_pick, b->d_cand, w.sig,
+                                           v64, b->d_ref, side),
+                  "wpcd_eigh: reference choice launch");
+        WPCD_HIPX(b->ctx, hipEventRecord(b->ctx->join, side), "wpcd_eigh: join");
       }
       for (int k = 0; k < L; ++k) WPCD_HIPX(b->ctx, solve(k, k, nullptr), "wpcd_eigh: FP32 Jacobi launch");
       if (side_pick) WPCD_HIPX(b->ctx, hipStreamWaitEvent(stream, b->ctx->join, 0), "wpcd_eigh: join");
       if (n_warm > 0) {
-        WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_WARM_PREP, stream,
-                       [&] {
-                         return launch_jacobi_warm_prep(b->d_items, b->n_items, b->d_jlist + b->jl_ptr[2 * L],
-                                                        b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L],
-                                                        b->d_jlist + b->jl_ptr[L], n_warm, b->d_ref,
-                                                        b->warm_min_n, b->warm_max_n, b->d_jlist, b->d_pick,
-                                                        side_pick ? 0 : b->n_pick, b->d_cand, b->d_sig, b->d_grids,
-                                                        v64, b->d_x32, b->d_work, stream);
-                       }),
-                 "wpcd_eigh: warm-start preparation launch");
+        WPCD_HIPX(b->ctx, stage(WPCD_STAGE_WARM_PREP,
+                                [&] {
+                                  return launch_jacobi_warm_prep(
+                                      b->d_items, b->n_items, b->d_jlist + b->jl_ptr[2 * L],
+                                      b->jl_ptr[2 * L + 1] - b->jl_ptr[2 * L], b->d_jlist + b->jl_ptr[L], n_warm,
+                                      b->d_ref, b->warm_min_n, b->warm_max_n, b->d_jlist, b->d_pick,
+                                      side_pick ? 0 : b->n_pick, b->d_cand, w.sig, b->d_grids, v64, w.x32, w.work,
+                                      stream);
+                                }),
+                  "wpcd_eigh: warm-start preparation launch");
       }
       for (int k = 0; k < L; ++k) WPCD_HIPX(b->ctx, solve(L + k, k, b->d_ref), "wpcd_eigh: FP32 Jacobi launch");
     }
-    WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_REFINE, stream,
-                   [&] {
-                     return launch_refine(b->d_items, b->n_items, b->min_n, b->max_n, b->d_grids, v64, b->d_x32,
-                                          evec, eval,
-                                          b->d_lam, b->d_work, b->d_cl, status, c.refine_steps,
-                                          c.refine_close_log10, c.refine_gemm, stream, b->ctx->side,
-                                          b->ctx->fork, b->ctx->join);
-                   }),
-             "wpcd_eigh: FP64 refinement launch");
+    WPCD_HIPX(b->ctx, stage(WPCD_STAGE_REFINE,
+                            [&] {
+                              return launch_refine(b->d_items, b->n_items, b->min_n, b->max_n, b->d_grids, v64, w.x32,
+                                                   evec, eval, w.lam, w.work, w.cl, status, c.refine_steps,
+                                                   c.refine_close_log10, c.refine_gemm, c.refine_rr_steps, stream, side,
+                                                   b->ctx->fork, b->ctx->join);
+                            }),
+              "wpcd_eigh: FP64 refinement launch");
   } else {
-    WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_JACOBI_F64, stream,
-                   [&] {
-                     return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids, v64,
-                                                 b->d_work, evec, b->d_x32, eval, status, c.max_sweeps,
-                                                 c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, nullptr, stream);
-                   }),
-             "wpcd_eigh: FP64 Jacobi launch");
+    WPCD_HIPX(b->ctx, stage(WPCD_STAGE_JACOBI_F64,
+                            [&] {
+                              return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids,
+                                                          v64, w.work, evec, w.x32, eval, status, c.max_sweeps,
+                                                          c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, nullptr, stream);
+                            }),
+              "wpcd_eigh: FP64 Jacobi launch");
   }
   return WPCD_OK;
 }
+
+// Argument checks of wpcd_eigh.
+static int eigh_check(wpcd_batch b, const double* v64, int mode, const double* eval, const double* evec,
+                      const int32_t* status, const char* who) {
+  if (!b || !v64 || !eval || !evec || !status) return fail(WPCD_ERR_INVALID, "%s: NULL argument", who);
+  if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "%s: unknown mode %d", who, mode);
+  if (mode == WPCD_MIXED && b->ctx->cfg.refine_steps < 1)
+    return fail(WPCD_ERR_UNSUPPORTED, "%s: WPCD_MIXED needs refine_steps >= 1", who);
+  return WPCD_OK;
+}
+
+int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
+              hipStream_t stream) {
+  const int rc = eigh_check(b, v64, mode, eval, evec, status, "wpcd_eigh");
+  if (rc != WPCD_OK) return rc;
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  return eigh_run(b, v64, mode, eval, evec, status, stream, EighBufs{b->d_x32, b->d_work, b->d_cl, b->d_lam, b->d_sig},
+                  true);
+}
+
 
 int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const double* evec, int mode, double* t,
                  int32_t* status, hipStream_t stream) {
@@ -821,10 +901,29 @@ int wpcd_sigma_tot(wpcd_batch b, const double* delta_deg, const double* mix_deg,
   return WPCD_OK;
 }
 
+int wpcd_sigma_band(wpcd_batch b, const double* delta_deg, const double* mix_deg, const double* tlab_mev, int n_tlab,
+                    const double* fracs, int n_frac, double* sigma_lo_mb, double* sigma_hi_mb, hipStream_t stream) {
+  if (!b || !delta_deg || !mix_deg || !tlab_mev || !fracs || !sigma_lo_mb || !sigma_hi_mb)
+    return fail(WPCD_ERR_INVALID, "wpcd_sigma_band: NULL argument");
+  if (n_tlab < 1 || n_tlab > 256) return fail(WPCD_ERR_INVALID, "wpcd_sigma_band: n_tlab must be in [1, 256]");
+  if (n_frac < 1 || n_frac > 16) return fail(WPCD_ERR_INVALID, "wpcd_sigma_band: n_frac must be in [1, 16]");
+  if (b->max_nbins > 1200) return fail(WPCD_ERR_UNSUPPORTED, "wpcd_sigma_band: more than 1200 bins");
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  WPCD_HIPX(b->ctx, timed(b->ctx, WPCD_STAGE_SIGMA, stream,
+                          [&] {
+                            return launch_sigma_band(b->d_items, b->d_sample_ptr, b->d_sample_items, b->n_samples,
+                                                     b->d_grids, delta_deg, mix_deg, tlab_mev, n_tlab, fracs, n_frac,
+                                                     sigma_lo_mb, sigma_hi_mb, stream);
+                          }),
+            "wpcd_sigma_band launch");
+  return WPCD_OK;
+}
+
 // ------------------------------------------------------- matrix inversion
 void wpcd_mi_destroy(wpcd_mi m) {
   if (!m) return;
-  hipSetDevice(m->ctx->device);
+  hipSetDevice(m->device);
   hipFree(m->d_items);
   hipFree(m->d_pts);
   hipFree(m->d_qw);
@@ -845,6 +944,7 @@ int wpcd_mi_create(wpcd_ctx ctx, const wpcd_mi_item* items_host, int n_items, in
   wpcd_mi_s* m = new (std::nothrow) wpcd_mi_s;
   if (!m) return fail(WPCD_ERR_NOMEM, "wpcd_mi_create: host allocation");
   m->ctx = ctx;
+  m->device = ctx->device;
   m->n_items = n_items;
   m->nq = n_q;
   m->ne = n_e;
@@ -979,6 +1079,198 @@ int wpcd_mi_solve(wpcd_mi m, const double* u, double* kmat, double* delta_deg, d
                             sigma_mb ? m->n_samples : 0, sigma_mb, status, stream),
             "wpcd_mi_solve launch");
   return WPCD_OK;
+}
+
+// ------------------------------------------------------------ whole path
+int wpcd_run(wpcd_batch b, const wpcd_path_args* a, int mode, hipStream_t stream) {
+  if (!b || !a) return fail(WPCD_ERR_INVALID, "wpcd_run: NULL argument");
+  if (b->n_fine > 0 && !a->u_fine) return fail(WPCD_ERR_INVALID, "wpcd_run: the batch has fine-mesh items but no u_fine");
+  if (b->n_affine > 0 && !a->coef) return fail(WPCD_ERR_INVALID, "wpcd_run: the batch has basis items but no coef");
+  if (a->n_tlab > 0 && (!a->tlab_mev || !a->sigma_mb)) return fail(WPCD_ERR_INVALID, "wpcd_run: n_tlab > 0 needs tlab and sigma");
+  int rc = WPCD_OK;
+  if (b->n_fine > 0) rc = wpcd_project(b, a->u_fine, a->u_dtype, a->v64, stream);
+  if (rc == WPCD_OK && b->n_affine > 0) rc = wpcd_project_affine(b, a->coef, a->v64, stream);
+  if (rc == WPCD_OK) rc = wpcd_eigh(b, a->v64, mode, a->eval, a->evec, a->eig_status, stream);
+  if (rc == WPCD_OK) rc = wpcd_tmatrix(b, a->v64, a->eval, a->evec, mode, a->t, a->t_status, stream);
+  if (rc == WPCD_OK) rc = wpcd_observables(b, a->t, a->delta_deg, a->mix_deg, a->s_dev, stream);
+  if (rc == WPCD_OK && a->n_tlab > 0)
+    rc = wpcd_sigma_tot(b, a->delta_deg, a->mix_deg, a->tlab_mev, a->n_tlab, a->sigma_mb, stream);
+  return rc;
+}
+
+// ------------------------------------------------------------- autotuner
+// Signature of a batch for the tune cache: mode and, per eigensolver size
+// class, the item count and largest n (what decides the launches).
+static std::string tune_signature(wpcd_batch b, int mode) {
+  std::string sig = mode == WPCD_MIXED ? "mixed" : "f64";
+  char buf[64];
+  for (int c = 0; c < kNumClasses; ++c) {
+    snprintf(buf, sizeof(buf), ":%d/%d", b->class_ptr[c + 1] - b->class_ptr[c], b->class_maxn[c]);
+    sig += buf;
+  }
+  return sig;
+}
+
+int wpcd_autotune(wpcd_batch b, const wpcd_path_args* a, int mode, int reps, const char* cache_path,
+                  wpcd_tune_result* out) {
+  if (!b || !a || !out) return fail(WPCD_ERR_INVALID, "wpcd_autotune: NULL argument");
+  if (reps < 1 || reps > 100) return fail(WPCD_ERR_INVALID, "wpcd_autotune: reps must be in [1, 100]");
+  if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_autotune: unknown mode %d", mode);
+  memset(out, 0, sizeof(*out));
+  wpcd_ctx ctx = b->ctx;
+  const std::string sig = tune_signature(b, mode);
+  // the tune cache: one line per signature, "<signature> <jacobi_block> <refine_gemm> <ms>"
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[512], key[400];
+      int jb = 0, rg = 0;
+      double ms = 0.0;
+      bool hit = false;
+      while (fgets(line, sizeof(line), f))
+        if (sscanf(line, "%399s %d %d %lf", key, &jb, &rg, &ms) == 4 && sig == key && jb >= 0 && jb <= 6 &&
+            (rg == 0 || rg == 1)) {
+          out->jacobi_block = jb;
+          out->refine_gemm = rg;
+          out->best_ms = ms;
+          hit = true;  // the last matching line wins
+        }
+      fclose(f);
+      if (hit) {
+        out->from_cache = 1;
+        ctx->cfg.jacobi_block = out->jacobi_block;
+        ctx->cfg.refine_gemm = out->refine_gemm;
+        return WPCD_OK;
+      }
+    }
+  }
+  if (ctx->profiling) return fail(WPCD_ERR_INVALID, "wpcd_autotune: the stage timers are on");
+  WPCD_HIPX(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  WPCD_STICKY(ctx);
+  // candidates: LDS Jacobi variant (two-column blocks / four-column blocks
+  // with one angle per quarter row) x refinement products (whole-item /
+  // tiles); the FP64 path has one schedule
+  const int cand[4][2] = {{0, 0}, {5, 0}, {0, 1}, {5, 1}};
+  const int n_cand = mode == WPCD_MIXED ? 4 : 1;
+  const wpcd_config saved = ctx->cfg;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int rc = e == hipSuccess ? WPCD_OK : hip_fail(e, "wpcd_autotune: stream and events");
+  double best = 0.0;
+  int best_i = 0;
+  for (int i = 0; i < n_cand && rc == WPCD_OK; ++i) {
+    ctx->cfg.jacobi_block = cand[i][0];
+    ctx->cfg.refine_gemm = cand[i][1];
+    rc = wpcd_run(b, a, mode, st);  // warm-up (first use of kernels and streams)
+    if (rc == WPCD_OK) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == WPCD_OK && e == hipSuccess; ++r) rc = wpcd_run(b, a, mode, st);
+    if (rc == WPCD_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+    if (rc == WPCD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (rc == WPCD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (rc == WPCD_OK && e != hipSuccess) rc = dev_fail(ctx, e, "wpcd_autotune: timing");
+    if (rc != WPCD_OK) break;
+    out->cand_ms[i] = (double)ms / reps;
+    if (i == 0 || out->cand_ms[i] < best) {
+      best = out->cand_ms[i];
+      best_i = i;
+    }
+  }
+  if (e1) hipEventDestroy(e1);
+  if (e0) hipEventDestroy(e0);
+  if (st) hipStreamDestroy(st);
+  ctx->cfg = saved;
+  if (rc != WPCD_OK) return rc;
+  out->n_cand = n_cand;
+  out->jacobi_block = mode == WPCD_MIXED ? cand[best_i][0] : saved.jacobi_block;
+  out->refine_gemm = mode == WPCD_MIXED ? cand[best_i][1] : saved.refine_gemm;
+  out->best_ms = best;
+  ctx->cfg.jacobi_block = out->jacobi_block;
+  ctx->cfg.refine_gemm = out->refine_gemm;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(WPCD_ERR_INVALID, "wpcd_autotune: cannot append to the tune cache %s", cache_path);
+    fprintf(f, "%s %d %d %.6f\n", sig.c_str(), out->jacobi_block, out->refine_gemm, best);
+    fclose(f);
+  }
+  return WPCD_OK;
+}
+
+}  // extern "C"
+
+struct wpcd_graph_s {
+  wpcd_ctx ctx = nullptr;
+  int device = 0;  // the context's device (destroy must not read the context: it may be gone)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t nodes = 0;
+};
+
+extern "C" {
+
+int wpcd_graph_create(wpcd_batch b, const wpcd_path_args* a, int mode, wpcd_graph* out) {
+  if (!b || !a || !out) return fail(WPCD_ERR_INVALID, "wpcd_graph_create: NULL argument");
+  *out = nullptr;
+  if (b->ctx->profiling)
+    return fail(WPCD_ERR_INVALID, "wpcd_graph_create: the stage timers are on (they cannot time a graph's replays)");
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  if (mode == WPCD_MIXED) {
+    const int rc = ensure_side(b->ctx);  // before the capture: the capture creates no stream
+    if (rc != WPCD_OK) return rc;
+  }
+  hipStream_t cs = nullptr;
+  WPCD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "wpcd_graph_create: capture stream");
+  wpcd_graph_s* g = new (std::nothrow) wpcd_graph_s;
+  if (!g) {
+    hipStreamDestroy(cs);
+    return fail(WPCD_ERR_NOMEM, "wpcd_graph_create: host allocation");
+  }
+  g->ctx = b->ctx;
+  g->device = b->ctx->device;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int rc = e == hipSuccess ? wpcd_run(b, a, mode, cs) : WPCD_OK;
+  std::string run_err = rc != WPCD_OK ? g_err : std::string();
+  // end the capture in every case (a failed run leaves a partial graph)
+  hipGraph_t graph = nullptr;
+  const hipError_t e_end = e == hipSuccess ? hipStreamEndCapture(cs, &graph) : e;
+  if (rc == WPCD_OK && e_end == hipSuccess && graph) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  else if (e == hipSuccess) e = e_end;
+  g->graph = graph;
+  if (e == hipSuccess && graph) e = hipGraphGetNodes(graph, nullptr, &g->nodes);
+  hipStreamDestroy(cs);
+  if (rc != WPCD_OK || e != hipSuccess || !g->exec) {
+    wpcd_graph_destroy(g);
+    if (rc != WPCD_OK) return fail(rc, "wpcd_graph_create: %s", run_err.c_str());
+    return hip_fail(e != hipSuccess ? e : hipErrorUnknown, "wpcd_graph_create: capture");
+  }
+  *out = g;
+  return WPCD_OK;
+}
+
+int wpcd_graph_launch(wpcd_graph g, hipStream_t stream) {
+  if (!g) return fail(WPCD_ERR_INVALID, "wpcd_graph_launch: NULL graph");
+  WPCD_HIPX(g->ctx, hipSetDevice(g->ctx->device), "hipSetDevice");
+  WPCD_STICKY(g->ctx);
+  WPCD_HIPX(g->ctx, hipGraphLaunch(g->exec, stream), "wpcd_graph_launch");
+  return WPCD_OK;
+}
+
+int wpcd_graph_nodes(wpcd_graph g, int64_t* nodes) {
+  if (!g || !nodes) return fail(WPCD_ERR_INVALID, "wpcd_graph_nodes: NULL argument");
+  *nodes = (int64_t)g->nodes;
+  return WPCD_OK;
+}
+
+void wpcd_graph_destroy(wpcd_graph g) {
+  if (!g) return;
+  hipSetDevice(g->device);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
 }
 
 int wpcd_profile_enable(wpcd_ctx ctx, int on) {

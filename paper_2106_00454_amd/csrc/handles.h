@@ -52,6 +52,7 @@ struct wpcd_context {
 
 struct wpcd_batch_s {
   wpcd_ctx ctx = nullptr;
+  int device = 0;  // the context's device (destroy must not read the context: it may be gone)
   int n_items = 0, n_samples = 0, max_n = 0, min_n = 0, max_nbins = 0;
   int warm_min_n = 0, warm_max_n = 0;  // sizes of the warm-started items
   std::vector<wpcd::ItemDev> h_items;
@@ -92,6 +93,7 @@ struct wpcd_batch_s {
 
 struct wpcd_mi_s {
   wpcd_ctx ctx = nullptr;
+  int device = 0;  // the context's device (destroy must not read the context: it may be gone)
   int n_items = 0, n_samples = 0, nq = 0, ne = 0, max_nch = 0;
   double cutoff = 0.0;
   std::vector<wpcd::MiItemDev> h_items;

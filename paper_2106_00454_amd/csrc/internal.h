@@ -11,14 +11,16 @@
 namespace wpcd {
 
 // Device view of a resident bin grid.
+// Momentum packets (f = 1, N_i = dk_i) and energy packets (f = sqrt(2k),
+// N_i = dE_i) differ only in these tables.
 struct GridDev {
   const double* kb;    // N+1 bin boundaries k_j
   const double* eb;    // N+1 boundary energies k_j^2
-  const double* dk;    // N bin widths
-  const double* kbar;  // N midpoints
-  const double* e0;    // N free-Hamiltonian diagonal <k^2> over the bin
-  const double* wk;    // N*ng Gauss weight times node, bin-major
-  const double* rsdk;  // N 1/sqrt(dk)
+  const double* dk;    // N: N_i/f(q_i)^2 (the bin width for momentum packets)
+  const double* kbar;  // N on-shell momenta q_i (the bin midpoints for momentum packets)
+  const double* e0;    // N free-Hamiltonian diagonal <x_i|k^2|x_i>
+  const double* wk;    // N*ng Gauss weight times node times f(node), bin-major
+  const double* rsdk;  // N 1/sqrt(N_i)
   int32_t N;
   int32_t ng;
 };
@@ -109,13 +111,14 @@ hipError_t launch_rayleigh_f64(const ItemDev* items, int n_items, int max_n, con
                                const double* v64, double* work, double* evec, double* eval, int32_t* status,
                                hipStream_t s);
 // gemm: 0 = whole-item products when every item has 193..208 rows, else
-// 64 x 64 tiles; 1 = tiles.  side (with two events, or nullptr): a second
-// stream on which part of each step runs concurrently; the work on s waits
-// for it before going on.
+// 64 x 64 tiles; 1 = tiles.  rr_steps: the last rr_steps steps solve
+// clusters by Rayleigh-Ritz (0 = all).  side (with two events, or nullptr):
+// a second stream on which part of each step runs concurrently; the work on
+// s waits for it before going on.
 hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n, const GridDev* grids,
                          const double* v64, const float* x32, double* evec, double* eval, double* lam_pre,
                          double* work, int32_t* cl, int32_t* status, int steps, int close_log10, int gemm,
-                         hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join);
+                         int rr_steps, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join);
 hipError_t launch_tmatrix(const ItemDev* items, int n_items, int max_n, const GridDev* grids, const double* v64,
                           const double* eval, const double* evec, int mode, double* t, int32_t* status,
                           hipStream_t s);
@@ -128,6 +131,10 @@ hipError_t launch_saclay(const ItemDev* items, const int32_t* sample_ptr, const 
 hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
                         int n_samples, const GridDev* grids, const double* delta, const double* mix,
                         const double* tlab, const int32_t* tlab_off, int n_tlab, double* sigma, hipStream_t s);
+hipError_t launch_sigma_band(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
+                             int n_samples, const GridDev* grids, const double* delta, const double* mix,
+                             const double* tlab, int n_tlab, const double* fracs, int n_frac, double* sigma_lo,
+                             double* sigma_hi, hipStream_t s);
 
 // Matrix-inversion solver (the paper's comparison method): one item = one
 // channel of one sample, solved at every energy of the solver object.

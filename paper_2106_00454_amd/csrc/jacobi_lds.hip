@@ -11,6 +11,7 @@
 // and eigenvectors as a row-major FP32 workspace X[r*n + m], both sorted by
 // ascending eigenvalue.
 #include "jacobi_common.h"
+#include "jacobi_quad.h"
 
 namespace wpcd {
 namespace {
@@ -28,10 +29,12 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   extern __shared__ float W[];
   __shared__ int s_nrot;
   __shared__ float nrm[kMaxLdsN];
-  constexpr bool kSorted = B == 0 || B == 5 || B == 6 || B == 7;  // variants with sorted columns, tracked norms
+  constexpr bool kSorted = B == 0 || (B >= 5 && B <= 9);  // sorted columns, tracked norms
+  constexpr bool kScaled = B >= 7 && B <= 9;               // scaled rotations
+  constexpr int kPadCols = (B == 7 || B == 9) ? 2 : (B == 8 ? 4 : 1);  // W holds n rounded up to this many columns
   __shared__ float diag[kSorted ? kMaxLdsN : 1];
   __shared__ int perm[kSorted ? kMaxLdsN : 1];
-  __shared__ float dsc[B == 7 ? kMaxLdsN : 1];  // column scales of the scaled-rotation variant
+  __shared__ float dsc[kScaled ? kMaxLdsN : 1];  // column scales of the scaled-rotation variants
   __shared__ int rot_flag[64];
   __shared__ float scratch[BLOCK / 64];
   __shared__ int bad;
@@ -39,9 +42,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   const int item = sel ? sel[blockIdx.x] : (int)blockIdx.x;
   const ItemDev it = items[item];
   const int n = it.n, N = it.N;
-  // variant 0 reads RMAX*G rows per column unguarded, variants 5, 6 and 7 guard
+  // variant 0 reads RMAX*G rows per column unguarded, variants 5 to 9 guard
   // only their last row chunk: the rows up to there (n .. rows-1) are zero
-  const int rows = B == 0 ? max(n, RMAX * G) : ((B == 5 || B == 6 || B == 7) ? max(n, (RMAX - 1) * G) : n);
+  const int rows = B == 0 ? max(n, RMAX * G) : ((B >= 5 && B <= 9) ? max(n, (RMAX - 1) * G) : n);
   const int ld = lds_stride(rows);
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
@@ -95,8 +98,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
       const int j = e / rows, r = e - j * rows;
       W[j * ld + r] = r < n ? fmaf(sigma, Q0[j * n + r], Y0[j * n + r]) : 0.f;
     }
-    if (B == 7 && (n & 1))  // the zero column completing the last block of 2
-      for (int r = threadIdx.x; r < rows; r += BLOCK) W[n * ld + r] = 0.f;
+    if (kPadCols > 1)  // the zero columns completing the last block
+      for (int e = threadIdx.x; e < (((n + kPadCols - 1) / kPadCols) * kPadCols - n) * rows; e += BLOCK)
+        W[(n + e / rows) * ld + e % rows] = 0.f;
     __syncthreads();
   } else if constexpr (kSorted) {
     // |B e_c|^2 = |H e_c|^2 + 2 sigma H_cc + sigma^2; rank by descending norm.
@@ -128,8 +132,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
       if (r == c) w += sigma;
       W[j * ld + r] = w;
     }
-    if (B == 7 && (n & 1))  // the zero column completing the last block of 2
-      for (int r = threadIdx.x; r < rows; r += BLOCK) W[n * ld + r] = 0.f;
+    if (kPadCols > 1)  // the zero columns completing the last block
+      for (int e = threadIdx.x; e < (((n + kPadCols - 1) / kPadCols) * kPadCols - n) * rows; e += BLOCK)
+        W[(n + e / rows) * ld + e % rows] = 0.f;
     __syncthreads();
   } else {
     const int nr = n * rows;
@@ -159,6 +164,10 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   else if constexpr (B == 7)  // blocks of 2 columns, tracked norms, scaled rotations
     sweeps = onesided_jacobi_blocked_scaled<BLOCK, G, RMAX, 2>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc,
                                                                 nrot);
+  else if constexpr (B == 8)  // blocks of 4 columns, scaled rotations, one angle per quarter row
+    sweeps = onesided_jacobi_parts<BLOCK, RMAX, 4>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc, nrot);
+  else if constexpr (B == 9)  // blocks of 2 columns, scaled rotations, one angle per half row
+    sweeps = onesided_jacobi_parts<BLOCK, RMAX, 2>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc, nrot);
   else if constexpr (B == 6)  // blocks of 4 columns, tracked norms
     sweeps = onesided_jacobi_blocked_tracked<BLOCK, G, RMAX, 4>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, nrot);
   else  // unblocked, three dot products per pair
@@ -221,9 +230,9 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
   if (max_n > kMaxLdsN) return hipErrorInvalidValue;
   if (max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
-  auto go = [&](auto kern, int block, int rows_min, bool pad = false) -> hipError_t {
-    // pad: one more column for odd sizes and 16 spare floats (scaled-rotation variant)
-    const int cols = pad ? (max_n + 1) / 2 * 2 : max_n;
+  auto go = [&](auto kern, int block, int rows_min, int pad = 0) -> hipError_t {
+    // pad: columns rounded up to a multiple of pad and 16 spare floats (scaled-rotation variants)
+    const int cols = pad ? (max_n + pad - 1) / pad * pad : max_n;
     const size_t lds =
         ((size_t)lds_stride(max_n > rows_min ? max_n : rows_min) * cols + (pad ? 16 : 0)) * sizeof(float);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -237,12 +246,18 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
   // with tracked norms and scaled rotations, 1 unblocked with three dot
   // products per pair, 2 unblocked with tracked norms, 3 blocks of 2 columns
   // with tracked norms and plain rotations, 4 blocks of 4 columns with
-  // tracked norms
-  const int B = block_cols == 0 ? 7 : (block_cols == 1 ? 1 : (block_cols == 2 ? 0 : (block_cols == 3 ? 5 : 6)));
+  // tracked norms, 5 blocks of 4 columns with scaled rotations and one angle
+  // per quarter row, 6 blocks of 2 columns with one angle per half row
+  // (jacobi_quad.h)
+  static constexpr int kVariant[7] = {7, 1, 0, 5, 6, 8, 9};
+  if (block_cols < 0 || block_cols > 6) return hipErrorInvalidValue;
+  const int B = kVariant[block_cols];
   if (max_n <= 64) {
     if (B == 0) return go(jacobi_f32_lds_kernel<256, 4, 16, 0>, 256, 64);
     if (B == 5) return go(jacobi_f32_lds_kernel<256, 16, 4, 5>, 256, 48);
-    if (B == 7) return go(jacobi_f32_lds_kernel<256, 16, 4, 7>, 256, 48, true);
+    if (B == 7) return go(jacobi_f32_lds_kernel<256, 16, 4, 7>, 256, 48, 2);
+    if (B == 8) return go(jacobi_f32_lds_kernel<128, 16, 4, 8>, 128, 48, 4);
+    if (B == 9) return go(jacobi_f32_lds_kernel<256, 16, 4, 9>, 256, 48, 2);
     if (B == 6) return go(jacobi_f32_lds_kernel<256, 32, 2, 6>, 256, 32);
     if (B == 1) return go(jacobi_f32_lds_kernel<256, 4, 16, 1>, 256, 0);
     return hipErrorInvalidValue;
@@ -250,14 +265,18 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
   if (max_n <= 128) {
     if (B == 0) return go(jacobi_f32_lds_kernel<512, 8, 16, 0>, 512, 128);
     if (B == 5) return go(jacobi_f32_lds_kernel<512, 16, 8, 5>, 512, 112);
-    if (B == 7) return go(jacobi_f32_lds_kernel<512, 16, 8, 7>, 512, 112, true);
+    if (B == 7) return go(jacobi_f32_lds_kernel<512, 16, 8, 7>, 512, 112, 2);
+    if (B == 8) return go(jacobi_f32_lds_kernel<256, 16, 8, 8>, 256, 112, 4);
+    if (B == 9) return go(jacobi_f32_lds_kernel<512, 16, 8, 9>, 512, 112, 2);
     if (B == 6) return go(jacobi_f32_lds_kernel<512, 32, 4, 6>, 512, 96);
     if (B == 1) return go(jacobi_f32_lds_kernel<512, 8, 16, 1>, 512, 0);
     return hipErrorInvalidValue;
   }
   if (B == 0) return go(jacobi_f32_lds_kernel<1024, 8, 25, 0>, 1024, 200);
   if (B == 5) return go(jacobi_f32_lds_kernel<1024, 16, 13, 5>, 1024, 192);
-  if (B == 7) return go(jacobi_f32_lds_kernel<1024, 16, 13, 7>, 1024, 192, true);
+  if (B == 7) return go(jacobi_f32_lds_kernel<1024, 16, 13, 7>, 1024, 192, 2);
+  if (B == 8) return go(jacobi_f32_lds_kernel<512, 16, 13, 8>, 512, 192, 4);
+  if (B == 9) return go(jacobi_f32_lds_kernel<1024, 16, 13, 9>, 1024, 192, 2);
   if (B == 6) return go(jacobi_f32_lds_kernel<1024, 32, 7, 6>, 1024, 192);
   if (B == 1) return go(jacobi_f32_lds_kernel<1024, 8, 25, 1>, 1024, 0);
   return hipErrorInvalidValue;

@@ -57,6 +57,65 @@ __global__ __launch_bounds__(256) void observables_kernel(const ItemDev* __restr
 constexpr int kSigBlock = 256;
 constexpr int kSigMaxBins = 1200;
 
+// The phases of one item unwrapped modulo 180 degrees from its lowest bin up
+// (dl, one thread per orbital channel; sh the multiples of 180 applied) and
+// its mixing angle with the sign of the parity of the two shifts (mx).  Called
+// by the whole work-group; begins and ends with a barrier.
+__device__ void unwrap_item(const ItemDev& it, const double* __restrict__ delta, const double* __restrict__ mix,
+                            double (*dl)[kSigMaxBins], int (*sh)[kSigMaxBins], double* mx) {
+  const int N = it.N, K = it.nch;
+  __syncthreads();
+  if (threadIdx.x < K) {
+    const int a = threadIdx.x;
+    const double* dp = delta + it.d_off;
+    double prev = dp[a];
+    dl[a][0] = prev;
+    sh[a][0] = 0;
+    for (int k = 1; k < N; ++k) {
+      const double raw = dp[(int64_t)k * K + a];
+      const double s = rint((prev - raw) / 180.0);
+      prev = raw + 180.0 * s;
+      dl[a][k] = prev;
+      sh[a][k] = (int)s;
+    }
+  }
+  __syncthreads();
+  if (K == 2)
+    for (int k = threadIdx.x; k < N; k += blockDim.x)
+      mx[k] = (((sh[0][k] + sh[1][k]) & 1) ? -1.0 : 1.0) * mix[it.m_off + k];
+  __syncthreads();
+}
+
+// (2J+1) sum_a (1 - Re S_aa) at momentum p from the unwrapped phases, linear
+// in q between the abscissae x (N of them, ascending; the end segments
+// extrapolated), S rebuilt in the Stapp form.
+template <class X>
+__device__ double item_loss(const ItemDev& it, X x, double p, const double (*dl)[kSigMaxBins], const double* mx) {
+  const int N = it.N, K = it.nch;
+  // i = number of abscissae <= p, clamped to [1, N-1]
+  int lo = 0, hi = N;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x(mid) <= p) lo = mid + 1;
+    else hi = mid;
+  }
+  const int i = lo < 1 ? 1 : (lo > N - 1 ? N - 1 : lo);
+  const double x0 = x(i - 1), x1 = x(i);
+  const double f = (p - x0) / (x1 - x0);
+  double loss = 0.0;
+  if (K == 1) {
+    const double d = (dl[0][i - 1] + (dl[0][i] - dl[0][i - 1]) * f) / kRadToDeg;
+    loss = 1.0 - cos(2.0 * d);
+  } else {
+    const double e = (mx[i - 1] + (mx[i] - mx[i - 1]) * f) / kRadToDeg;
+    for (int a = 0; a < 2; ++a) {
+      const double d = (dl[a][i - 1] + (dl[a][i] - dl[a][i - 1]) * f) / kRadToDeg;
+      loss += 1.0 - cos(2.0 * e) * cos(2.0 * d);
+    }
+  }
+  return (2.0 * it.J + 1.0) * loss;
+}
+
 __global__ __launch_bounds__(kSigBlock) void sigma_kernel(const ItemDev* __restrict__ items,
                                                           const int32_t* __restrict__ sample_ptr,
                                                           const int32_t* __restrict__ sample_items,
@@ -88,26 +147,7 @@ __global__ __launch_bounds__(kSigBlock) void sigma_kernel(const ItemDev* __restr
     const ItemDev it = items[sample_items[ii]];
     const GridDev g = grids[it.grid];
     const int N = it.N, K = it.nch;
-    __syncthreads();
-    if (threadIdx.x < K) {
-      const int a = threadIdx.x;
-      const double* dp = delta + it.d_off;
-      double prev = dp[a];
-      dl[a][0] = prev;
-      sh[a][0] = 0;
-      for (int k = 1; k < N; ++k) {
-        const double raw = dp[(int64_t)k * K + a];
-        const double s = rint((prev - raw) / 180.0);
-        prev = raw + 180.0 * s;
-        dl[a][k] = prev;
-        sh[a][k] = (int)s;
-      }
-    }
-    __syncthreads();
-    if (K == 2)
-      for (int k = threadIdx.x; k < N; k += kSigBlock)
-        mx[k] = (((sh[0][k] + sh[1][k]) & 1) ? -1.0 : 1.0) * mix[it.m_off + k];
-    __syncthreads();
+    unwrap_item(it, delta, mix, dl, sh, mx);
     const double* kb = g.kbar;
     const double kmax = g.kb[N];
     for (int q = 0; q < kPer; ++q) {
@@ -118,28 +158,7 @@ __global__ __launch_bounds__(kSigBlock) void sigma_kernel(const ItemDev* __restr
         acc[q] = NAN;
         continue;
       }
-      // i = number of midpoints <= p, clamped to [1, N-1]
-      int lo = 0, hi = N;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (kb[mid] <= p) lo = mid + 1;
-        else hi = mid;
-      }
-      int i = lo < 1 ? 1 : (lo > N - 1 ? N - 1 : lo);
-      const double x0 = kb[i - 1], x1 = kb[i];
-      const double f = (p - x0) / (x1 - x0);
-      double loss = 0.0;
-      if (K == 1) {
-        const double d = (dl[0][i - 1] + (dl[0][i] - dl[0][i - 1]) * f) / kRadToDeg;
-        loss = 1.0 - cos(2.0 * d);
-      } else {
-        const double e = (mx[i - 1] + (mx[i] - mx[i - 1]) * f) / kRadToDeg;
-        for (int a = 0; a < 2; ++a) {
-          const double d = (dl[a][i - 1] + (dl[a][i] - dl[a][i - 1]) * f) / kRadToDeg;
-          loss += 1.0 - cos(2.0 * e) * cos(2.0 * d);
-        }
-      }
-      acc[q] += (2.0 * it.J + 1.0) * loss;
+      acc[q] += item_loss(it, [kb](int m) { return kb[m]; }, p, dl, mx);
     }
   }
   for (int q = 0; q < kPer; ++q) {
@@ -148,6 +167,57 @@ __global__ __launch_bounds__(kSigBlock) void sigma_kernel(const ItemDev* __restr
     const double p = sqrt(kMnMeV * tlab[j] / 2.0) / kHbarcMeVfm;
     sigma[j] = 10.0 * kPi / (2.0 * p * p) * acc[q];
   }
+}
+
+// Interpolation-point bands (Sec. 5.1.1): the phases of bin i are placed at
+// q_i = k_{i-1} + f (k_i - k_{i-1}) for every fraction f of the list, sigma is
+// evaluated for each f as in sigma_kernel, and the lowest and highest values
+// over f are written.  One work-group per sample, one thread per energy.
+constexpr int kBandMaxFrac = 16;
+
+__global__ __launch_bounds__(kSigBlock) void sigma_band_kernel(
+    const ItemDev* __restrict__ items, const int32_t* __restrict__ sample_ptr, const int32_t* __restrict__ sample_items,
+    const GridDev* __restrict__ grids, const double* __restrict__ delta, const double* __restrict__ mix,
+    const double* __restrict__ tlab, int n_tlab, const double* __restrict__ fracs, int n_frac,
+    double* __restrict__ sigma_lo, double* __restrict__ sigma_hi) {
+  __shared__ double dl[2][kSigMaxBins];
+  __shared__ double mx[kSigMaxBins];
+  __shared__ int sh[2][kSigMaxBins];
+  __shared__ double fr[kBandMaxFrac];
+  const int smp = blockIdx.x;
+  const int i0 = sample_ptr[smp], i1 = sample_ptr[smp + 1];
+  if (threadIdx.x < n_frac) fr[threadIdx.x] = fracs[threadIdx.x];
+  const int j = threadIdx.x;
+  const double p = j < n_tlab ? sqrt(kMnMeV * tlab[j] / 2.0) / kHbarcMeVfm : 1.0;
+  double acc[kBandMaxFrac];
+#pragma unroll
+  for (int f = 0; f < kBandMaxFrac; ++f) acc[f] = 0.0;
+  bool out = !(p > 0.0);
+  for (int ii = i0; ii < i1; ++ii) {
+    const ItemDev it = items[sample_items[ii]];
+    const GridDev g = grids[it.grid];
+    unwrap_item(it, delta, mix, dl, sh, mx);
+    if (j >= n_tlab) continue;
+    const double* kb = g.kb;
+    out = out || p > kb[it.N];
+#pragma unroll
+    for (int f = 0; f < kBandMaxFrac; ++f) {
+      if (f >= n_frac) break;
+      const double fv = fr[f];
+      acc[f] += item_loss(it, [kb, fv](int m) { return kb[m] + fv * (kb[m + 1] - kb[m]); }, p, dl, mx);
+    }
+  }
+  if (j >= n_tlab) return;
+  double lo = acc[0], hi = acc[0];
+#pragma unroll
+  for (int f = 1; f < kBandMaxFrac; ++f) {
+    if (f >= n_frac) break;
+    lo = fmin(lo, acc[f]);
+    hi = fmax(hi, acc[f]);
+  }
+  const double sc = 10.0 * kPi / (2.0 * p * p);
+  sigma_lo[(int64_t)smp * n_tlab + j] = out ? NAN : sc * lo;
+  sigma_hi[(int64_t)smp * n_tlab + j] = out ? NAN : sc * hi;
 }
 
 // ------------------------------------------------------- spin observables
@@ -237,26 +307,7 @@ __global__ __launch_bounds__(kSigBlock) void saclay_kernel(const ItemDev* __rest
     const ItemDev it = items[sample_items[ii]];
     const GridDev g = grids[it.grid];
     const int N = it.N, K = it.nch;
-    __syncthreads();
-    if (threadIdx.x < K) {
-      const int a = threadIdx.x;
-      const double* dp = delta + it.d_off;
-      double prev = dp[a];
-      dl[a][0] = prev;
-      sh[a][0] = 0;
-      for (int k = 1; k < N; ++k) {
-        const double raw = dp[(int64_t)k * K + a];
-        const double s = rint((prev - raw) / 180.0);
-        prev = raw + 180.0 * s;
-        dl[a][k] = prev;
-        sh[a][k] = (int)s;
-      }
-    }
-    __syncthreads();
-    if (K == 2)
-      for (int k = threadIdx.x; k < N; k += kSigBlock)
-        mx[k] = (((sh[0][k] + sh[1][k]) & 1) ? -1.0 : 1.0) * mix[it.m_off + k];
-    __syncthreads();
+    unwrap_item(it, delta, mix, dl, sh, mx);
     const double* kb = g.kbar;
     const double kmax = g.kb[N];
     const int s = it.spin, J = it.J;
@@ -386,6 +437,16 @@ hipError_t launch_sigma(const ItemDev* items, const int32_t* sample_ptr, const i
   if (n_tlab > 4 * kSigBlock) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sigma_kernel, dim3(n_samples), dim3(kSigBlock), 0, s, items, sample_ptr, sample_items, grids,
                      delta, mix, tlab, tlab_off, n_tlab, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_band(const ItemDev* items, const int32_t* sample_ptr, const int32_t* sample_items,
+                             int n_samples, const GridDev* grids, const double* delta, const double* mix,
+                             const double* tlab, int n_tlab, const double* fracs, int n_frac, double* sigma_lo,
+                             double* sigma_hi, hipStream_t s) {
+  if (n_tlab < 1 || n_tlab > kSigBlock || n_frac < 1 || n_frac > kBandMaxFrac) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sigma_band_kernel, dim3(n_samples), dim3(kSigBlock), 0, s, items, sample_ptr, sample_items,
+                     grids, delta, mix, tlab, n_tlab, fracs, n_frac, sigma_lo, sigma_hi);
   return hipGetLastError();
 }
 

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restric
   const WS ws(work, it);
   for (int i = threadIdx.x; i < n; i += kBlock) {
     lam[i] = lam_pre[it.e_off + i];
-    rch[i] = cl[it.e_off + i];
+    rch[i] = cl ? cl[it.e_off + i] : i;  // no reach list: no chains
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1589,7 +1589,7 @@ struct IgWarm {
 hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n, const GridDev* grids,
                          const double* v64, const float* x32, double* evec, double* eval, double* lam_pre,
                          double* work, int32_t* cl, int32_t* status, int steps, int close_log10, int gemm,
-                         hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+                         int rr_steps, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
   if (max_n > kMaxN) return hipErrorInvalidValue;
   const int nt = (max_n + kTM - 1) / kTM;  // 64-row blocks of form_m
   const int nt2 = (max_n + T64::TM - 1) / T64::TM;  // GEMM tiles
@@ -1642,24 +1642,35 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
       hipLaunchKernelGGL(refine_reach_kernel, dim3((max_n + kReachRows - 1) / kReachRows, gy),
                          dim3(64 * kReachRows), 0, s, items + i0, lam_pre, work, cl, closec);
     }
+    // a step without Rayleigh-Ritz: M = I + E for every column (close pairs
+    // take R_ij/2), no chain kernel
+    const bool rr = rr_steps <= 0 || st >= steps - rr_steps;
+    if (!rr) {
+      for (int i0 = 0; i0 < n_items; i0 += 65535) {
+        const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
+        hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work,
+                           (const int32_t*)nullptr, closec);
+      }
+    }
     // M: the columns outside chains (form_m, streaming S and G) on the side
     // stream while the chain kernel (latency-bound) writes the chain columns
     hipStream_t sm = s;
-    if (side != nullptr) {
+    if (rr && side != nullptr) {
       err = hipEventRecord(fork, s);
       if (err == hipSuccess) err = hipStreamWaitEvent(side, fork, 0);
       if (err != hipSuccess) return err;
       sm = side;
     }
-    for (int i0 = 0; i0 < n_items; i0 += 65535) {
+    for (int i0 = 0; rr && i0 < n_items; i0 += 65535) {
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, sm, items, i0, lam_pre, work, cl, closec);
     }
-    hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
-                       status, closec);
+    if (rr)
+      hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
+                         status, closec);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    if (side != nullptr) {
+    if (rr && side != nullptr) {
       err = hipEventRecord(join, side);
       if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
       if (err != hipSuccess) return err;

@@ -85,6 +85,7 @@ struct Slot {
 
 struct wpcd_server_s {
   wpcd_ctx ctx = nullptr;
+  int device = 0;  // the context's device (destroy must not read the context: it may be gone)
   wpcd_server_config cfg{};
   std::vector<GridHost*> grids_host;
   std::vector<BasisHost> bases;
@@ -302,7 +303,8 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
   }
   if (e == hipSuccess)
     e = launch_refine(d_items, n, min_n, max_n, d_grids, d_v64, d_x32, d_evec, d_eval, d_lam, d_work, d_cl, d_est,
-                      std::max(1, c.refine_steps), c.refine_close_log10, c.refine_gemm, s.stream, nullptr, nullptr,
+                      std::max(1, c.refine_steps), c.refine_close_log10, c.refine_gemm, c.refine_rr_steps, s.stream, nullptr,
+                      nullptr,
                       nullptr);
   if (e == hipSuccess)
     e = launch_tmatrix(d_items, n, max_n, d_grids, d_v64, d_eval, d_evec, WPCD_MIXED, d_t, d_tst, s.stream);
@@ -455,6 +457,7 @@ int wpcd_server_create(wpcd_ctx ctx, const wpcd_server_config* cfg, wpcd_server*
   wpcd_server_s* s = new (std::nothrow) wpcd_server_s;
   if (!s) return sfail(WPCD_ERR_NOMEM, "wpcd_server_create: host allocation");
   s->ctx = ctx;
+  s->device = ctx->device;
   s->cfg = c;
   s->bases = ctx->bases;
   for (auto& g : ctx->grids) s->grids_host.push_back(&g);
@@ -494,7 +497,7 @@ void wpcd_server_destroy(wpcd_server s) {
   }
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  hipSetDevice(s->ctx->device);
+  hipSetDevice(s->device);
   for (auto& sl : s->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
     if (sl.stream) hipStreamDestroy(sl.stream);

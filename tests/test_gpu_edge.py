@@ -30,10 +30,12 @@ def coupled():
     return k, configs.coupled_yukawa_terms(xo)
 
 
-@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
-def test_weak_tensor_coupling(coupled, mode):
+@pytest.mark.parametrize("mode,rr", [(wp.MIXED, 0), (wp.MIXED, 1), (wp.F64, 0)])
+def test_weak_tensor_coupling(coupled, mode, rr):
+    # rr = 1: only the last refinement step solves clusters by Rayleigh-Ritz
+    # (wpcd_config.refine_rr_steps); the near-degenerate pairs are such clusters
     k, t_or = coupled
-    ctx = wp.Context(0)
+    ctx = wp.Context(0, refine_rr_steps=rr)
     g = ctx.grid(k, configs.N_GAUSS)
     t_lib = configs.coupled_yukawa_terms(g.nodes)
     base = configs.yukawa_coefficients(3)
@@ -52,7 +54,7 @@ def test_weak_tensor_coupling(coupled, mode):
         sig_ref = oo.sigma_tot([(1, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
         print(f"weak tensor C_t scale {sc:g}: min eigenvalue gap {np.diff(ref['evals']).min():.2e}, "
               f"max |eps| oracle {np.abs(ref['mix']).max():.3e} gpu {np.abs(it['mix']).max():.3e}", flush=True)
-        check_item(f"weak tensor mode={mode} scale={sc:g}", it, ref, k, mode, 1, sig_ref, host["sigma"][i])
+        check_item(f"weak tensor mode={mode} rr={rr} scale={sc:g}", it, ref, k, mode, 1, sig_ref, host["sigma"][i])
         if sc == 0.0:
             # decoupled blocks: no rotation ever mixes the two orbital channels
             assert np.abs(it["mix"]).max() <= 1e-9

@@ -89,8 +89,8 @@ def test_coupled_batch_matches_oracle(ctx, coupled_setup, mode, dtype):
 
 
 # ------------------------------------------------ ragged mixed batch, odd n
-@pytest.mark.parametrize("mode", [wp.MIXED, wp.F64])
-def test_ragged_mixed_batch(ctx, mode):
+@pytest.mark.parametrize("mode,rr", [(wp.MIXED, 0), (wp.MIXED, 1), (wp.F64, 0)])
+def test_ragged_mixed_batch(ctx, mode, rr):
     # n = 37, 240, 40, 64, 233, 150, 100, 128, 200: every eigensolver size class
     # (<= 64, <= 128, <= 200 in LDS, > 200 in device memory) with its boundary
     # sizes, interleaved so each class launch works from a scattered item list
@@ -117,13 +117,18 @@ def test_ragged_mixed_batch(ctx, mode):
         items.append((g, K, J, sid))
         mats.append(f(g.nodes))
         refs.append((k, ow.solve_channel(k, 8, f(xo), K), J))
-    b, host = run_items(ctx, items, mats, mode)
+    # rr = 1: Rayleigh-Ritz on clusters in the last refinement step only
+    # (wpcd_config.refine_rr_steps), on a context of its own
+    rctx = ctx if rr == 0 else wp.Context(0, refine_rr_steps=rr)
+    if rctx is not ctx:
+        items = [(rctx.grid(g.k_bounds, 8), K, J, sid) for (g, K, J, sid) in items]
+    b, host = run_items(rctx, items, mats, mode)
     for i, (k, ref, J) in enumerate(refs):
         _, kbar, _ = ow.bins(k)
         it = item_view(b, host, i)
         K = it["delta"].shape[1]
         sig_ref = oo.sigma_tot([(J, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
-        check_item(f"ragged mode={mode} item={i} n={it['v'].shape[0]}", it, ref, k, mode, J, sig_ref,
+        check_item(f"ragged mode={mode} rr={rr} item={i} n={it['v'].shape[0]}", it, ref, k, mode, J, sig_ref,
                    host["sigma"][i])
 
 
@@ -163,7 +168,7 @@ def test_argument_errors_are_reported_before_launch(ctx):
 
 
 # ------------------------------------------------- LDS Jacobi variants
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 def test_lds_jacobi_variants_match_oracle(variant):
     # every variant of the in-LDS FP32 Jacobi (wpcd_config.jacobi_block), on
     # one item of each LDS size class (n = 37, 40, 128, 200), mixed precision
