@@ -278,6 +278,26 @@ int wpcd_project_affine(wpcd_batch b, const double* coef, double* v64, hipStream
 int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
               hipStream_t stream);
 
+/* wpcd_eigh_noalloc: wpcd_eigh for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * wpcd_eigh, but the eigensolver work-space (FP32 eigenvectors, the per-item
+ * FP64 work-space of 7 n^2 + 40 doubles, cluster lists, Rayleigh quotients,
+ * warm-start samples) is taken from a static device array of 128 MiB that the
+ * library holds on every device it runs on until the process ends, instead of
+ * the batch's own work-space.  The call allocates nothing and creates no
+ * stream or event: every launch goes to `stream` (the reference choice and
+ * the refinement's second stream of wpcd_eigh run in order on it) and the
+ * stage timers do not record it.  A batch whose work-space exceeds 128 MiB
+ * (e.g. more than 53 coupled N_WP = 100 items) returns WPCD_ERR_UNSUPPORTED
+ * with nothing enqueued; WPCD_ERR_DEVICE if the array's device address is
+ * unavailable.  All calls on one device share the array and it keeps the last
+ * call's contents (every kernel writes the parts it reads first): calls that
+ * may overlap on one device -- on different streams, or from several host
+ * threads -- race and must not be issued.                                    */
+int wpcd_eigh_noalloc(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
+                      hipStream_t stream);
+
 /* wpcd_tmatrix (Sec. 3.1, scattering-packet bins; Sec. 3.2, steps 3-5 and the
  * energy average; App. B): for every bin k and channels a, b
  *   T_ab(k) = V_(a,k),(b,k) + sum_m VC_(a,k),m VC_(b,k),m gbar_km,

@@ -40,6 +40,7 @@ EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wp
            "wpcd_graph_nodes", "wpcd_graph_destroy", "wpcd_autotune",
            "wpcd_grid_nodes", "wpcd_batch_create", "wpcd_batch_destroy", "wpcd_batch_layout_get",
            "wpcd_batch_offsets", "wpcd_basis_register", "wpcd_project", "wpcd_project_affine", "wpcd_eigh",
+           "wpcd_eigh_noalloc",
            "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_saclay", "wpcd_server_create", "wpcd_server_destroy",
            "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times",
            "wpcd_jacobi_counts", "wpcd_mi_create", "wpcd_mi_destroy", "wpcd_mi_points", "wpcd_mi_layout_get",
@@ -161,6 +162,7 @@ def lib() -> ctypes.CDLL:
         "wpcd_project": (i32, [vp, dp, i32, dp, vp]),
         "wpcd_project_affine": (i32, [vp, dp, dp, vp]),
         "wpcd_eigh": (i32, [vp, dp, i32, dp, dp, dp, vp]),
+        "wpcd_eigh_noalloc": (i32, [vp, dp, i32, dp, dp, dp, vp]),
         "wpcd_tmatrix": (i32, [vp, dp, dp, dp, i32, dp, dp, vp]),
         "wpcd_observables": (i32, [vp, dp, dp, dp, dp, vp]),
         "wpcd_sigma_tot": (i32, [vp, dp, dp, dp, i32, dp, vp]),
@@ -433,10 +435,12 @@ class Batch:
         _check(lib().wpcd_project_affine(self._h, cp, _ptr(v64, torch.float64, L["v_elems"], "v64"),
                                          _stream(stream)))
 
-    def eigh(self, v64, mode, eval_, evec, status, stream=None):
+    def eigh(self, v64, mode, eval_, evec, status, stream=None, noalloc=False):
+        """wpcd_eigh, or wpcd_eigh_noalloc (static device scratch) when noalloc is set."""
         import torch
         L = self.layout
-        _check(lib().wpcd_eigh(self._h, _ptr(v64, torch.float64, L["v_elems"], "v64"), mode,
+        f = lib().wpcd_eigh_noalloc if noalloc else lib().wpcd_eigh
+        _check(f(self._h, _ptr(v64, torch.float64, L["v_elems"], "v64"), mode,
                  _ptr(eval_, torch.float64, L["eval_elems"], "eval"),
                  _ptr(evec, torch.float64, L["v_elems"], "evec"),
                  _ptr(status, torch.int32, L["n_items"], "status"), _stream(stream)))

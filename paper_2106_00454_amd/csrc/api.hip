@@ -130,6 +130,72 @@ namespace wpcd {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace wpcd
 
+// ------------------------------------------------ static eigensolver scratch
+// The eigensolver work-space of wpcd_eigh_noalloc lives in this file-scope
+// device array (one copy per device, held until the process ends) instead of
+// the batch's own allocation.  In host code `scratch` only names the symbol:
+// its device address on the current device comes from hipGetSymbolAddress,
+// looked up once per device (at the first wpcd_eigh_noalloc call there, with
+// the device current) and kept in g_scratch; kernels only ever receive that
+// address.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// With `dev` current: the device address of `scratch` on it (nullptr if the
+// lookup failed; the next call tries again, and the failure is cleared from
+// HIP's last-error state so that no later launch check reports it).
+unsigned char* scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = e;
+    if (e == hipSuccess && p) g_scratch[dev] = static_cast<unsigned char*>(p);
+    else (void)hipGetLastError();
+  }
+  return g_scratch[dev];
+}
+
+unsigned char* scratch_ptr(int dev) { return scratch_lookup(dev); }
+
+const char* scratch_error(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return "device index beyond the scratch table";
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_err[dev] == hipSuccess ? "scratch address unavailable" : hipGetErrorString(g_scratch_err[dev]);
+}
+
+// Byte offsets of the work-space arrays of a batch inside the scratch, each
+// on a 256-byte boundary.
+struct ScratchPlan {
+  size_t x32, work, cl, lam, sig, total;
+};
+ScratchPlan scratch_plan(const wpcd_batch_s* b) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  ScratchPlan p{};
+  size_t o = 0;
+  p.x32 = o;
+  o = up(o + sizeof(float) * (size_t)b->v_elems);
+  p.work = o;
+  o = up(o + sizeof(double) * (size_t)b->work_doubles);
+  p.cl = o;
+  o = up(o + sizeof(int32_t) * (size_t)b->eval_elems);
+  p.lam = o;
+  o = up(o + sizeof(double) * (size_t)b->eval_elems);
+  p.sig = o;
+  o = up(o + (b->n_pick > 0 ? sizeof(float) * kWarmSig * (size_t)b->n_items : 0));
+  p.total = o;
+  return p;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -811,7 +877,7 @@ static int eigh_run(wpcd_batch b, const double* v64, int mode, double* eval, dou
   return WPCD_OK;
 }
 
-// Argument checks of wpcd_eigh.
+// Argument checks shared by wpcd_eigh and wpcd_eigh_noalloc.
 static int eigh_check(wpcd_batch b, const double* v64, int mode, const double* eval, const double* evec,
                       const int32_t* status, const char* who) {
   if (!b || !v64 || !eval || !evec || !status) return fail(WPCD_ERR_INVALID, "%s: NULL argument", who);
@@ -831,6 +897,25 @@ int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* e
                   true);
 }
 
+int wpcd_eigh_noalloc(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
+                      hipStream_t stream) {
+  const int rc = eigh_check(b, v64, mode, eval, evec, status, "wpcd_eigh_noalloc");
+  if (rc != WPCD_OK) return rc;
+  const ScratchPlan sp = scratch_plan(b);
+  if (sp.total > kScratchBytes)
+    return fail(WPCD_ERR_UNSUPPORTED,
+                "wpcd_eigh_noalloc: the batch needs %zu bytes of eigensolver scratch, the static scratch holds %zu "
+                "(split the batch or use wpcd_eigh)",
+                sp.total, kScratchBytes);
+  WPCD_HIPX(b->ctx, hipSetDevice(b->ctx->device), "hipSetDevice");
+  WPCD_STICKY(b->ctx);
+  unsigned char* base = scratch_ptr(b->ctx->device);
+  if (!base) return fail(WPCD_ERR_DEVICE, "wpcd_eigh_noalloc: %s", scratch_error(b->ctx->device));
+  const EighBufs w{reinterpret_cast<float*>(base + sp.x32), reinterpret_cast<double*>(base + sp.work),
+                   reinterpret_cast<int32_t*>(base + sp.cl), reinterpret_cast<double*>(base + sp.lam),
+                   reinterpret_cast<float*>(base + sp.sig)};
+  return eigh_run(b, v64, mode, eval, evec, status, stream, w, false);
+}
 
 int wpcd_tmatrix(wpcd_batch b, const double* v64, const double* eval, const double* evec, int mode, double* t,
                  int32_t* status, hipStream_t stream) {
