@@ -182,6 +182,17 @@ def _affine_batch_run(args, ctx, specs, coefs, tlab, label):
             "stage_avg_launch_ms": {k: v for k, v in avg.items() if v}, "roofline": roof, "cpu_baseline": None}
 
 
+_TERMS = {}
+
+
+def _term_cache():
+    """One host cache of the unit-strength term matrices for every workload of a run."""
+    from synth import sweep
+    if "cache" not in _TERMS:
+        _TERMS["cache"] = sweep.TermCache()
+    return _TERMS["cache"]
+
+
 def run_sweep(args) -> dict:
     """J <= 6 batched sweep: args.samples x 20 channels, N_WP from {50, 100, 150}, affine bases."""
     import paper_2106_00454_amd as wp
@@ -190,7 +201,7 @@ def run_sweep(args) -> dict:
                      jacobi_start=args.jacobi_start, refine_gemm=args.refine_gemm, refine_steps=args.refine_steps,
                      refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
     t0 = time.perf_counter()
-    _, bases = _register_bases(ctx, sweep.TermCache(), sweep.N_WP_CHOICES, range(len(sweep.CHANNELS)))
+    _, bases = _register_bases(ctx, _term_cache(), sweep.N_WP_CHOICES, range(len(sweep.CHANNELS)))
     log(f"sweep: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
     items = sweep.items(args.samples)
     specs = [(bases[(c, N)].grid, sweep.CHANNELS[c][1], sweep.CHANNELS[c][2], s, bases[(c, N)])
@@ -285,11 +296,11 @@ def run_serve(args) -> dict:
                      refine_close_log10=args.refine_close, refine_rr_steps=args.refine_rr)
     n_wps = (50, 100, 150, 200)
     t0 = time.perf_counter()
-    _, bases = _register_bases(ctx, sweep.TermCache(), n_wps, range(len(sweep.CHANNELS)))
+    _, bases = _register_bases(ctx, _term_cache(), n_wps, range(len(sweep.CHANNELS)))
     log(f"serve: registered {len(bases)} bases in {time.perf_counter() - t0:.1f} s")
     srv = wp.Server(ctx, hbm_budget_bytes=16 << 30, max_inflight=4, max_batch_items=2048)
     rng = np.random.default_rng(np.random.SeedSequence([20210601 + 4, 0]))
-    warm = 5.0
+    warm = args.serve_warmup
     n_req = int((args.duration + warm) * args.rate * 1.2) + 10
     gaps = rng.exponential(1.0 / args.rate, n_req)
     arrivals = np.cumsum(gaps)
@@ -373,6 +384,9 @@ def main() -> int:
     ap.add_argument("--mi-nq", type=int, default=48, help="mi: Gauss nodes of the matrix-inversion solver")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals after warm-up")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="serve: seconds of arrivals before the measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="coupled workload only (by default a short J<=6 sweep and a short serving run follow)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: items are independent and the library has no multi-GPU path "
@@ -533,6 +547,25 @@ def main() -> int:
         cpu = cpu_baseline(args.cpu_seconds)
         log(f"cpu oracle: {cpu['value']:.1f} channel-solves/s on {cpu['cores']} cores")
 
+    extras = None
+    if not args.no_extras:
+        # the other workloads, short: the J <= 6 sweep (256 samples x 20
+        # channels, 3 steps) and the request loop (Poisson arrivals at
+        # 2000/s, 8 s measured after 2 s)
+        torch.cuda.synchronize()
+        ea = argparse.Namespace(**vars(args))
+        ea.samples, ea.steps, ea.warmup = 256, 3, 1
+        sw = run_sweep(ea)
+        ea.rate, ea.duration, ea.serve_warmup = 2000.0, 8.0, 2.0
+        sv = run_serve(ea)
+        extras = {
+            "sweep": {"value": sw["value"], "unit": sw["unit"], "ms_per_step": sw["ms_per_step"],
+                      "items_per_step": sw["config"]["items_per_step"], "jacobi_sweeps_mean": sw["jacobi_sweeps_mean"],
+                      "stages_ms_per_step": sw["stages_ms_per_step"], "workload": sw["config"]["workload"]},
+            "serve": {"latency_ms": sv["latency_ms"], "throughput": sv["throughput"], "requests": sv["steps"],
+                      "batches": sv["server"]["batches"], "workload": sv["config"]["workload"]},
+        }
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -560,6 +593,7 @@ def main() -> int:
         "paper_model_rate": paper_model,
         "roofline_refine_stage": ref_roof,
         "cpu_baseline": cpu,
+        "other_workloads": extras,
     }
     print(json.dumps(out), flush=True)
     return 0

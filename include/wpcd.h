@@ -439,8 +439,9 @@ typedef struct {
 int wpcd_run(wpcd_batch b, const wpcd_path_args* a, int mode, hipStream_t stream);
 
 /* Autotuner of the batch path's schedules: runs wpcd_run(b, a, mode) once
- * per candidate schedule as a warm-up, then `reps` times under HIP events on
- * a private stream, and keeps the fastest in the context's configuration
+ * per candidate schedule as a warm-up, then `reps` times between HIP events
+ * on `stream` (after the work already enqueued there; the call waits for the
+ * last run), and keeps the fastest in the context's configuration
  * (jacobi_block, refine_gemm; later calls on the context use it).  The
  * candidates (WPCD_MIXED) are the LDS Jacobi with two-column blocks
  * (jacobi_block 0) or four-column blocks and one angle per quarter row (5),
@@ -458,7 +459,7 @@ typedef struct {
   double cand_ms[4];                 /* per candidate: {0,0}, {5,0}, {0,1}, {5,1} */
 } wpcd_tune_result;
 int wpcd_autotune(wpcd_batch b, const wpcd_path_args* a, int mode, int reps, const char* cache_path,
-                  wpcd_tune_result* out);
+                  wpcd_tune_result* out, hipStream_t stream);
 
 /* HIP graph of a batch's whole path: wpcd_graph_create captures the launches
  * of wpcd_run(b, a, mode) (including the second stream of wpcd_eigh) into a

@@ -152,7 +152,7 @@ def lib() -> ctypes.CDLL:
         "wpcd_graph_nodes": (i32, [vp, ctypes.POINTER(i64)]),
         "wpcd_graph_destroy": (None, [vp]),
         "wpcd_autotune": (i32, [vp, ctypes.POINTER(_PathArgs), i32, i32, ctypes.c_char_p,
-                                ctypes.POINTER(_TuneResult)]),
+                                ctypes.POINTER(_TuneResult), vp]),
         "wpcd_grid_nodes": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "wpcd_batch_create": (i32, [vp, ctypes.POINTER(_Item), i32, ctypes.POINTER(vp)]),
         "wpcd_batch_destroy": (None, [vp]),
@@ -412,12 +412,13 @@ class Batch:
         _check(lib().wpcd_graph_create(self._h, ctypes.byref(a), mode, ctypes.byref(h)))
         return Graph(h, self)
 
-    def autotune(self, u, bufs, mode, tlab=None, sigma=None, coef=None, reps=2, cache_path=None) -> dict:
+    def autotune(self, u, bufs, mode, tlab=None, sigma=None, coef=None, reps=2, cache_path=None,
+                 stream=None) -> dict:
         """wpcd_autotune: time the candidate schedules on this batch, keep the fastest in the context."""
         a = self.path_args(u, bufs, tlab, sigma, coef)
         r = _TuneResult()
         cp = cache_path.encode() if cache_path else None
-        _check(lib().wpcd_autotune(self._h, ctypes.byref(a), mode, reps, cp, ctypes.byref(r)))
+        _check(lib().wpcd_autotune(self._h, ctypes.byref(a), mode, reps, cp, ctypes.byref(r), _stream(stream)))
         return {"jacobi_block": r.jacobi_block, "refine_gemm": r.refine_gemm, "from_cache": bool(r.from_cache),
                 "best_ms": r.best_ms, "cand_ms": list(r.cand_ms)[:r.n_cand]}
 

@@ -1197,7 +1197,7 @@ static std::string tune_signature(wpcd_batch b, int mode) {
 }
 
 int wpcd_autotune(wpcd_batch b, const wpcd_path_args* a, int mode, int reps, const char* cache_path,
-                  wpcd_tune_result* out) {
+                  wpcd_tune_result* out, hipStream_t stream) {
   if (!b || !a || !out) return fail(WPCD_ERR_INVALID, "wpcd_autotune: NULL argument");
   if (reps < 1 || reps > 100) return fail(WPCD_ERR_INVALID, "wpcd_autotune: reps must be in [1, 100]");
   if (mode != WPCD_MIXED && mode != WPCD_F64) return fail(WPCD_ERR_INVALID, "wpcd_autotune: unknown mode %d", mode);
@@ -1238,12 +1238,13 @@ int wpcd_autotune(wpcd_batch b, const wpcd_path_args* a, int mode, int reps, con
   const int cand[4][2] = {{0, 0}, {5, 0}, {0, 1}, {5, 1}};
   const int n_cand = mode == WPCD_MIXED ? 4 : 1;
   const wpcd_config saved = ctx->cfg;
-  hipStream_t st = nullptr;
+  // the runs go to the caller's stream, in order after the work already
+  // there (they use the batch's work-space)
+  hipStream_t st = stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreate(&e0);
+  hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  int rc = e == hipSuccess ? WPCD_OK : hip_fail(e, "wpcd_autotune: stream and events");
+  int rc = e == hipSuccess ? WPCD_OK : hip_fail(e, "wpcd_autotune: events");
   double best = 0.0;
   int best_i = 0;
   for (int i = 0; i < n_cand && rc == WPCD_OK; ++i) {
@@ -1266,7 +1267,6 @@ int wpcd_autotune(wpcd_batch b, const wpcd_path_args* a, int mode, int reps, con
   }
   if (e1) hipEventDestroy(e1);
   if (e0) hipEventDestroy(e0);
-  if (st) hipStreamDestroy(st);
   ctx->cfg = saved;
   if (rc != WPCD_OK) return rc;
   out->n_cand = n_cand;

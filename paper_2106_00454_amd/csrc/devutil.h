@@ -52,6 +52,38 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wavefront, in every lane (a scalar): row sums
+// by the DPP butterfly above, then row_bcast:15 adds row 0 to row 1 and row
+// 2 to row 3 (rows 1 and 3 written), row_bcast:31 adds rows 0-1 to rows 2-3
+// (rows 2 and 3 written), and lane 63 holds the total, read as a scalar.  No
+// LDS traffic (a __shfl_xor butterfly takes six ds_bpermute round trips).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_f64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffLL), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float wave_total(float v) {
+  v = group_sum<16>(v);
+  v += dpp_rows_f32<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_rows_f32<0x143, 0xC>(v);  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double wave_total(double v) {
+  v = group_sum<16>(v);
+  v += dpp_rows_f64<0x142, 0xA>(v);
+  v += dpp_rows_f64<0x143, 0xC>(v);
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Round-robin ("circle") ordering of a parallel Jacobi sweep over ne (even)
 // indices: position 0 keeps index 0, position q >= 1 holds
 // 1 + ((q - 1 + step) mod (ne - 1)); pairs are positions (i, ne-1-i).  Over

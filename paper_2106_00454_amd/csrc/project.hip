@@ -42,7 +42,7 @@ __device__ __forceinline__ T block_sum_rt(const T* __restrict__ up, int64_t ld, 
   return acc;
 }
 
-// Generic kernel (items not taken by project8_kernel).
+// Generic kernel (items not taken by project8c_kernel).
 // grid: x = blocks over the item's n*n elements, y = item (chunked by the host)
 template <typename T>
 __global__ __launch_bounds__(256) void project_kernel(const ItemDev* __restrict__ items, int item0,
@@ -74,35 +74,24 @@ __global__ __launch_bounds__(256) void project_kernel(const ItemDev* __restrict_
   v64[it.v_off + (int64_t)J * n + I] = v;
 }
 
-// 8 consecutive U elements of one row (two 16-byte loads)
-__device__ __forceinline__ void load8(const float* p, float (&x)[8]) {
-  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
-  x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-  x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
-}
-__device__ __forceinline__ void load8(const double* p, double (&x)[8]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double2 a = reinterpret_cast<const double2*>(p)[q];
-    x[2 * q] = a.x;
-    x[2 * q + 1] = a.y;
-  }
-}
-
 // Tiled projection for ng = 8: one work-group per 32 x 32 tile of V in the
-// upper block triangle (tile row <= tile column).  Thread t produces
-// V[I0 + t/32 + 8r][J0 + t%32], r = 0..3, each from an 8 x 8 block of U
-// (8 rows of 8 consecutive elements: a wavefront reads 32 consecutive
-// 32-byte segments of each of two U rows).  Inside a diagonal tile only
-// I <= J is computed and mirrored, so V is exactly symmetric.  The tile is
-// staged in LDS and written to (I, J) and, transposed, to (J, I) as rows of
-// 32 consecutive doubles.  Taken by items whose U block starts on a 16-byte
-// boundary (the 16-byte loads stay aligned: rows are 8n elements long).
-// grid: x = upper tiles of the largest item, y = item (chunked by the host)
+// upper block triangle (tile row <= tile column); a wavefront reads whole 16-byte-per-lane runs of one U row (64 lanes x 16 B =
+// 1 KB contiguous per load for FP32): lane L of a pass holds E = 16/sizeof(T)
+// consecutive elements of the 8-wide column block J = L / (8/E), forms their
+// weighted partial sum, and the 8/E lanes of a block add theirs with DPP
+// (quad_perm), so every 128-byte line of U is fetched by one load
+// instruction.  Wavefront w takes the tile rows I0 + w, I0 + w + 4, ...; in a
+// diagonal tile the lanes of blocks J < I issue no load.  Same arithmetic
+// order for every element (weights applied per E-run, then per row), V
+// written to (I, J) and (J, I) through the LDS tile.
 template <typename T>
-__global__ __launch_bounds__(256) void project8_kernel(const ItemDev* __restrict__ items, int item0,
-                                                       const GridDev* __restrict__ grids,
-                                                       const T* __restrict__ u, double* __restrict__ v64) {
+__global__ __launch_bounds__(256) void project8c_kernel(const ItemDev* __restrict__ items, int item0,
+                                                        const GridDev* __restrict__ grids,
+                                                        const T* __restrict__ u, double* __restrict__ v64) {
+  constexpr int E = 16 / (int)sizeof(T);  // elements per lane and load
+  constexpr int LB = 8 / E;               // lanes per 8-wide column block
+  constexpr int JW = 64 / LB;             // column blocks per pass
+  constexpr int NP = 32 / JW;             // passes per tile row
   __shared__ double tile[32][33];
   const ItemDev it = items[item0 + blockIdx.y];
   if (it.basis >= 0 || !project_tiled(it, u, (int)sizeof(T))) return;
@@ -119,44 +108,72 @@ __global__ __launch_bounds__(256) void project8_kernel(const ItemDev* __restrict
   const GridDev g = grids[it.grid];
   const int N = it.N;
   const int64_t M = (int64_t)n * 8;
-  const int jj = threadIdx.x & 31, ii0 = threadIdx.x >> 5;
-  const int J = J0 + jj;
-  double wb[8];
-  double sj = 0.0;
-  if (J < n) {
-    const int j = J % N;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int sub = lane % LB;  // which E-run of the block
+  for (int pass = 0; pass < NP; ++pass) {
+    const int jj = pass * JW + lane / LB;  // tile column of this lane
+    const int J = J0 + jj;
+    const bool colok = J < n;
+    const int j = colok ? J % N : 0;
+    T wb[E];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) wb[b] = g.wk[j * 8 + b];
-    sj = g.rsdk[j];
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int ii = ii0 + 8 * r, I = I0 + ii;
-    if (I < n && J < n && (ti < tj || ii <= jj)) {
+    for (int e = 0; e < E; ++e) wb[e] = T(g.wk[j * 8 + sub * E + e]);
+    const double sj = g.rsdk[j];
+    for (int ii = w; ii < 32; ii += 4) {
+      const int I = I0 + ii;
+      if (I >= n) break;  // wavefront-uniform
+      const bool need = colok && (ti < tj || ii <= jj);
       const int i = I % N;
-      const T* up = u + it.u_off + (int64_t)I * 8 * M + (int64_t)J * 8;
+      const T* up = u + it.u_off + (int64_t)I * 8 * M + (int64_t)J * 8 + sub * E;
       T acc = T(0);
 #pragma unroll
       for (int al = 0; al < 8; ++al) {
-        T x[8];
-        load8(up + al * M, x);
+        T x[E];
+        if (need) {
+          if constexpr (E == 4) {
+            const float4 a = *reinterpret_cast<const float4*>(up + al * M);
+            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+          } else {
+            const double2 a = *reinterpret_cast<const double2*>(up + al * M);
+            x[0] = a.x; x[1] = a.y;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) x[e] = T(0);
+        }
         T s = T(0);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) s = fma(T(wb[b]), x[b], s);
+        for (int e = 0; e < E; ++e) s = fma(wb[e], x[e], s);
+        // the block's runs: lanes L and L ^ 1 (and L ^ 2 for E = 2)
+        if constexpr (sizeof(T) == 4) {
+          s += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0xB1, 0xF, 0xF, false));
+        } else {
+          const long long b = __double_as_longlong(s);
+          int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+          int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+          s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+          const long long b2 = __double_as_longlong(s);
+          lo = __builtin_amdgcn_update_dpp(0, (int)(b2 & 0xffffffffLL), 0x4E, 0xF, 0xF, false);
+          hi = __builtin_amdgcn_update_dpp(0, (int)(b2 >> 32), 0x4E, 0xF, 0xF, false);
+          s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        }
         acc = fma(T(g.wk[i * 8 + al]), s, acc);
       }
-      const double v = (double)acc * g.rsdk[i] * sj;
-      tile[ii][jj] = v;
-      if (ti == tj) tile[jj][ii] = v;
+      if (need && sub == 0) {
+        const double v = (double)acc * g.rsdk[i] * sj;
+        tile[ii][jj] = v;
+        if (ti == tj) tile[jj][ii] = v;
+      }
     }
   }
   __syncthreads();
   double* V = v64 + it.v_off;
+  const int cj = threadIdx.x & 31, r0 = threadIdx.x >> 5;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int rr = ii0 + 8 * r;
-    if (I0 + rr < n && J0 + jj < n) V[(int64_t)(I0 + rr) * n + J0 + jj] = tile[rr][jj];
-    if (ti < tj && J0 + rr < n && I0 + jj < n) V[(int64_t)(J0 + rr) * n + I0 + jj] = tile[jj][rr];
+    const int rr = r0 + 8 * r;
+    if (I0 + rr < n && J0 + cj < n) V[(int64_t)(I0 + rr) * n + J0 + cj] = tile[rr][cj];
+    if (ti < tj && J0 + rr < n && I0 + cj < n) V[(int64_t)(J0 + rr) * n + I0 + cj] = tile[cj][rr];
   }
 }
 
@@ -204,13 +221,13 @@ hipError_t launch_project(const ItemDev* items, int n_items, int max_n, const Gr
   for (int i0 = 0; i0 < n_items; i0 += 65535) {
     const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
     if (u_dtype == WPCD_DTYPE_F32) {
-      hipLaunchKernelGGL(project8_kernel<float>, dim3(gt, gy), dim3(bs), 0, s, items, i0, grids,
+      hipLaunchKernelGGL(project8c_kernel<float>, dim3(gt, gy), dim3(bs), 0, s, items, i0, grids,
                          (const float*)u, v64);
       if (generic)
         hipLaunchKernelGGL(project_kernel<float>, dim3(gx, gy), dim3(bs), 0, s, items, i0, grids,
                            (const float*)u, v64);
     } else {
-      hipLaunchKernelGGL(project8_kernel<double>, dim3(gt, gy), dim3(bs), 0, s, items, i0, grids,
+      hipLaunchKernelGGL(project8c_kernel<double>, dim3(gt, gy), dim3(bs), 0, s, items, i0, grids,
                          (const double*)u, v64);
       if (generic)
         hipLaunchKernelGGL(project_kernel<double>, dim3(gx, gy), dim3(bs), 0, s, items, i0, grids,

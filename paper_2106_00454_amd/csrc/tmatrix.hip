@@ -17,6 +17,7 @@
 // The resolvent table is always FP64 (its four x ln x terms cancel strongly for
 // narrow low-energy bins).  The contraction is FP32 with FP32 accumulation in
 // WPCD_MIXED mode and FP64 in WPCD_F64 mode.
+#include "devutil.h"
 #include "internal.h"
 
 namespace wpcd {
@@ -26,13 +27,6 @@ constexpr int kBlock = 256;
 constexpr double kPi = 3.14159265358979323846;
 
 __device__ __forceinline__ double xlogx(double x) { return x == 0.0 ? 0.0 : x * log(fabs(x)); }
-
-template <typename A>
-__device__ __forceinline__ A wave_sum(A v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Items with n <= 64 kMJ: each wavefront takes a contiguous run of bins, so
 // the x ln x terms at the bins' upper boundary E_k carry over as the lower
@@ -95,8 +89,8 @@ __device__ __forceinline__ void tmatrix_bins_carry(const ItemDev& it, const Grid
     }
     for (int p = 0; p < K; ++p)
       for (int q = 0; q < K; ++q) {
-        const A sr = wave_sum(acc_re[p][q]);
-        const A si = wave_sum(acc_im[p][q]);
+        const A sr = wave_total(acc_re[p][q]);
+        const A si = wave_total(acc_im[p][q]);
         if (lane == 0) {
           const double vd = V[(int64_t)(p * N + k) * n + (q * N + k)];
           double* out = t + it.t_off + 2 * ((int64_t)(k * K + p) * K + q);
@@ -212,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void tmatrix_kernel(const ItemDev* __restri
     }
     for (int p = 0; p < K; ++p)
       for (int q = 0; q < K; ++q) {
-        const A sr = wave_sum(acc_re[p][q]);
-        const A si = wave_sum(acc_im[p][q]);
+        const A sr = wave_total(acc_re[p][q]);
+        const A si = wave_total(acc_im[p][q]);
         if (lane == 0) {
           const double vd = V[(int64_t)(p * N + k) * n + (q * N + k)];
           double* out = t + it.t_off + 2 * ((int64_t)(k * K + p) * K + q);

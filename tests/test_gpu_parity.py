@@ -315,3 +315,41 @@ def test_warm_start_picks_the_nearest_cold_item():
         sig_ref = oo.sigma_tot([(0, ref["delta"], None)], kbar, TLAB, k[-1])
         check_item(f"nearest-reference warm start s={s}", item_view(b, host, s), ref, k, wp.MIXED, 0, sig_ref,
                    host["sigma"][s])
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("variant", [0, 5, 6])
+def test_lds_jacobi_variants_on_a_batch(variant):
+    # the LDS Jacobi variants on batches of many items per launch: 24
+    # Yamaguchi n = 50 items (13 blocks of 4: an odd block count) and 12
+    # coupled n = 200 items, all cold; every item against the oracle
+    vctx = wp.Context(0, jacobi_block=variant)
+    ky, kc = configs.grid("yamaguchi_s"), configs.grid("coupled_yukawa")
+    gy, gc = vctx.grid(ky, 8), vctx.grid(kc, 8)
+    xy, _ = ow.gauss_nodes(ky, 8)
+    xc, _ = ow.gauss_nodes(kc, 8)
+    items, mats, refs = [], [], []
+    for s in range(24):
+        lam = configs.yamaguchi_lambda(s)
+        items.append((gy, 1, 0, s))
+        mats.append(potentials.yamaguchi(gy.nodes, gy.nodes, lam, configs.YAMAGUCHI_BETA))
+        refs.append((ky, 0, lambda x, lam=lam: potentials.yamaguchi(x, x, lam, configs.YAMAGUCHI_BETA), xy, 1))
+    for s in range(12):
+        c = configs.yukawa_coefficients(300 + s)
+        f = lambda x, c=c: sum(ci * t for ci, t in zip(c, configs.coupled_yukawa_terms(x)))
+        items.append((gc, 2, 1, 24 + s))
+        mats.append(f(gc.nodes))
+        refs.append((kc, 1, f, xc, 2))
+    b, host = run_items(vctx, items, mats, wp.MIXED)
+    worst = {}
+    for i, (k, J, f, xo, K) in enumerate(refs):
+        ref = ow.solve_channel(k, 8, f(xo), K)
+        it = item_view(b, host, i)
+        dd = dmod180(it["delta"], ref["delta"]).max()
+        worst[K] = max(worst.get(K, 0.0), dd)
+        if dd > DELTA_TOL or i in (0, 23, 24, 35):
+            _, kbar, _ = ow.bins(k)
+            sig_ref = oo.sigma_tot([(J, ref["delta"], ref["mix"])], kbar, TLAB, k[-1])
+            check_item(f"variant={variant} batch item={i} n={K * (k.size - 1)}", it, ref, k, wp.MIXED, J, sig_ref,
+                       host["sigma"][i])
+    print(f"variant={variant}: worst ddelta per channel count {worst}", flush=True)
