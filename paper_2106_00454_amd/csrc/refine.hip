@@ -272,17 +272,20 @@ __device__ __forceinline__ void tile_store(int m0, int c0, int rows, int cols, c
     }
 }
 
-// Newton correction E(k,j) for k != j (R_kj/2 for a close pair), R_jj/2 on the diagonal
+// Newton correction E(k,j) from g = G_kj, s = S_kj and the Rayleigh quotients
+// lk, lj: for k != j the first-order update (R_kj/2 for a close pair), R_jj/2
+// on the diagonal
+__device__ __forceinline__ double newton_e_of(double g, double s, double lk, double lj, bool diag, double closec) {
+  if (diag) return 0.5 * (1.0 - g);
+  const double r = -g;
+  const double d = fabs(lj - lk);
+  const double num = s + lj * r;
+  if (closec * fabs(num) >= d || closec * fabs(s + lk * r) >= d) return 0.5 * r;
+  return num / (lj - lk);
+}
 __device__ __forceinline__ double newton_e(const double* S, const double* G, const double* lam, int n, int k,
                                            int j, double closec) {
-  const double g = G[(int64_t)k * n + j];
-  if (j == k) return 0.5 * (1.0 - g);
-  const double r = -g;
-  const double d = fabs(lam[j] - lam[k]);
-  const double s = S[(int64_t)k * n + j];
-  const double num = s + lam[j] * r;
-  if (closec * fabs(num) >= d || closec * fabs(s + lam[k] * r) >= d) return 0.5 * r;
-  return num / (lam[j] - lam[k]);
+  return newton_e_of(G[(int64_t)k * n + j], S[(int64_t)k * n + j], lam[k], lam[j], j == k, closec);
 }
 
 // Per-item work-space (doubles): P1 | Y | S | G | W5 | W6 | W7, each n*n.
@@ -468,26 +471,59 @@ __global__ __launch_bounds__(64 * kReachRows) void refine_reach_kernel(const Ite
   }
 }
 
+// Exclusive scan of one int per thread over the work-group (thread order),
+// by addition or by maximum (identity -1: the values scanned by maximum are
+// column indices); total receives the whole group's result.  Every thread
+// of the work-group must call it; sh holds kBlock/64 ints.  Ends with a
+// barrier, so sh can be reused at once.
+template <bool MAX>
+__device__ int block_xscan(int v, int* sh, int& total) {
+  constexpr int kIdent = MAX ? -1 : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x = MAX ? max(x, y) : x + y;
+  }
+  if (lane == 63) sh[wave] = x;
+  int ex = __shfl_up(x, 1, 64);
+  if (lane == 0) ex = kIdent;
+  __syncthreads();
+  int pre = kIdent, tot = kIdent;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < wave) pre = MAX ? max(pre, sh[w]) : pre + sh[w];
+    tot = MAX ? max(tot, sh[w]) : tot + sh[w];
+  }
+  __syncthreads();
+  total = tot;
+  return MAX ? max(pre, ex) : pre + ex;
+}
+
 // One-sided Jacobi on the block-diagonal W of a Rayleigh-Ritz batch (Tb
 // columns, leading dimension ldw): its chains are independent, so each chain
 // runs its own round-robin ordering over its own rows only, and all chains
 // advance together -- a sweep has max(ne_c) - 1 barrier-separated steps
 // instead of Tb - 1.  bstart/blen: the batch's chains (batch-local first
-// column, length), nb of them; poff[c] = sum of (len+1)/2 over earlier chains.
-// Same tolerance semantics and return value as onesided_jacobi_lds.
+// column, length), nb of them; poff[c] = sum of (len+1)/2 over earlier chains;
+// pch[i]: the chain of the batch's pair slot i (poff[c] <= i < poff[c + 1]).
+// Same tolerance semantics and return value as onesided_jacobi_lds (the
+// iteration ends after a sweep whose largest rotated cosine is below stop).
 template <int BLOCK, int G, int RMAX>
-__device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short* blen, const short* poff, int nb,
-                            double tol, int max_sweeps, int* rot_flag) {
+__device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short* blen, const short* poff,
+                            const unsigned char* pch, int nb, double tol, double stop, int max_sweeps,
+                            int* rot_flag) {
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
   constexpr int ngrp = BLOCK / G;
   int ne_max = 0;
   for (int c = 0; c < nb; ++c) ne_max = max(ne_max, (blen[c] + 1) & ~1);
   const int ptot = poff[nb];
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    float cmax = 0.0f;  // largest rotated cosine of this lane's pairs in the sweep
     for (int step = 0; step < ne_max - 1; ++step) {
       for (int idx = grp; idx < ptot; idx += ngrp) {
-        int c = 0;
-        while (poff[c + 1] <= idx) ++c;
+        const int c = pch[idx];
         const int m = blen[c], ne = (m + 1) & ~1, b0 = bstart[c];
         if (step >= ne - 1) continue;
         const int pr = idx - poff[c];
@@ -510,10 +546,15 @@ __device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short
         al = group_sum<G>(al);
         be = group_sum<G>(be);
         ga = group_sum<G>(ga);
-        const double nab = sqrt(al * be);
-        if (fabs(ga) > tol * nab) {
-          double cs, sn;
-          hestenes_rotation(al, be, ga, cs, sn);
+        // cosine |w_p.w_q| / (|w_p||w_q|) (a zero column gives NaN: no rotation)
+        const double cosv = fabs(ga) * rsqrt(al * be);
+        if (cosv > tol) {
+          // the rotation of hestenes_rotation written with one division:
+          // with d = be - al, g = 2 ga, zeta = d/g and
+          // t = sign(zeta)/(|zeta| + sqrt(1 + zeta^2)) = sign(d) g/(|d| + sqrt(d^2 + g^2))
+          const double d = be - al, g = 2.0 * ga;
+          const double t = copysign(1.0, d) * g / (fabs(d) + sqrt(fma(d, d, g * g)));
+          const double cs = rsqrt(fma(t, t, 1.0)), sn = cs * t;
 #pragma unroll
           for (int k = 0; k < RMAX; ++k) {
             const int r = lane + k * G;
@@ -522,12 +563,17 @@ __device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short
               wq[r] = sn * xp[k] + cs * xq[k];
             }
           }
-          if (lane == 0) atomicMax(&rot_flag[sweep], __float_as_int((float)(fabs(ga) / nab)));
+          cmax = fmaxf(cmax, (float)cosv);
         }
       }
       __syncthreads();
     }
-    if (__int_as_float(rot_flag[sweep]) < 8.0f * (float)tol) return sweep + 1;
+    // the sweep's largest rotation: wavefront maximum, one LDS atomic per wavefront
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, off, 64));
+    if ((threadIdx.x & 63) == 0 && cmax > 0.0f) atomicMax(&rot_flag[sweep], __float_as_int(cmax));
+    __syncthreads();
+    if (__int_as_float(rot_flag[sweep]) < (float)stop) return sweep + 1;
   }
   return max_sweeps + 1;
 }
@@ -548,7 +594,8 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
                                                               double* __restrict__ lam_pre,
                                                               double* __restrict__ eval, double* work,
                                                               int32_t* __restrict__ cl,
-                                                              int32_t* __restrict__ status, double closec) {
+                                                              int32_t* __restrict__ status, double closec,
+                                                              double jtol, double jstop) {
   constexpr int ldw = kMaxChain | 1;
   // the chain matrix W of a batch shares LDS with the GEMM staging tiles: it
   // is written after the P^T S P product's last chunk and read into Q before
@@ -571,7 +618,11 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   __shared__ short big_start[kMaxBig], big_len[kMaxBig];
   __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
   __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
+  __shared__ short bend[kMaxChain];
+  __shared__ unsigned char pch[kMaxChain];
   __shared__ int s_nch, s_c1, s_Tb, s_fail, s_nbig, s_nbt;
+  __shared__ short seg_start[kMaxN];
+  __shared__ int scan_sh[kBlock / 64];
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
   const WS ws(work, it);
@@ -583,49 +634,77 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     reach[i] = cl[it.e_off + i];
   }
   __syncthreads();
-  // chains = unions of overlapping [p, reach[p]] with at least two columns;
-  // one thread walks the reach list in LDS and overwrites it in place with
-  // each column's chain position (or -1).  The positions stay in LDS: cl is
+  // chains = unions of overlapping [p, reach[p]] (reach[p] >= p) with at
+  // least two columns.  Column i opens a new segment iff every reach[p] with
+  // p < i is below i, so the segments follow from a prefix maximum of reach,
+  // and each chain's position among all chain columns from prefix sums over
+  // the segments (all chains first, then the long ones of the list).  reach
+  // is overwritten in place with each column's chain position (>= 0), -1
+  // (single column) or -2 (a long chain beyond the list: its columns get
+  // I + E below and the item is flagged).  The positions stay in LDS: cl is
   // read-only here, because form_m_kernel reads the same reach list from cl
-  // at the same time on the side stream
-  if (threadIdx.x == 0) {
-    int T = 0, fail = 0, i = 0, nch = 0, nbig = 0;
-    while (i < n) {
-      int j = reach[i], q = i;
-      while (q <= j) {
-        j = reach[q] > j ? reach[q] : j;
-        ++q;
-      }
-      const int m = j - i + 1;
+  // at the same time on the side stream.
+  {
+    const int per = (n + kBlock - 1) / kBlock;
+    const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+    int lm = -1;
+    for (int i = i0; i < i1; ++i) lm = max(lm, reach[i]);
+    int tot;
+    const int pm0 = block_xscan<true>(lm, scan_sh, tot);
+    int pm = pm0, ns = 0;
+    for (int i = i0; i < i1; ++i) {
+      ns += pm < i ? 1 : 0;
+      pm = max(pm, reach[i]);
+    }
+    int nseg;
+    int sid = block_xscan<false>(ns, scan_sh, nseg);
+    pm = pm0;
+    for (int i = i0; i < i1; ++i) {
+      if (pm < i) seg_start[sid++] = (short)i;
+      pm = max(pm, reach[i]);
+    }
+    __syncthreads();
+    // per segment: (chain count << 16 | chain columns), (long count << 16 | long columns)
+    const int sper = (nseg + kBlock - 1) / kBlock;
+    const int s0 = min(nseg, (int)threadIdx.x * sper), s1 = min(nseg, s0 + sper);
+    int vc = 0, vb = 0;
+    for (int g = s0; g < s1; ++g) {
+      const int m = (g + 1 < nseg ? seg_start[g + 1] : n) - seg_start[g];
+      if (m >= 2 && m <= kMaxChain) vc += (1 << 16) + m;
+      if (m > kMaxChain) vb += (1 << 16) + m;
+    }
+    int tc, tb;
+    int xc = block_xscan<false>(vc, scan_sh, tc);
+    int xb = block_xscan<false>(vb, scan_sh, tb);
+    const int tcols = tc & 0xffff;
+    for (int g = s0; g < s1; ++g) {
+      const int i = seg_start[g], m = (g + 1 < nseg ? seg_start[g + 1] : n) - i;
       if (m >= 2 && m <= kMaxChain) {
-        for (int t = 0; t < m; ++t) reach[i + t] = T + t;
-        ch_start[nch] = (short)i;
-        ch_len[nch] = (short)m;
-        ++nch;
-        T += m;
-      } else if (m > kMaxChain && nbig < kMaxBig) {
-        big_start[nbig] = (short)i;
-        big_len[nbig] = (short)m;
-        ++nbig;
+        const int c = xc >> 16, T0 = xc & 0xffff;
+        ch_start[c] = (short)i;
+        ch_len[c] = (short)m;
+        for (int t = 0; t < m; ++t) reach[i + t] = T0 + t;
+        xc += (1 << 16) + m;
+      } else if (m > kMaxChain) {
+        const int b = xb >> 16, T0 = tcols + (xb & 0xffff);
+        if (b < kMaxBig) {
+          big_start[b] = (short)i;
+          big_len[b] = (short)m;
+        }
+        for (int t = 0; t < m; ++t) reach[i + t] = b < kMaxBig ? T0 + t : -2;
+        xb += (1 << 16) + m;
       } else {
-        // a single column, or a long chain beyond the list (-2: its columns
-        // get I + E below, the item is flagged)
-        if (m > kMaxChain) fail = 1;
-        for (int t = 0; t < m; ++t) reach[i + t] = m > kMaxChain ? -2 : -1;
+        reach[i] = -1;
       }
-      i = j + 1;
     }
-    // chain columns are marked >= 0 (their position among all chain columns)
-    for (int b = 0; b < nbig; ++b) {
-      for (int t = 0; t < big_len[b]; ++t) reach[big_start[b] + t] = T + t;
-      T += big_len[b];
+    if (threadIdx.x == 0) {
+      s_nch = tc >> 16;
+      s_nbig = min(tb >> 16, kMaxBig);
+      s_fail = (tb >> 16) > kMaxBig ? 1 : 0;
+      s_c1 = 0;
     }
-    s_nch = nch;
-    s_nbig = nbig;
-    s_fail = fail;
-    s_c1 = 0;
+    __syncthreads();
   }
-  __syncthreads();
   // columns of chains beyond the list: M = I + E (form_m_kernel takes them
   // for chain columns)
   if (s_fail)
@@ -650,7 +729,9 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
         for (int t = 0; t < ch_len[c1]; ++t) {
           cols[Tb + t] = ch_start[c1] + t;
           blk[Tb + t] = Tb;
+          bend[Tb + t] = (short)(Tb + ch_len[c1]);
         }
+        for (int t = 0; t < (ch_len[c1] + 1) / 2; ++t) pch[bt_poff[nbt] + t] = (unsigned char)nbt;
         bt_start[nbt] = (short)Tb;
         bt_len[nbt] = ch_len[c1];
         bt_poff[nbt + 1] = (short)(bt_poff[nbt] + (ch_len[c1] + 1) / 2);
@@ -665,10 +746,29 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     const int Tb = s_Tb;
     if (Tb == 0) break;
-    for (int64_t e = threadIdx.x; e < (int64_t)n * Tb; e += kBlock) {
-      const int k = (int)(e / Tb), t = (int)(e - (int64_t)k * Tb);
-      const int j = cols[t];
-      P[e] = (k == j ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, j, closec);
+    // P: lane t of every wavefront takes column t (Tb <= 64), the wavefronts
+    // interleave the rows
+    // (all loads of a round of 8 rows are issued before their use: S and G
+    // come from HBM)
+    if ((int)(threadIdx.x & 63) < Tb) {
+      const int t = threadIdx.x & 63, j = cols[t];
+      const double lj = lam[j];
+      constexpr int U = 8, KS = kBlock / 64;
+      for (int k0 = threadIdx.x >> 6; k0 < n; k0 += U * KS) {
+        double gv[U], sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = min(k0 + u * KS, n - 1);
+          gv[u] = G[(int64_t)k * n + j];
+          sv[u] = S[(int64_t)k * n + j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * KS;
+          if (k < n)
+            P[(int64_t)k * Tb + t] = (k == j ? 1.0 : 0.0) + newton_e_of(gv[u], sv[u], lam[k], lj, k == j, closec);
+        }
+      }
     }
     __syncthreads();
     for (int tm = 0; tm < nt; ++tm) {
@@ -686,19 +786,27 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     });
     if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
     __syncthreads();
-    // per-chain Gershgorin shift making every diagonal block positive definite
+    // per-chain Gershgorin shift making every diagonal block positive
+    // definite: each column's disc (lower end -> shift, upper end -> nrm,
+    // which is rewritten after the Jacobi), then each chain's first column
+    // takes the extremes over its chain
+    for (int q = threadIdx.x; q < Tb; q += kBlock) {
+      const int e = bend[q];
+      double sacc = 0.0;
+      for (int r = blk[q]; r < e; ++r)
+        if (r != q) sacc += fabs(W[q * ldw + r]);
+      const double d = W[q * ldw + q];
+      shift[q] = d - sacc;
+      nrm[q] = d + sacc;
+    }
+    __syncthreads();
     for (int j = threadIdx.x; j < Tb; j += kBlock) {
       if (blk[j] != j) continue;
-      int e = j + 1;
-      while (e < Tb && blk[e] == j) ++e;
+      const int e = bend[j];
       double lo = DBL_MAX, hi = -DBL_MAX;
       for (int q = j; q < e; ++q) {
-        double s = 0.0;
-        for (int r = j; r < e; ++r)
-          if (r != q) s += fabs(W[q * ldw + r]);
-        const double d = W[q * ldw + q];
-        lo = fmin(lo, d - s);
-        hi = fmax(hi, d + s);
+        lo = fmin(lo, shift[q]);
+        hi = fmax(hi, nrm[q]);
       }
       const double sh = (lo < 0.0 ? -lo : 0.0) + 0.05 * (hi - lo) + DBL_MIN;
       for (int q = j; q < e; ++q) shift[q] = sh;
@@ -706,7 +814,7 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     for (int j = threadIdx.x; j < Tb; j += kBlock) W[j * ldw + j] += shift[j];
     __syncthreads();
-    const int sw = chain_jacobi<kBlock, 8, 8>(W, ldw, bt_start, bt_len, bt_poff, s_nbt, 1e-15, 40, rot_flag);
+    const int sw = chain_jacobi<kBlock, 8, 8>(W, ldw, bt_start, bt_len, bt_poff, pch, s_nbt, jtol, jstop, 40, rot_flag);
     if (sw > 40 && threadIdx.x == 0) s_fail = 1;
     for (int j = threadIdx.x; j < Tb; j += kBlock) {
       double s2 = 0.0;
@@ -1665,9 +1773,14 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
       const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
       hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, sm, items, i0, lam_pre, work, cl, closec);
     }
+    // Rayleigh-Ritz of the chains to FP64 accuracy in the last step; in an
+    // earlier one the Newton columns keep second-order errors of up to
+    // 1/c^2 = 1e-6 and the next step squares what is left, so the chains'
+    // Jacobi stops after a sweep whose largest rotation was below 1e-6 (the
+    // cosines left are then of order 1e-12)
     if (rr)
       hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
-                         status, closec);
+                         status, closec, last ? 1e-15 : 1e-12, last ? 8e-15 : 1e-6);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (rr && side != nullptr) {
