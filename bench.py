@@ -530,6 +530,8 @@ def main() -> int:
     pb, pu, pbuf, psig = pbs[0]
     pb.run(pu, pbuf, wp.F64, tlab, psig)          # warm-up
     torch.cuda.synchronize()
+    for pb, _, _, _ in pbs:
+        pb.jacobi_launches(clear=True)
     tp0 = time.perf_counter()
     for pb, pu, pbuf, psig in pbs:
         t1 = time.perf_counter()
@@ -538,8 +540,12 @@ def main() -> int:
         plain_lat.append((time.perf_counter() - t1) * 1e3)
     plain_wall = time.perf_counter() - tp0
     plain_lat = np.array(plain_lat)
+    jl = [pb.jacobi_launches() for pb, _, _, _ in pbs]
     plain = {"value": P / plain_wall, "unit": "channel-solves/s", "items": P,
-             "p50_ms": float(np.percentile(plain_lat, 50)), "p99_ms": float(np.percentile(plain_lat, 99))}
+             "p50_ms": float(np.percentile(plain_lat, 50)), "p99_ms": float(np.percentile(plain_lat, 99)),
+             "jacobi_launches_per_item": float(np.mean([c["launches"] for c in jl])),
+             "jacobi_sweeps_enqueued_per_item": float(np.mean([c["sweeps"] for c in jl])),
+             "jacobi_sweeps_per_item": float(np.mean([pbuf["eig_status"].cpu().numpy().max() for _, _, pbuf, _ in pbs]))}
     log(f"plain FP64: {plain['value']:.1f} channel-solves/s, p50 {plain['p50_ms']:.2f} ms")
 
     cpu = None
@@ -563,7 +569,10 @@ def main() -> int:
                       "items_per_step": sw["config"]["items_per_step"], "jacobi_sweeps_mean": sw["jacobi_sweeps_mean"],
                       "stages_ms_per_step": sw["stages_ms_per_step"], "workload": sw["config"]["workload"]},
             "serve": {"latency_ms": sv["latency_ms"], "throughput": sv["throughput"], "requests": sv["steps"],
-                      "batches": sv["server"]["batches"], "workload": sv["config"]["workload"]},
+                      "batches": sv["server"]["batches"],
+                      "device_jacobi_launches_per_batch": sv["server"]["jacobi_launches"] / max(1, sv["server"]["batches"]),
+                      "device_jacobi_sweeps_per_batch": sv["server"]["jacobi_sweeps"] / max(1, sv["server"]["batches"]),
+                      "workload": sv["config"]["workload"]},
         }
 
     out = {

@@ -274,7 +274,12 @@ int wpcd_project_affine(wpcd_batch b, const double* coef, double* v64, hipStream
  * of Jacobi sweeps item i used; WPCD_ERR_NOCONV if the sweep cap was reached
  * (results still written), WPCD_ERR_NUMERIC on NaN/Inf.  In WPCD_MIXED mode the
  * FP32 eigenpairs are refined in FP64 (Newton-type update of all eigenpairs
- * with a Rayleigh-Ritz solve inside clusters of close eigenvalues).          */
+ * with a Rayleigh-Ritz solve inside clusters of close eigenvalues).  The work
+ * is enqueued on `stream`; for items in the device-memory Jacobi (every item
+ * in WPCD_F64, those above n = 200 in WPCD_MIXED) the call enqueues the
+ * sweeps a few at a time and waits on events until two sweeps after the
+ * first one that left them all converged (see wpcd_batch_jacobi_launches),
+ * except while the stream is being captured.                                */
 int wpcd_eigh(wpcd_batch b, const double* v64, int mode, double* eval, double* evec, int32_t* status,
               hipStream_t stream);
 
@@ -531,6 +536,9 @@ typedef struct {
 typedef struct {
   int64_t submitted, completed, batches, items, peak_arena_bytes;
   int32_t queued, inflight;
+  int64_t jacobi_launches; /* kernel launches of the device-memory Jacobi (items above n = 200) */
+  int64_t jacobi_sweeps;   /* sweeps it enqueued: all max_sweeps of them per launch sequence (the
+                              worker does not wait on the device; converged items return at once) */
 } wpcd_server_stats;
 
 /* cfg may be NULL for defaults.  Allocates the arena and pinned staging and
@@ -581,6 +589,16 @@ int wpcd_stage_times(wpcd_ctx ctx, double* ms_host, int64_t* launches_host);
  * evaluations (sum over items of sweeps * n^2 multiply-adds).  Synchronises
  * the device.  Used to state the kernel's algorithmic FLOP count.          */
 int wpcd_jacobi_counts(wpcd_ctx ctx, int64_t* counts_host);
+/* Launch counters of the batch's device-memory Jacobi (the FP64 path, and
+ * the mixed path's items above n = 200): counts_host[0] = kernel launches,
+ * [1] = sweeps enqueued, summed over its launch sequences since the batch
+ * was created or the counters were last cleared (clear != 0 clears them after
+ * reading).  Outside stream capture the sweeps are enqueued a few at a time
+ * and stop two sweeps after the first one that left every item of the
+ * sequence converged (the host waits on events for that); a captured
+ * sequence enqueues max_sweeps sweeps, converged items returning at once.
+ * Host counters: no device synchronisation.                                */
+int wpcd_batch_jacobi_launches(wpcd_batch b, int clear, int64_t* counts_host);
 
 #ifdef __cplusplus
 }

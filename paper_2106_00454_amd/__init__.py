@@ -43,8 +43,8 @@ EXPORTS = ("wpcd_create", "wpcd_destroy", "wpcd_last_error", "wpcd_version", "wp
            "wpcd_eigh_noalloc",
            "wpcd_tmatrix", "wpcd_observables", "wpcd_sigma_tot", "wpcd_saclay", "wpcd_server_create", "wpcd_server_destroy",
            "wpcd_submit", "wpcd_poll", "wpcd_server_stats_get", "wpcd_profile_enable", "wpcd_stage_times",
-           "wpcd_jacobi_counts", "wpcd_mi_create", "wpcd_mi_destroy", "wpcd_mi_points", "wpcd_mi_layout_get",
-           "wpcd_mi_solve")
+           "wpcd_jacobi_counts", "wpcd_batch_jacobi_launches", "wpcd_mi_create", "wpcd_mi_destroy",
+           "wpcd_mi_points", "wpcd_mi_layout_get", "wpcd_mi_solve")
 
 STAGES = ("project", "jacobi_f32", "jacobi_f64", "refine", "tmatrix", "observables", "sigma", "warm_prep")
 
@@ -118,7 +118,7 @@ class _TuneResult(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("items", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_int64), ("queued", ctypes.c_int32),
-                ("inflight", ctypes.c_int32)]
+                ("inflight", ctypes.c_int32), ("jacobi_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64)]
 
 
 _lib = None
@@ -175,6 +175,7 @@ def lib() -> ctypes.CDLL:
         "wpcd_profile_enable": (i32, [vp, i32]),
         "wpcd_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "wpcd_jacobi_counts": (i32, [vp, ctypes.POINTER(i64)]),
+        "wpcd_batch_jacobi_launches": (i32, [vp, i32, ctypes.POINTER(i64)]),
         "wpcd_mi_create": (i32, [vp, ctypes.POINTER(_MiItem), i32, i32, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(vp)]),
         "wpcd_mi_destroy": (None, [vp]),
@@ -472,6 +473,12 @@ class Batch:
                                     _ptr(tlab, torch.float64, n_tlab, "tlab"), n_tlab,
                                     _ptr(sigma, torch.float64, L["n_samples"] * n_tlab, "sigma"),
                                     _stream(stream)))
+
+    def jacobi_launches(self, clear: bool = False) -> dict:
+        """Kernel launches and sweeps enqueued by the batch's device-memory Jacobi."""
+        c = (ctypes.c_int64 * 2)()
+        _check(lib().wpcd_batch_jacobi_launches(self._h, int(bool(clear)), c))
+        return {"launches": c[0], "sweeps": c[1]}
 
     def sigma_band(self, delta, mix, tlab, fracs, sigma_lo, sigma_hi, stream=None):
         """wpcd_sigma_band: lowest and highest sigma_tot over interpolation points."""

@@ -376,6 +376,7 @@ void wpcd_batch_destroy(wpcd_batch b) {
   hipFree(b->d_pick);
   hipFree(b->d_sig);
   hipFree(b->d_bases);
+  jac_feedback_destroy(b->jfb);
   delete b;
 }
 
@@ -623,6 +624,7 @@ int wpcd_batch_create(wpcd_ctx ctx, const wpcd_item* items_host, int n_items, wp
     e = hipMemcpy(b->d_cand, cand.data(), sizeof(int32_t) * cand.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !pick.empty())
     e = hipMemcpy(b->d_pick, pick.data(), sizeof(int32_t) * pick.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = jac_feedback_create(b->jfb);
   if (e != hipSuccess) {
     wpcd_batch_destroy(b);
     return hip_fail(e, "wpcd_batch_create");
@@ -825,7 +827,7 @@ static int eigh_run(wpcd_batch b, const double* v64, int mode, double* eval, dou
                                          c.jacobi_block, ref, w.work, cnt, stream);
           return launch_jacobi_global(1, b->d_items, sel, n_sel, b->class_maxn[k], b->d_grids, v64, w.work, evec,
                                       w.x32, eval, status, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32, ref,
-                                      stream);
+                                      &b->jfb, stream);
         });
       };
       // cold starts (each group's reference among them), then the warm starts
@@ -870,7 +872,8 @@ static int eigh_run(wpcd_batch b, const double* v64, int mode, double* eval, dou
                             [&] {
                               return launch_jacobi_global(0, b->d_items, nullptr, b->n_items, b->max_n, b->d_grids,
                                                           v64, w.work, evec, w.x32, eval, status, c.max_sweeps,
-                                                          c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, nullptr, stream);
+                                                          c.jacobi_tol_f64, 8.0 * c.jacobi_tol_f64, nullptr,
+                                                          &b->jfb, stream);
                             }),
               "wpcd_eigh: FP64 Jacobi launch");
   }
@@ -1383,6 +1386,14 @@ int wpcd_jacobi_counts(wpcd_ctx ctx, int64_t* counts_host) {
   unsigned long long h[4];
   WPCD_HIP(hipMemcpy(h, ctx->d_counters, sizeof(h), hipMemcpyDeviceToHost), "wpcd_jacobi_counts: copy");
   for (int i = 0; i < 3; ++i) counts_host[i] = (int64_t)h[i];
+  return WPCD_OK;
+}
+
+int wpcd_batch_jacobi_launches(wpcd_batch b, int clear, int64_t* counts_host) {
+  if (!b || !counts_host) return fail(WPCD_ERR_INVALID, "wpcd_batch_jacobi_launches: NULL argument");
+  counts_host[0] = b->jfb.launches;
+  counts_host[1] = b->jfb.sweeps;
+  if (clear) b->jfb.launches = b->jfb.sweeps = 0;
   return WPCD_OK;
 }
 

@@ -89,6 +89,8 @@ struct wpcd_batch_s {
   int32_t* d_pick = nullptr;
   float* d_sig = nullptr;
   int n_pick = 0;
+  // convergence feedback and launch counters of the device-memory Jacobi
+  wpcd::JacFeedback jfb;
 };
 
 struct wpcd_mi_s {

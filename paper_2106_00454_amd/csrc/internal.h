@@ -100,10 +100,29 @@ hipError_t launch_jacobi_warm_prep(const ItemDev* items, int n_items, const int3
                                    const int32_t* jlist, const int32_t* pick, int n_pick, const int32_t* cand,
                                    float* sig, const GridDev* grids, const double* v64, float* x32, double* work,
                                    hipStream_t s);
+// Convergence feedback of the device-memory Jacobi.  With it (and a stream
+// that is not being captured) the sweeps are enqueued a few at a time: after
+// each sweep a one-work-group kernel writes 1 into flag[sweep] (pinned host
+// memory, written by the device) when every item of the launch has
+// converged, and the host, kJacLookahead sweeps behind the device, stops
+// enqueueing once a flag it has waited for is set.  Without it every sweep
+// up to max_sweeps is enqueued (converged items return at once); a feedback
+// object without flags only counts.  One feedback object serves one launch
+// sequence at a time.
+constexpr int kJacFbEvents = 4;
+constexpr int kJacLookahead = 2;
+struct JacFeedback {
+  int32_t* flag = nullptr;  // 64 ints, hipHostMalloc'd; the device writes them
+  hipEvent_t ev[kJacFbEvents] = {};
+  int64_t launches = 0;     // kernel launches of the device-memory Jacobi since the counters were cleared
+  int64_t sweeps = 0;       // sweeps enqueued since the counters were cleared
+};
+hipError_t jac_feedback_create(JacFeedback& f);
+void jac_feedback_destroy(JacFeedback& f);
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,
-                                const int32_t* ref, hipStream_t s);
+                                const int32_t* ref, JacFeedback* fb, hipStream_t s);
 // FP64 device-memory Jacobi epilogue: Rayleigh quotients x^T H x of the
 // normalised columns it left in the work-space (MFMA product H X), sort by
 // them, write eval and the row-major evec of every item of the batch.

@@ -269,6 +269,24 @@ __global__ __launch_bounds__(BW * G) void gjac_block_kernel(const ItemDev* __res
   if (lane == 0 && rmax > T(0)) atomicMax(&st->rotmax[sweep], __float_as_int((float)rmax));
 }
 
+// flag[sweep] = 1 when every item of the launch has converged after sweep
+// (its largest rotated pair of that sweep below its stopping threshold; an
+// item converged earlier rotated nothing), else 0.  One work-group.
+template <typename T>
+__global__ __launch_bounds__(256) void gjac_flag_kernel(const ItemDev* __restrict__ items,
+                                                        const int32_t* __restrict__ sel, int n_sel, double* work,
+                                                        int sweep, int32_t* flag) {
+  __shared__ int open;
+  if (threadIdx.x == 0) open = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_sel; i += blockDim.x) {
+    const GJacState<T>* st = gjac_state<T>(work, items[sel ? sel[i] : i]);
+    if (!(__int_as_float(st->rotmax[sweep]) < st->stop)) open = 1;  // NaN counts as not converged
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag + sweep, open ? 0 : 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Norms, eigenvalues and sorted outputs.  T = double: eigenvalues as Rayleigh
 // quotients v^T H v / v^T v of v = w/|w| (exact for a diagonal H, free of the
 // shift's rounding), eigenvectors to the caller's FP64 array.  T = float:
@@ -359,11 +377,13 @@ __global__ __launch_bounds__(BLOCK) void gjac_finish_kernel(const ItemDev* __res
     status[item] = bad ? WPCD_ERR_NUMERIC : (sweeps > max_sweeps ? WPCD_ERR_NOCONV : sweeps);
 }
 
-// Host side: init, max_sweeps x (INTRA + round-robin steps), finish.
+// Host side: init, up to max_sweeps x (INTRA + round-robin steps), finish;
+// with feedback the sweeps stop kJacLookahead sweeps after the first one
+// that left every item converged.
 template <typename T, int BW, int G, int RMAX>
 hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max_n, const GridDev* grids,
                     const double* v64, double* work, double* evec, float* x32, double* eval, int32_t* status,
-                    int max_sweeps, T tol, float stop, const int32_t* ref, hipStream_t s) {
+                    int max_sweeps, T tol, float stop, const int32_t* ref, JacFeedback* fb, hipStream_t s) {
   static_assert(BW * G <= 1024, "block size");
   if (max_n > RMAX * G) return hipErrorInvalidValue;
   const size_t lds = (size_t)2 * BW * gjac_ld<G>(max_n) * sizeof(T);
@@ -377,12 +397,43 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
                             (int)lds);
   if (e != hipSuccess) return e;
   const int nb = (max_n + BW - 1) / BW, nbp = (nb + 1) >> 1, nbe = nbp << 1;
+  // feedback only outside stream capture (a captured sequence cannot wait)
+  bool look = fb != nullptr && fb->flag != nullptr;
+  if (look) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    look = cs == hipStreamCaptureStatusNone;
+  }
+  int32_t* dflag = nullptr;
+  if (look) {
+    e = hipHostGetDevicePointer((void**)&dflag, fb->flag, 0);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((gjac_init_kernel<T, 1024>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work,
                      stop, ref, x32);
+  int64_t launches = 2, sweeps = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     hipLaunchKernelGGL(intra, dim3(nb, n_sel), dim3(G, BW), lds, s, items, sel, work, sw, 0, tol);
     for (int step = 0; step < nbe - 1; ++step)
       hipLaunchKernelGGL(cross, dim3(nbp, n_sel), dim3(G, BW), lds, s, items, sel, work, sw, step, tol);
+    launches += nbe;
+    ++sweeps;
+    if (!look) continue;
+    hipLaunchKernelGGL(gjac_flag_kernel<T>, dim3(1), dim3(256), 0, s, items, sel, n_sel, work, sw, dflag);
+    ++launches;
+    e = hipEventRecord(fb->ev[sw % kJacFbEvents], s);
+    if (e != hipSuccess) return e;
+    if (sw >= kJacLookahead) {
+      // the device still has kJacLookahead sweeps queued while the host waits
+      e = hipEventSynchronize(fb->ev[(sw - kJacLookahead) % kJacFbEvents]);
+      if (e != hipSuccess) return e;
+      if (__atomic_load_n(fb->flag + (sw - kJacLookahead), __ATOMIC_ACQUIRE) == 1) break;
+    }
+  }
+  if (fb != nullptr) {
+    fb->launches += launches;
+    fb->sweeps += sweeps;
   }
   hipLaunchKernelGGL((gjac_finish_kernel<T, 1024, 16>), dim3(n_sel), dim3(1024), 0, s, items, sel, grids, v64, work,
                      evec, x32, eval, status, max_sweeps, tol);
@@ -395,10 +446,31 @@ hipError_t gjac_run(const ItemDev* items, const int32_t* sel, int n_sel, int max
 
 }  // namespace
 
+hipError_t jac_feedback_create(JacFeedback& f) {
+  hipError_t e = hipHostMalloc((void**)&f.flag, 64 * sizeof(int32_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    f.flag = nullptr;
+    return e;
+  }
+  for (int i = 0; i < 64; ++i) f.flag[i] = 0;
+  for (int i = 0; i < kJacFbEvents && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&f.ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) jac_feedback_destroy(f);
+  return e;
+}
+
+void jac_feedback_destroy(JacFeedback& f) {
+  for (int i = 0; i < kJacFbEvents; ++i) {
+    if (f.ev[i]) hipEventDestroy(f.ev[i]);
+    f.ev[i] = nullptr;
+  }
+  if (f.flag) hipHostFree(f.flag);
+  f.flag = nullptr;
+}
+
 hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* sel, int n_sel, int max_n,
                                 const GridDev* grids, const double* v64, double* work, double* evec, float* x32,
                                 double* eval, int32_t* status, int max_sweeps, double tol, double stop,
-                                const int32_t* ref, hipStream_t s) {
+                                const int32_t* ref, JacFeedback* fb, hipStream_t s) {
   if (max_n > kMaxN || max_sweeps > 64) return hipErrorInvalidValue;
   if (n_sel == 0) return hipSuccess;
   // block width: two blocks of the largest item fill at most 160 KiB of LDS;
@@ -407,24 +479,24 @@ hipError_t launch_jacobi_global(int mixed, const ItemDev* items, const int32_t* 
     const float t = (float)tol;
     if (max_n <= 304)
       return gjac_run<float, 64, 16, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                         max_sweeps, t, (float)stop, ref, s);
+                                         max_sweeps, t, (float)stop, ref, fb, s);
     if (max_n <= 608)
       return gjac_run<float, 32, 32, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                         max_sweeps, t, (float)stop, ref, s);
+                                         max_sweeps, t, (float)stop, ref, fb, s);
     return gjac_run<float, 16, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, t, (float)stop, ref, s);
+                                       max_sweeps, t, (float)stop, ref, fb, s);
   }
   if (max_n <= 144)
     return gjac_run<double, 64, 16, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, tol, (float)stop, nullptr, s);
+                                       max_sweeps, tol, (float)stop, nullptr, fb, s);
   if (max_n <= 288)
     return gjac_run<double, 32, 32, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                       max_sweeps, tol, (float)stop, nullptr, s);
+                                       max_sweeps, tol, (float)stop, nullptr, fb, s);
   if (max_n <= 576)
     return gjac_run<double, 16, 64, 9>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status,
-                                        max_sweeps, tol, (float)stop, nullptr, s);
+                                        max_sweeps, tol, (float)stop, nullptr, fb, s);
   return gjac_run<double, 8, 64, 19>(items, sel, n_sel, max_n, grids, v64, work, evec, x32, eval, status, max_sweeps,
-                                     tol, (float)stop, nullptr, s);
+                                     tol, (float)stop, nullptr, fb, s);
 }
 
 }  // namespace wpcd

@@ -84,6 +84,8 @@ __global__ __launch_bounds__(256) void project_kernel(const ItemDev* __restrict_
 // diagonal tile the lanes of blocks J < I issue no load.  Same arithmetic
 // order for every element (weights applied per E-run, then per row), V
 // written to (I, J) and (J, I) through the LDS tile.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T>
 __global__ __launch_bounds__(256) void project8c_kernel(const ItemDev* __restrict__ items, int item0,
                                                         const GridDev* __restrict__ grids,
@@ -119,50 +121,66 @@ __global__ __launch_bounds__(256) void project8c_kernel(const ItemDev* __restric
 #pragma unroll
     for (int e = 0; e < E; ++e) wb[e] = T(g.wk[j * 8 + sub * E + e]);
     const double sj = g.rsdk[j];
-    for (int ii = w; ii < 32; ii += 4) {
-      const int I = I0 + ii;
-      if (I >= n) break;  // wavefront-uniform
-      const bool need = colok && (ti < tj || ii <= jj);
-      const int i = I % N;
-      const T* up = u + it.u_off + (int64_t)I * 8 * M + (int64_t)J * 8 + sub * E;
-      T acc = T(0);
+    // two tile rows (ii, ii + 4) per round: the 16 loads of a lane are all
+    // issued before their sums; U is read once, so the loads do not keep it
+    // in the caches (non-temporal)
+    for (int i2 = w; i2 < 32; i2 += 8) {
+      T x[2][8][E];
+      bool needr[2];
 #pragma unroll
-      for (int al = 0; al < 8; ++al) {
-        T x[E];
-        if (need) {
-          if constexpr (E == 4) {
-            const float4 a = *reinterpret_cast<const float4*>(up + al * M);
-            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+      for (int h = 0; h < 2; ++h) {
+        const int ii = i2 + 4 * h, I = I0 + ii;
+        needr[h] = I < n && colok && (ti < tj || ii <= jj);
+        const T* up = u + it.u_off + (int64_t)(I < n ? I : 0) * 8 * M + (int64_t)J * 8 + sub * E;
+#pragma unroll
+        for (int al = 0; al < 8; ++al) {
+          if (needr[h]) {
+            if constexpr (E == 4) {
+              const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(up + al * M));
+#pragma unroll
+              for (int e = 0; e < 4; ++e) x[h][al][e] = a[e];
+            } else {
+              const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(up + al * M));
+              x[h][al][0] = a[0];
+              x[h][al][1] = a[1];
+            }
           } else {
-            const double2 a = *reinterpret_cast<const double2*>(up + al * M);
-            x[0] = a.x; x[1] = a.y;
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[h][al][e] = T(0);
           }
-        } else {
-#pragma unroll
-          for (int e = 0; e < E; ++e) x[e] = T(0);
         }
-        T s = T(0);
-#pragma unroll
-        for (int e = 0; e < E; ++e) s = fma(wb[e], x[e], s);
-        // the block's runs: lanes L and L ^ 1 (and L ^ 2 for E = 2)
-        if constexpr (sizeof(T) == 4) {
-          s += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0xB1, 0xF, 0xF, false));
-        } else {
-          const long long b = __double_as_longlong(s);
-          int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
-          int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
-          s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-          const long long b2 = __double_as_longlong(s);
-          lo = __builtin_amdgcn_update_dpp(0, (int)(b2 & 0xffffffffLL), 0x4E, 0xF, 0xF, false);
-          hi = __builtin_amdgcn_update_dpp(0, (int)(b2 >> 32), 0x4E, 0xF, 0xF, false);
-          s += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-        }
-        acc = fma(T(g.wk[i * 8 + al]), s, acc);
       }
-      if (need && sub == 0) {
-        const double v = (double)acc * g.rsdk[i] * sj;
-        tile[ii][jj] = v;
-        if (ti == tj) tile[jj][ii] = v;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int ii = i2 + 4 * h, I = I0 + ii;
+        if (I >= n) break;  // wavefront-uniform
+        const int i = I % N;
+        T acc = T(0);
+#pragma unroll
+        for (int al = 0; al < 8; ++al) {
+          T sm = T(0);
+#pragma unroll
+          for (int e = 0; e < E; ++e) sm = fma(wb[e], x[h][al][e], sm);
+          // the block's runs: lanes L and L ^ 1 (and L ^ 2 for E = 2)
+          if constexpr (sizeof(T) == 4) {
+            sm += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sm), 0xB1, 0xF, 0xF, false));
+          } else {
+            const long long b = __double_as_longlong(sm);
+            int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+            int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+            sm += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+            const long long b2 = __double_as_longlong(sm);
+            lo = __builtin_amdgcn_update_dpp(0, (int)(b2 & 0xffffffffLL), 0x4E, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, (int)(b2 >> 32), 0x4E, 0xF, 0xF, false);
+            sm += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+          }
+          acc = fma(T(g.wk[i * 8 + al]), sm, acc);
+        }
+        if (needr[h] && sub == 0) {
+          const double v = (double)acc * g.rsdk[i] * sj;
+          tile[ii][jj] = v;
+          if (ti == tj) tile[jj][ii] = v;
+        }
       }
     }
   }

@@ -375,102 +375,6 @@ __global__ __launch_bounds__(T64::NT) void gemm_sg_kernel(const ItemDev* __restr
 
 // Columns of M = I + E outside chains, row-major into W6 (the chain kernel
 // writes the chain columns, possibly at the same time on another stream).
-// cl holds reach[p] from refine_reach_kernel: column j lies in a chain iff
-// some interval [p, reach[p]] with reach[p] > p covers it, i.e. reach[j] > j
-// or max_{p<j} reach[p] >= j.  lam_pre holds the Rayleigh quotients E was
-// built from.  Grid: x = blocks of 64 rows, y = item.
-__global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restrict__ items, int item0,
-                                                        const double* __restrict__ lam_pre, double* work,
-                                                        const int32_t* __restrict__ cl, double closec) {
-  __shared__ double lam[kMaxN];
-  __shared__ int rch[kMaxN];
-  __shared__ unsigned char inch[kMaxN];
-  const ItemDev it = items[item0 + blockIdx.y];
-  const int n = it.n;
-  const int r0 = blockIdx.x * kTM;
-  if (r0 >= n) return;
-  const WS ws(work, it);
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    lam[i] = lam_pre[it.e_off + i];
-    rch[i] = cl ? cl[it.e_off + i] : i;  // no reach list: no chains
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int cover = -1;
-    for (int j = 0; j < n; ++j) {
-      inch[j] = (rch[j] > j || cover >= j) ? 1 : 0;
-      cover = rch[j] > cover ? rch[j] : cover;
-    }
-  }
-  __syncthreads();
-  const int r1 = min(n, r0 + kTM);
-  for (int64_t e = threadIdx.x; e < (int64_t)(r1 - r0) * n; e += kBlock) {
-    const int k = r0 + (int)(e / n), j = (int)(e % n);
-    if (!inch[j]) ws.W6[(int64_t)k * n + j] = (k == j ? 1.0 : 0.0) + newton_e(ws.S, ws.G, lam, n, k, j, closec);
-  }
-}
-
-// X' = X M with M in W6 (form_m_kernel and refine_chain_kernel).
-template <typename XT>
-__global__ __launch_bounds__(T64::NT, 3) void gemm_xm_kernel(const ItemDev* __restrict__ items, int n_items,
-                                                         const XT* xin, int xin_ws, double* evec, int xout_ws,
-                                                         double* work, int tiles) {
-  WPCD_LDS_TILES(T64, 1);
-  int item, tile;
-  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
-  const ItemDev it = items[item];
-  const int n = it.n;
-  const int nt = (n + T64::TM - 1) / T64::TM;
-  if (tile >= nt * nt) return;
-  const int tm = tile / nt, tc = tile % nt;
-  const WS ws(work, it);
-  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
-  double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
-  d4 acc[2][2];
-  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, row_view(X, n, n), col_view<double>(ws.W6, n, n), acc);
-  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
-}
-
-// ------------------------------------------------------------ reach kernel
-// Rayleigh quotients lam_i = S_ii/G_ii (-> lam_pre) and, per row p, the
-// largest q > p with (p, q) close (else p; -> cl, read back by the chain
-// kernel).  Grid: x = blocks of kReachRows rows, y = item; one wavefront per
-// row with lanes over q (coalesced reads of rows of S and G).
-constexpr int kReachRows = 16;
-__global__ __launch_bounds__(64 * kReachRows) void refine_reach_kernel(const ItemDev* __restrict__ items,
-                                                                       double* __restrict__ lam_pre,
-                                                                       const double* work, int32_t* __restrict__ cl,
-                                                                       double closec) {
-  __shared__ double lam[kMaxN];
-  const ItemDev it = items[blockIdx.y];
-  const int n = it.n;
-  if ((int)blockIdx.x * kReachRows >= n) return;
-  const WS ws(const_cast<double*>(work), it);
-  const double* S = ws.S;
-  const double* G = ws.G;
-  for (int i = threadIdx.x; i < n; i += 64 * kReachRows) lam[i] = S[(int64_t)i * n + i] / G[(int64_t)i * n + i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, p = blockIdx.x * kReachRows + (threadIdx.x >> 6);
-  if (p >= n) return;
-  const double lp = lam[p];
-  int rq = p;
-  for (int q = p + 1 + lane; q < n; q += 64) {
-    const double r = -G[(int64_t)p * n + q];
-    const double sv = S[(int64_t)p * n + q];
-    const double d = fabs(lam[q] - lp);
-    if (closec * fabs(sv + lam[q] * r) >= d || closec * fabs(sv + lp * r) >= d) rq = q;
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const int o = __shfl_xor(rq, off, 64);
-    rq = o > rq ? o : rq;
-  }
-  if (lane == 0) {
-    cl[it.e_off + p] = rq;
-    lam_pre[it.e_off + p] = lp;
-  }
-}
-
 // Exclusive scan of one int per thread over the work-group (thread order),
 // by addition or by maximum (identity -1: the values scanned by maximum are
 // column indices); total receives the whole group's result.  Every thread
@@ -499,6 +403,169 @@ __device__ int block_xscan(int v, int* sh, int& total) {
   __syncthreads();
   total = tot;
   return MAX ? max(pre, ex) : pre + ex;
+}
+
+// cl holds reach[p] from refine_reach_kernel: column j lies in a chain iff
+// some interval [p, reach[p]] with reach[p] > p covers it, i.e. reach[j] > j
+// or max_{p<j} reach[p] >= j (a prefix maximum over the work-group).  lam_pre
+// holds the Rayleigh quotients E was built from.  One-dimensional grid over
+// (item, block of 64 rows) from xcd_item_tile; each wavefront takes rows
+// r0 + w + 4 u and issues the loads of kFormRows of them before using any.
+constexpr int kFormRows = 4;
+__global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restrict__ items,
+                                                        const double* __restrict__ lam_pre, double* work,
+                                                        const int32_t* __restrict__ cl, double closec, int tiles,
+                                                        int n_items) {
+  __shared__ double lam[kMaxN];
+  __shared__ int rch[kMaxN];
+  __shared__ unsigned char inch[kMaxN];
+  __shared__ int scan_sh[kBlock / 64];
+  int item, tile;
+  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
+  const ItemDev it = items[item];
+  const int n = it.n;
+  const int r0 = tile * kTM;
+  if (r0 >= n) return;
+  const WS ws(work, it);
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    lam[i] = lam_pre[it.e_off + i];
+    rch[i] = cl ? cl[it.e_off + i] : i;  // no reach list: no chains
+  }
+  __syncthreads();
+  {
+    const int per = (n + kBlock - 1) / kBlock;
+    const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+    int lm = -1;
+    for (int i = i0; i < i1; ++i) lm = max(lm, rch[i]);
+    int tot;
+    int cover = block_xscan<true>(lm, scan_sh, tot);
+    for (int j = i0; j < i1; ++j) {
+      inch[j] = (rch[j] > j || cover >= j) ? 1 : 0;
+      cover = max(cover, rch[j]);
+    }
+  }
+  __syncthreads();
+  const int r1 = min(n, r0 + kTM);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int KS = kBlock / 64;
+  for (int kb = r0 + w; kb < r1; kb += KS * kFormRows)
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      const int j = j0 + lane;
+      double gv[kFormRows], sv[kFormRows];
+#pragma unroll
+      for (int u = 0; u < kFormRows; ++u) {
+        const int k = kb + KS * u;
+        const int64_t e = (k < r1 && j < n) ? (int64_t)k * n + j : 0;
+        gv[u] = ws.G[e];
+        sv[u] = ws.S[e];
+      }
+      if (j >= n || inch[j]) continue;
+      const double lj = lam[j];
+#pragma unroll
+      for (int u = 0; u < kFormRows; ++u) {
+        const int k = kb + KS * u;
+        if (k < r1)
+          ws.W6[(int64_t)k * n + j] = (k == j ? 1.0 : 0.0) + newton_e_of(gv[u], sv[u], lam[k], lj, k == j, closec);
+      }
+    }
+}
+
+// X' = X M with M in W6 (form_m_kernel and refine_chain_kernel).
+template <typename XT>
+__global__ __launch_bounds__(T64::NT, 3) void gemm_xm_kernel(const ItemDev* __restrict__ items, int n_items,
+                                                         const XT* xin, int xin_ws, double* evec, int xout_ws,
+                                                         double* work, int tiles) {
+  WPCD_LDS_TILES(T64, 1);
+  int item, tile;
+  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
+  const ItemDev it = items[item];
+  const int n = it.n;
+  const int nt = (n + T64::TM - 1) / T64::TM;
+  if (tile >= nt * nt) return;
+  const int tm = tile / nt, tc = tile % nt;
+  const WS ws(work, it);
+  const XT* X = xin_ws ? reinterpret_cast<const XT*>(ws.P1) : (xin + it.v_off);
+  double* Xo = xout_ws ? ws.P1 : (evec + it.v_off);
+  d4 acc[2][2];
+  gemm_tile<T64>(As, Bs, tm * T64::TM, tc * T64::TM, n, n, n, row_view(X, n, n), col_view<double>(ws.W6, n, n), acc);
+  tile_store<T64>(tm * T64::TM, tc * T64::TM, n, n, acc, [&](int r, int c, double v) { Xo[(int64_t)r * n + c] = v; });
+}
+
+// ------------------------------------------------------------ reach kernel
+// Rayleigh quotients lam_i = S_ii/G_ii (-> lam_pre) and, per row p, the
+// largest q > p with (p, q) close (else p; -> cl, read back by the chain
+// kernel).  One-dimensional grid over (item, block of kReachRows rows) from
+// xcd_item_tile, so the blocks of an item share one L2 for the diagonal
+// reads; 8 wavefronts, each taking kReachRPW rows (p = block row + wave + 8 r)
+// with lanes over q (coalesced reads of rows of S and G); the loads of all
+// its rows for kReachChunks chunks of 64 columns are issued before any is
+// tested (S and G come from HBM).
+constexpr int kReachWaves = 8;
+constexpr int kReachRPW = 4;
+constexpr int kReachRows = kReachWaves * kReachRPW;
+constexpr int kReachChunks = 4;
+__global__ __launch_bounds__(64 * kReachWaves) void refine_reach_kernel(const ItemDev* __restrict__ items,
+                                                                        double* __restrict__ lam_pre,
+                                                                        const double* work, int32_t* __restrict__ cl,
+                                                                        double closec, int tiles, int n_items) {
+  __shared__ double lam[kMaxN];
+  int item, tile;
+  if (!xcd_item_tile(tiles, n_items, item, tile)) return;
+  const ItemDev it = items[item];
+  const int n = it.n;
+  if (tile * kReachRows >= n) return;
+  const WS ws(const_cast<double*>(work), it);
+  const double* S = ws.S;
+  const double* G = ws.G;
+  for (int i = threadIdx.x; i < n; i += 64 * kReachWaves) lam[i] = S[(int64_t)i * n + i] / G[(int64_t)i * n + i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p0 = tile * kReachRows + w;
+  int rq[kReachRPW];
+#pragma unroll
+  for (int r = 0; r < kReachRPW; ++r) rq[r] = p0 + kReachWaves * r;
+  // chunk c of row p covers q = p + 1 + 64 c + lane
+  const int nchunk = (n - p0 - 1 + 63) / 64;  // of the wave's first (longest) row
+  for (int c0 = 0; c0 < nchunk; c0 += kReachChunks) {
+    double sv[kReachRPW][kReachChunks], gv[kReachRPW][kReachChunks];
+#pragma unroll
+    for (int r = 0; r < kReachRPW; ++r)
+#pragma unroll
+      for (int c = 0; c < kReachChunks; ++c) {
+        const int p = p0 + kReachWaves * r, q = p + 1 + 64 * (c0 + c) + lane;
+        const int64_t e = (p < n && q < n) ? (int64_t)p * n + q : 0;
+        sv[r][c] = S[e];
+        gv[r][c] = G[e];
+      }
+#pragma unroll
+    for (int r = 0; r < kReachRPW; ++r) {
+      const int p = p0 + kReachWaves * r;
+      if (p >= n) continue;
+      const double lp = lam[p];
+#pragma unroll
+      for (int c = 0; c < kReachChunks; ++c) {
+        const int q = p + 1 + 64 * (c0 + c) + lane;
+        if (q >= n) continue;
+        const double rr = -gv[r][c];
+        const double d = fabs(lam[q] - lp);
+        if (closec * fabs(sv[r][c] + lam[q] * rr) >= d || closec * fabs(sv[r][c] + lp * rr) >= d) rq[r] = q;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kReachRPW; ++r) {
+    int v = rq[r];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int o = __shfl_xor(v, off, 64);
+      v = o > v ? o : v;
+    }
+    const int p = p0 + kReachWaves * r;
+    if (lane == 0 && p < n) {
+      cl[it.e_off + p] = v;
+      lam_pre[it.e_off + p] = lam[p];
+    }
+  }
 }
 
 // One-sided Jacobi on the block-diagonal W of a Rayleigh-Ritz batch (Tb
@@ -1745,20 +1812,17 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    for (int i0 = 0; i0 < n_items; i0 += 65535) {
-      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
-      hipLaunchKernelGGL(refine_reach_kernel, dim3((max_n + kReachRows - 1) / kReachRows, gy),
-                         dim3(64 * kReachRows), 0, s, items + i0, lam_pre, work, cl, closec);
+    {
+      const int rt = (max_n + kReachRows - 1) / kReachRows;
+      hipLaunchKernelGGL(refine_reach_kernel, dim3(xcd_grid(rt, n_items)), dim3(64 * kReachWaves), 0, s, items,
+                         lam_pre, work, cl, closec, rt, n_items);
     }
     // a step without Rayleigh-Ritz: M = I + E for every column (close pairs
     // take R_ij/2), no chain kernel
     const bool rr = rr_steps <= 0 || st >= steps - rr_steps;
     if (!rr) {
-      for (int i0 = 0; i0 < n_items; i0 += 65535) {
-        const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
-        hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, s, items, i0, lam_pre, work,
-                           (const int32_t*)nullptr, closec);
-      }
+      hipLaunchKernelGGL(form_m_kernel, dim3(xcd_grid(nt, n_items)), dim3(kBlock), 0, s, items, lam_pre, work,
+                         (const int32_t*)nullptr, closec, nt, n_items);
     }
     // M: the columns outside chains (form_m, streaming S and G) on the side
     // stream while the chain kernel (latency-bound) writes the chain columns
@@ -1769,10 +1833,9 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
       if (err != hipSuccess) return err;
       sm = side;
     }
-    for (int i0 = 0; rr && i0 < n_items; i0 += 65535) {
-      const unsigned gy = (unsigned)((n_items - i0) < 65535 ? (n_items - i0) : 65535);
-      hipLaunchKernelGGL(form_m_kernel, dim3(nt, gy), dim3(kBlock), 0, sm, items, i0, lam_pre, work, cl, closec);
-    }
+    if (rr)
+      hipLaunchKernelGGL(form_m_kernel, dim3(xcd_grid(nt, n_items)), dim3(kBlock), 0, sm, items, lam_pre, work, cl,
+                         closec, nt, n_items);
     // Rayleigh-Ritz of the chains to FP64 accuracy in the last step; in an
     // earlier one the Newton columns keep second-order errors of up to
     // 1/c^2 = 1e-6 and the next step squares what is left, so the chains'

@@ -79,6 +79,10 @@ struct Slot {
   std::vector<int64_t> d_off, m_off;  // per item delta / mix offsets
   int64_t n_items = 0;
   hipError_t err = hipSuccess;
+  // launch counters of the device-memory Jacobi of this slot's batches; no
+  // pinned flags, so every sweep is enqueued: the worker thread must not wait
+  // on the device while requests arrive
+  wpcd::JacFeedback jfb;
 };
 
 }  // namespace
@@ -299,7 +303,7 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
     else
       e = launch_jacobi_global(1, d_items, d_cls + class_ptr[k], n_sel, class_maxn[k], d_grids, d_v64, d_work,
                                d_evec, d_x32, d_eval, d_est, c.max_sweeps, c.jacobi_tol_f32, c.jacobi_stop_f32,
-                               nullptr, s.stream);
+                               nullptr, &s.jfb, s.stream);
   }
   if (e == hipSuccess)
     e = launch_refine(d_items, n, min_n, max_n, d_grids, d_v64, d_x32, d_evec, d_eval, d_lam, d_work, d_cl, d_est,
@@ -321,6 +325,9 @@ bool wpcd_server_s::launch(Slot& s, std::vector<Req*>& take) {
     std::lock_guard<std::mutex> lk(mu);
     st.batches++;
     st.items += ni;
+    st.jacobi_launches += s.jfb.launches;
+    st.jacobi_sweeps += s.jfb.sweeps;
+    s.jfb.launches = s.jfb.sweeps = 0;
     st.peak_arena_bytes = std::max<int64_t>(st.peak_arena_bytes, (int64_t)arena.used());
   }
   return true;
