@@ -645,72 +645,20 @@ __device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short
   return max_sweeps + 1;
 }
 
-// ------------------------------------------------------------ chain kernel
-// One work-group per item: Rayleigh quotients, close pairs and chains, and the
-// Rayleigh-Ritz rotation of every chain.  Chains of up to kMaxChain columns
-// are processed in batches of whole chains with at most kMaxChain columns;
-// for a batch with columns cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb),
-// P^T S P -> LDS (kept block-diagonal, one block per chain), one-sided Jacobi,
-// Q -> LDS, and P Q -> the batch's columns of M (n x n, W6).
-// Longer chains (dense parts of the spectrum of large items) are solved one
-// at a time in device memory: P -> W5, S P -> Y, P^T S P -> W7 (m x m), FP64
-// one-sided Jacobi on W7, the sorted Q -> Y, P Q -> their columns of M.
-// Writes the refined eigenvalues to eval (the Rayleigh quotients outside
-// chains); the other columns of M come from form_m_kernel.
-__global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* __restrict__ items,
-                                                              double* __restrict__ lam_pre,
-                                                              double* __restrict__ eval, double* work,
-                                                              int32_t* __restrict__ cl,
-                                                              int32_t* __restrict__ status, double closec,
-                                                              double jtol, double jstop) {
-  constexpr int ldw = kMaxChain | 1;
-  // the chain matrix W of a batch shares LDS with the GEMM staging tiles: it
-  // is written after the P^T S P product's last chunk and read into Q before
-  // the P Q product stages its first one
-  constexpr int kSmem = (2 * kTileLds > kMaxChain * ldw) ? 2 * kTileLds : kMaxChain * ldw;
-  __shared__ double smem[kSmem];
-  double* const As = smem;
-  double* const Bs = smem + kTileLds;
-  double* const W = smem;
-  __shared__ double lam[kMaxN];
-  __shared__ int reach[kMaxN];
-  __shared__ short ch_start[kMaxN / 2];
-  __shared__ short ch_len[kMaxN / 2];
-  __shared__ double shift[kMaxChain];
-  __shared__ double nrm[kMaxChain];
-  __shared__ int cols[kMaxChain];
-  __shared__ int blk[kMaxChain];
-  __shared__ int rot_flag[64];
-  __shared__ double bnrm[kMaxN];
-  __shared__ short big_start[kMaxBig], big_len[kMaxBig];
-  __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
-  __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
-  __shared__ short bend[kMaxChain];
-  __shared__ unsigned char pch[kMaxChain];
-  __shared__ int s_nch, s_c1, s_Tb, s_fail, s_nbig, s_nbt;
-  __shared__ short seg_start[kMaxN];
-  __shared__ int scan_sh[kBlock / 64];
-  const ItemDev it = items[blockIdx.x];
-  const int n = it.n;
-  const WS ws(work, it);
-  const double* S = ws.S;
-  const double* G = ws.G;
-  // Rayleigh quotients and reach[p] from refine_reach_kernel (reach staged in cl)
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    lam[i] = lam_pre[it.e_off + i];
-    reach[i] = cl[it.e_off + i];
-  }
-  __syncthreads();
-  // chains = unions of overlapping [p, reach[p]] (reach[p] >= p) with at
-  // least two columns.  Column i opens a new segment iff every reach[p] with
-  // p < i is below i, so the segments follow from a prefix maximum of reach,
-  // and each chain's position among all chain columns from prefix sums over
-  // the segments (all chains first, then the long ones of the list).  reach
-  // is overwritten in place with each column's chain position (>= 0), -1
-  // (single column) or -2 (a long chain beyond the list: its columns get
-  // I + E below and the item is flagged).  The positions stay in LDS: cl is
-  // read-only here, because form_m_kernel reads the same reach list from cl
-  // at the same time on the side stream.
+// Chains of one item from its reach list in LDS: the unions of overlapping
+// [p, reach[p]] (reach[p] >= p) with at least two columns.  Column i opens a
+// new segment iff every reach[p] with p < i is below i, so the segments
+// follow from a prefix maximum of reach, and each chain's position among all
+// chain columns from prefix sums over the segments (all chains of up to
+// kMaxChain columns first, then the long ones of the list).  reach is
+// overwritten in place with each column's chain position (>= 0), -1 (single
+// column) or -2 (a long chain beyond the list of kMaxBig: its columns get
+// I + E and the item is flagged).  Chains of up to kMaxChain columns go to
+// ch_start/ch_len (*s_nch of them), long ones to big_start/big_len
+// (*s_nbig); *s_fail is set when the list overflows.  Every thread of the
+// work-group calls it; it ends with a barrier.
+__device__ void find_chains(int n, int* reach, short* seg_start, int* scan_sh, short* ch_start, short* ch_len,
+                            short* big_start, short* big_len, int* s_nch, int* s_nbig, int* s_fail) {
   {
     const int per = (n + kBlock - 1) / kBlock;
     const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
@@ -765,12 +713,81 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       }
     }
     if (threadIdx.x == 0) {
-      s_nch = tc >> 16;
-      s_nbig = min(tb >> 16, kMaxBig);
-      s_fail = (tb >> 16) > kMaxBig ? 1 : 0;
-      s_c1 = 0;
+      *s_nch = tc >> 16;
+      *s_nbig = min(tb >> 16, kMaxBig);
+      *s_fail = (tb >> 16) > kMaxBig ? 1 : 0;
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ chain kernel
+// One work-group per item: Rayleigh quotients, close pairs and chains, and the
+// Rayleigh-Ritz rotation of every chain.  Chains of up to kMaxChain columns
+// are processed in batches of whole chains with at most kMaxChain columns;
+// for a batch with columns cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb),
+// P^T S P -> LDS (kept block-diagonal, one block per chain), one-sided Jacobi,
+// Q -> LDS, and P Q -> the batch's columns of M (n x n, W6).
+// Longer chains (dense parts of the spectrum of large items) are left to
+// refine_bigchain_kernel, their list at the end of the item's W7.  Writes the
+// refined eigenvalues of its chains to eval, the Rayleigh quotients outside
+// chains; the other columns of M come from form_m_kernel.
+__global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* __restrict__ items,
+                                                              double* __restrict__ lam_pre,
+                                                              double* __restrict__ eval, double* work,
+                                                              int32_t* __restrict__ cl,
+                                                              int32_t* __restrict__ status, double closec,
+                                                              double jtol, double jstop) {
+  constexpr int ldw = kMaxChain | 1;
+  // the chain matrix W of a batch shares LDS with the GEMM staging tiles: it
+  // is written after the P^T S P product's last chunk and read into Q before
+  // the P Q product stages its first one
+  constexpr int kSmem = (2 * kTileLds > kMaxChain * ldw) ? 2 * kTileLds : kMaxChain * ldw;
+  __shared__ double smem[kSmem];
+  double* const As = smem;
+  double* const Bs = smem + kTileLds;
+  double* const W = smem;
+  __shared__ double lam[kMaxN];
+  __shared__ int reach[kMaxN];
+  __shared__ short ch_start[kMaxN / 2];
+  __shared__ short ch_len[kMaxN / 2];
+  __shared__ double shift[kMaxChain];
+  __shared__ double nrm[kMaxChain];
+  __shared__ int cols[kMaxChain];
+  __shared__ int blk[kMaxChain];
+  __shared__ int rot_flag[64];
+  __shared__ short big_start[kMaxBig], big_len[kMaxBig];
+  __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
+  __shared__ short bend[kMaxChain];
+  __shared__ unsigned char pch[kMaxChain];
+  __shared__ int s_nch, s_c1, s_Tb, s_fail, s_nbig, s_nbt;
+  __shared__ short seg_start[kMaxN];
+  __shared__ int scan_sh[kBlock / 64];
+  const ItemDev it = items[blockIdx.x];
+  const int n = it.n;
+  const WS ws(work, it);
+  const double* S = ws.S;
+  const double* G = ws.G;
+  // Rayleigh quotients and reach[p] from refine_reach_kernel (reach staged in cl)
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    lam[i] = lam_pre[it.e_off + i];
+    reach[i] = cl[it.e_off + i];
+  }
+  __syncthreads();
+  // the chain positions stay in LDS: cl is read-only here, because
+  // form_m_kernel reads the same reach list from cl at the same time on the
+  // side stream
+  find_chains(n, reach, seg_start, scan_sh, ch_start, ch_len, big_start, big_len, &s_nch, &s_nbig, &s_fail);
+  if (threadIdx.x == 0) s_c1 = 0;
+  // the long chains go to refine_bigchain_kernel: their list at the end of
+  // the item's W7 (the batches below use its first kMaxChain^2 doubles)
+  if (threadIdx.x == 0 && n > kMaxChain) {
+    double* tail = ws.W7 + (int64_t)n * n - (2 * kMaxBig + 1);
+    tail[0] = (double)s_nbig;
+    for (int b = 0; b < s_nbig; ++b) {
+      tail[1 + 2 * b] = (double)big_start[b];
+      tail[2 + 2 * b] = (double)big_len[b];
+    }
   }
   // columns of chains beyond the list: M = I + E (form_m_kernel takes them
   // for chain columns)
@@ -909,15 +926,76 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     }
     __syncthreads();
   }
-  // long chains, one at a time in device memory
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* C = ws.W7;
+  for (int i = threadIdx.x; i < n; i += kBlock)
+    if (reach[i] < 0) eval[it.e_off + i] = lam[i];
+  if (threadIdx.x == 0 && s_fail && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
+}
+
+// ------------------------------------------------------------ long chains
+// The chains of more than kMaxChain columns that refine_chain_kernel listed
+// at the end of the item's W7, one work-group per item, after it on the same
+// stream (items with none return at once).  Per chain i0 .. i0+m-1:
+// P = (I + E)[:, chain] -> W5 (n x m), S P -> Y, C = P^T S P, a Gershgorin
+// shift, the FP64 one-sided Jacobi on C, the sorted Q -> Y, P Q -> the
+// chain's columns of M, eigenvalues |w_j| - shift.  C stays in LDS for
+// m <= kBigLdsN (the chain Jacobi: 32 lane groups of 8, all pairs of a
+// round-robin step at once), above in W7 (16-lane-group Jacobi in device
+// memory).  Dynamic LDS: the GEMM staging tiles, overlaid by C, then the
+// column norms.
+constexpr int kBigLdsN = 126;
+constexpr int kBigLd = kBigLdsN | 1;
+constexpr int kBigDynDoubles = (2 * kTileLds > kBigLdsN * kBigLd ? 2 * kTileLds : kBigLdsN * kBigLd) + kMaxN;
+__global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* __restrict__ items,
+                                                                 const double* __restrict__ lam_pre,
+                                                                 double* __restrict__ eval, double* work,
+                                                                 int32_t* __restrict__ status, double closec,
+                                                                 double jtol, double jstop) {
+  extern __shared__ double bsm[];
+  double* const As = bsm;
+  double* const Bs = bsm + kTileLds;
+  double* const bnrm = bsm + (kBigDynDoubles - kMaxN);
+  __shared__ double lam[kMaxN];
+  __shared__ short big_start[kMaxBig], big_len[kMaxBig];
+  __shared__ int rot_flag[64];
+  __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
+  __shared__ short bt_start[1], bt_len[1], bt_poff[2];
+  __shared__ unsigned char pch[kMaxChain];
+  __shared__ int s_nbig, s_fail;
+  const ItemDev it = items[blockIdx.x];
+  const int n = it.n;
+  if (n <= kMaxChain) return;  // no chain can be longer than kMaxChain
+  const WS ws(work, it);
+  if (threadIdx.x == 0) {
+    const double* tail = ws.W7 + (int64_t)n * n - (2 * kMaxBig + 1);
+    s_nbig = (int)tail[0];
+    for (int b = 0; b < s_nbig; ++b) {
+      big_start[b] = (short)tail[1 + 2 * b];
+      big_len[b] = (short)tail[2 + 2 * b];
+    }
+    s_fail = 0;
+  }
+  __syncthreads();
+  if (s_nbig == 0) return;
+  for (int i = threadIdx.x; i < n; i += kBlock) lam[i] = lam_pre[it.e_off + i];
+  if (threadIdx.x < kMaxChain) pch[threadIdx.x] = 0;
+  __syncthreads();
+  const double* S = ws.S;
+  const double* G = ws.G;
+  double* P = ws.W5;
+  double* SP = ws.Y;
   double* Q = ws.Y;
+  double* M = ws.W6;
+  const int nt = (n + kTM - 1) / kTM;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  d4 acc[2][2];
   for (int b = 0; b < s_nbig; ++b) {
     const int i0 = big_start[b], m = big_len[b];
     const int mt = (m + kTM - 1) / kTM;
-    for (int64_t e = threadIdx.x; e < (int64_t)n * m; e += kBlock) {
-      const int k = (int)(e / m), t = (int)(e - (int64_t)k * m);
+    const bool in_lds = m <= kBigLdsN;
+    double* const C = in_lds ? bsm : ws.W7;  // C overlays the staging tiles in LDS
+    const int ld = in_lds ? kBigLd : m;
+    for (int e = threadIdx.x; e < n * m; e += kBlock) {
+      const int k = e / m, t = e - k * m;
       P[e] = (k == i0 + t ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, i0 + t, closec);
     }
     __syncthreads();
@@ -927,25 +1005,45 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
         tile_store<T64>(tm * kTM, tc * kTM, n, m, acc, [&](int r, int cc, double v) { SP[(int64_t)r * m + cc] = v; });
       }
     __syncthreads();
-    for (int tm = 0; tm < mt; ++tm)
-      for (int tc = tm; tc < mt; ++tc) {
-        gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc);
-        tile_store<T64>(tm * kTM, tc * kTM, m, m, acc, [&](int r, int cc, double v) {
-          if (r > cc) return;  // symmetric: one writer per pair
-          C[(int64_t)cc * m + r] = v;
-          C[(int64_t)r * m + cc] = v;
-        });
+    auto put_c = [&](int r, int cc, double v) {
+      if (r > cc) return;  // symmetric: one writer per pair
+      C[cc * ld + r] = v;
+      C[r * ld + cc] = v;
+    };
+    if (in_lds) {
+      // m <= 126: the upper tiles (0,0), (0,1), (1,1) of C are all computed
+      // before any is stored, since C overlays the staging tiles
+      static_assert(kBigLdsN <= 2 * kTM, "at most 2 x 2 tiles of C in LDS");
+      d4 acc3[3][2][2];
+      gemm_tile<T64>(As, Bs, 0, 0, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[0]);
+      if (mt > 1) {
+        gemm_tile<T64>(As, Bs, 0, kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[1]);
+        gemm_tile<T64>(As, Bs, kTM, kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[2]);
       }
+      __syncthreads();
+      tile_store<T64>(0, 0, m, m, acc3[0], put_c);
+      if (mt > 1) {
+        tile_store<T64>(0, kTM, m, m, acc3[1], put_c);
+        tile_store<T64>(kTM, kTM, m, m, acc3[2], put_c);
+      }
+    } else {
+      for (int tm = 0; tm < mt; ++tm)
+        for (int tc = tm; tc < mt; ++tc) {
+          gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m),
+                         acc);
+          tile_store<T64>(tm * kTM, tc * kTM, m, m, acc, put_c);
+        }
+    }
     if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
     __syncthreads();
     // Gershgorin shift: one wavefront per column
     double lo = DBL_MAX, hi = -DBL_MAX;
     for (int q = wave; q < m; q += kBlock / 64) {
       double sacc = 0.0;
-      for (int r = lane; r < m; r += 64) sacc += (r == q) ? 0.0 : fabs(C[(int64_t)q * m + r]);
+      for (int r = lane; r < m; r += 64) sacc += (r == q) ? 0.0 : fabs(C[q * ld + r]);
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
-      const double d = C[(int64_t)q * m + q];
+      const double d = C[q * ld + q];
       lo = fmin(lo, d - sacc);
       hi = fmax(hi, d + sacc);
     }
@@ -962,13 +1060,21 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     }
     const double sh = (lo < 0.0 ? -lo : 0.0) + 0.05 * (hi - lo) + DBL_MIN;
     __syncthreads();
-    for (int j = threadIdx.x; j < m; j += kBlock) C[(int64_t)j * m + j] += sh;
+    for (int j = threadIdx.x; j < m; j += kBlock) C[j * ld + j] += sh;
+    if (threadIdx.x == 0) {
+      bt_start[0] = 0;
+      bt_len[0] = (short)m;
+      bt_poff[0] = 0;
+      bt_poff[1] = (short)((m + 1) / 2);
+    }
     __syncthreads();
-    const int swb = onesided_jacobi_lds<double, kBlock, 64, kBigRows>(C, m, m, 1e-15, 8e-15, 40, rot_flag);
+    const int swb = in_lds ? chain_jacobi<kBlock, 8, 16>(C, ld, bt_start, bt_len, bt_poff, pch, 1, jtol, jstop, 40,
+                                                          rot_flag)
+                           : onesided_jacobi_lds<double, kBlock, 64, kBigRows>(C, m, m, 1e-15, 8e-15, 40, rot_flag);
     if (swb > 40 && threadIdx.x == 0) s_fail = 1;
     for (int j = wave; j < m; j += kBlock / 64) {
       double s2 = 0.0;
-      for (int r = lane; r < m; r += 64) s2 = fma(C[(int64_t)j * m + r], C[(int64_t)j * m + r], s2);
+      for (int r = lane; r < m; r += 64) s2 = fma(C[j * ld + r], C[j * ld + r], s2);
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) s2 += __shfl_xor(s2, off, 64);
       if (lane == 0) bnrm[j] = sqrt(s2);
@@ -981,7 +1087,7 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       for (int q = lane; q < m; q += 64) cnt += (bnrm[q] < lj || (bnrm[q] == lj && q < j)) ? 1 : 0;
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-      for (int r = lane; r < m; r += 64) Q[(int64_t)r * m + cnt] = C[(int64_t)j * m + r] / lj;
+      for (int r = lane; r < m; r += 64) Q[(int64_t)r * m + cnt] = C[j * ld + r] / lj;
       if (lane == 0) eval[it.e_off + i0 + cnt] = lj - sh;
     }
     __syncthreads();
@@ -989,12 +1095,10 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       for (int tc = 0; tc < mt; ++tc) {
         gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, n, m, m, row_view<double>(P, n, m), col_view<double>(Q, m, m), acc);
         tile_store<T64>(tm * kTM, tc * kTM, n, m, acc,
-                   [&](int r, int cc, double v) { M[(int64_t)r * n + i0 + cc] = v; });
+                        [&](int r, int cc, double v) { M[(int64_t)r * n + i0 + cc] = v; });
       }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += kBlock)
-    if (reach[i] < 0) eval[it.e_off + i] = lam[i];
   if (threadIdx.x == 0 && s_fail && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
@@ -1841,9 +1945,18 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
     // 1/c^2 = 1e-6 and the next step squares what is left, so the chains'
     // Jacobi stops after a sweep whose largest rotation was below 1e-6 (the
     // cosines left are then of order 1e-12)
-    if (rr)
+    if (rr) {
       hipLaunchKernelGGL(refine_chain_kernel, dim3(n_items), dim3(kBlock), 0, s, items, lam_pre, eval, work, cl,
                          status, closec, last ? 1e-15 : 1e-12, last ? 8e-15 : 1e-6);
+      if (max_n > kMaxChain) {
+        err = hipFuncSetAttribute(reinterpret_cast<const void*>(refine_bigchain_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kBigDynDoubles * sizeof(double)));
+        if (err != hipSuccess) return err;
+      }
+      if (max_n > kMaxChain)
+        hipLaunchKernelGGL(refine_bigchain_kernel, dim3(n_items), dim3(kBlock), kBigDynDoubles * sizeof(double), s,
+                           items, lam_pre, eval, work, status, closec, last ? 1e-15 : 1e-12, last ? 8e-15 : 1e-6);
+    }
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (rr && side != nullptr) {
