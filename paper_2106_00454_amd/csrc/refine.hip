@@ -738,7 +738,10 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
                                                               int32_t* __restrict__ cl,
                                                               int32_t* __restrict__ status, double closec,
                                                               double jtol, double jstop) {
-  constexpr int ldw = kMaxChain | 1;
+  // column stride of the chain matrix: 72 = 8 (mod 32) doubles, so the
+  // columns read by the four 8-lane groups of a half wavefront in one step
+  // (consecutive chain positions) start 16 banks apart and cover all 64 banks
+  constexpr int ldw = 72;
   // the chain matrix W of a batch shares LDS with the GEMM staging tiles: it
   // is written after the P^T S P product's last chunk and read into Q before
   // the P Q product stages its first one
@@ -931,6 +934,81 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   if (threadIdx.x == 0 && s_fail && status[blockIdx.x] >= 0) status[blockIdx.x] = WPCD_ERR_NUMERIC;
 }
 
+// One-sided Jacobi on one chain matrix C (m <= G * RMAX columns of m rows,
+// leading dimension ld, in LDS) for the long-chain kernel: lane groups of G
+// take one column pair each, BLOCK / G >= m / 2 groups cover every pair of a
+// round-robin step at once, and the squared column norms are tracked through
+// the rotations (|w_p'|^2 = |w_p|^2 - t g, |w_q'|^2 = |w_q|^2 + t g with
+// g = w_p.w_q) from exact values at the start of every sweep, so a pair
+// costs one dot product.  nrm: m doubles of LDS.  Same skip test (cosine
+// above tol), stopping rule (a sweep whose largest rotated cosine is below
+// stop) and return value as chain_jacobi; ends with a barrier.  Rows m ..
+// G * RMAX - 1 of every column must be zero (ld >= G * RMAX): the loads and
+// stores then need no guard, and rotations keep those rows zero.
+template <int BLOCK, int G, int RMAX>
+__device__ __forceinline__ int long_chain_jacobi(double* C, int ld, int m, double* nrm, double tol, double stop,
+                                                 int max_sweeps, int* rot_flag) {
+  static_assert(BLOCK / G * 2 >= G * RMAX, "one round per step");
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+  const int ne = (m + 1) & ~1;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int j = grp; j < m; j += BLOCK / G) {
+      const double* c = C + j * ld + lane;
+      double s2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) s2 = fma(c[k * G], c[k * G], s2);
+      s2 = group_sum<G>(s2);
+      if (lane == 0) nrm[j] = s2;
+    }
+    __syncthreads();
+    float cmax = 0.0f;
+    for (int step = 0; step < ne - 1; ++step) {
+      const int p = rr_index(grp, step, ne), q = rr_index(ne - 1 - grp, step, ne);
+      if (grp < ne / 2 && p < m && q < m) {
+        double* wp = C + p * ld + lane;
+        double* wq = C + q * ld + lane;
+        double xp[RMAX], xq[RMAX];
+        double ga0 = 0.0, ga1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) {
+          xp[k] = wp[k * G];
+          xq[k] = wq[k * G];
+          if (k & 1)
+            ga1 = fma(xp[k], xq[k], ga1);
+          else
+            ga0 = fma(xp[k], xq[k], ga0);
+        }
+        const double ga = group_sum<G>(ga0 + ga1);
+        const double al = nrm[p], be = nrm[q];
+        const double cosv = fabs(ga) * rsqrt(al * be);
+        if (cosv > tol) {
+          // hestenes_rotation with one division (as in chain_jacobi)
+          const double d = be - al, g = 2.0 * ga;
+          const double t = copysign(1.0, d) * g / (fabs(d) + sqrt(fma(d, d, g * g)));
+          const double cs = rsqrt(fma(t, t, 1.0)), sn = cs * t;
+#pragma unroll
+          for (int k = 0; k < RMAX; ++k) {
+            wp[k * G] = cs * xp[k] - sn * xq[k];
+            wq[k * G] = sn * xp[k] + cs * xq[k];
+          }
+          if (lane == 0) {
+            nrm[p] = al - t * ga;
+            nrm[q] = be + t * ga;
+          }
+          cmax = fmaxf(cmax, (float)cosv);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, off, 64));
+    if ((threadIdx.x & 63) == 0 && cmax > 0.0f) atomicMax(&rot_flag[sweep], __float_as_int(cmax));
+    __syncthreads();
+    if (__int_as_float(rot_flag[sweep]) < (float)stop) return sweep + 1;
+  }
+  return max_sweeps + 1;
+}
+
 // ------------------------------------------------------------ long chains
 // The chains of more than kMaxChain columns that refine_chain_kernel listed
 // at the end of the item's W7, one work-group per item, after it on the same
@@ -938,12 +1016,15 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
 // P = (I + E)[:, chain] -> W5 (n x m), S P -> Y, C = P^T S P, a Gershgorin
 // shift, the FP64 one-sided Jacobi on C, the sorted Q -> Y, P Q -> the
 // chain's columns of M, eigenvalues |w_j| - shift.  C stays in LDS for
-// m <= kBigLdsN (the chain Jacobi: 32 lane groups of 8, all pairs of a
-// round-robin step at once), above in W7 (16-lane-group Jacobi in device
-// memory).  Dynamic LDS: the GEMM staging tiles, overlaid by C, then the
+// m <= kBigLdsN (long_chain_jacobi: 64 lane groups of 4, all pairs of a
+// round-robin step at once, tracked norms), above in W7 (Jacobi with lane
+// groups of 64 in device memory).  Dynamic LDS: the GEMM staging tiles, overlaid by C, then the
 // column norms.
 constexpr int kBigLdsN = 126;
-constexpr int kBigLd = kBigLdsN | 1;
+// column stride of C in LDS: 132 = 4 (mod 32) doubles, so the columns read by
+// the eight 4-lane groups of a half wavefront in one round-robin step
+// (consecutive indices) start 8 banks apart and cover all 64 banks
+constexpr int kBigLd = 132;
 constexpr int kBigDynDoubles = (2 * kTileLds > kBigLdsN * kBigLd ? 2 * kTileLds : kBigLdsN * kBigLd) + kMaxN;
 __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* __restrict__ items,
                                                                  const double* __restrict__ lam_pre,
@@ -958,8 +1039,6 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
   __shared__ short big_start[kMaxBig], big_len[kMaxBig];
   __shared__ int rot_flag[64];
   __shared__ double s_lo[kBlock / 64], s_hi[kBlock / 64];
-  __shared__ short bt_start[1], bt_len[1], bt_poff[2];
-  __shared__ unsigned char pch[kMaxChain];
   __shared__ int s_nbig, s_fail;
   const ItemDev it = items[blockIdx.x];
   const int n = it.n;
@@ -977,7 +1056,6 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
   __syncthreads();
   if (s_nbig == 0) return;
   for (int i = threadIdx.x; i < n; i += kBlock) lam[i] = lam_pre[it.e_off + i];
-  if (threadIdx.x < kMaxChain) pch[threadIdx.x] = 0;
   __syncthreads();
   const double* S = ws.S;
   const double* G = ws.G;
@@ -1013,7 +1091,7 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
     if (in_lds) {
       // m <= 126: the upper tiles (0,0), (0,1), (1,1) of C are all computed
       // before any is stored, since C overlays the staging tiles
-      static_assert(kBigLdsN <= 2 * kTM, "at most 2 x 2 tiles of C in LDS");
+      static_assert(kBigLdsN <= 2 * kTM && kBigLd >= 128, "at most 2 x 2 tiles of C in LDS, 128 rows per column");
       d4 acc3[3][2][2];
       gemm_tile<T64>(As, Bs, 0, 0, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[0]);
       if (mt > 1) {
@@ -1061,15 +1139,15 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
     const double sh = (lo < 0.0 ? -lo : 0.0) + 0.05 * (hi - lo) + DBL_MIN;
     __syncthreads();
     for (int j = threadIdx.x; j < m; j += kBlock) C[j * ld + j] += sh;
-    if (threadIdx.x == 0) {
-      bt_start[0] = 0;
-      bt_len[0] = (short)m;
-      bt_poff[0] = 0;
-      bt_poff[1] = (short)((m + 1) / 2);
-    }
+    // in LDS: rows m .. 127 of every column zero (long_chain_jacobi reads and
+    // writes them unguarded)
+    if (in_lds)
+      for (int e = threadIdx.x; e < m * (128 - m); e += kBlock) {
+        const int j = e / (128 - m);
+        bsm[j * kBigLd + m + (e - j * (128 - m))] = 0.0;
+      }
     __syncthreads();
-    const int swb = in_lds ? chain_jacobi<kBlock, 8, 16>(C, ld, bt_start, bt_len, bt_poff, pch, 1, jtol, jstop, 40,
-                                                          rot_flag)
+    const int swb = in_lds ? long_chain_jacobi<kBlock, 4, 32>(bsm, kBigLd, m, bnrm, jtol, jstop, 40, rot_flag)
                            : onesided_jacobi_lds<double, kBlock, 64, kBigRows>(C, m, m, 1e-15, 8e-15, 40, rot_flag);
     if (swb > 40 && threadIdx.x == 0) s_fail = 1;
     for (int j = wave; j < m; j += kBlock / 64) {
