@@ -454,7 +454,7 @@ def main() -> int:
     # column-pair visit, per applied rotation 4n (scaled rotations, the
     # default variant: one FMA per element and column) or 6n (plain
     # rotations), 2 per norm multiply-add
-    rot_flops = 4.0 if args.jacobi_block in (0, 5, 6) else 6.0   # scaled rotations: one FMA per element and column
+    rot_flops = 4.0 if args.jacobi_block in (0, 5, 6, 7) else 6.0   # scaled rotations: one FMA per element and column
     jac_flops = (2.0 * n * counts["pair_visits"] + rot_flops * n * counts["rotations"]
                  + 2.0 * counts["norm_madds"])          # over all timed launches
     jac_ms, jac_launches = stages["jacobi_f32"]          # HIP events around each launch

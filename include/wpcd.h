@@ -109,7 +109,11 @@ typedef struct {
                             group and 4 rotations per block step, with tracked
                             column norms (one dot product per pair) and scaled
                             rotations (each column carries a scale factor, one
-                            FMA per element and column); 1 one column pair per
+                            FMA per element and column), in a recursive
+                            halving ordering in which each lane group keeps
+                            one of its blocks in registers for a whole level
+                            (one block per step through LDS); 7 the same in
+                            the round-robin ordering; 1 one column pair per
                             lane group, three dot products per pair; 2 one pair
                             per group, tracked norms; 3 as 0 with plain
                             rotations; 4 blocks of 4 columns, tracked norms;
@@ -117,7 +121,7 @@ typedef struct {
                             16-lane row per block pair whose four quarters
                             compute the four angles of a stage at once; 6
                             the same with blocks of 2 columns (two halves);
-                            other values: WPCD_ERR_INVALID                   */
+                            7 see above; other values: WPCD_ERR_INVALID      */
   int32_t refine_close_log10; /* closeness constant of the first refinement
                             step, c = 10^k (pairs whose first-order update
                             would exceed 1/c are solved by Rayleigh-Ritz);

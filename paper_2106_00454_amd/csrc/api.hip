@@ -225,8 +225,8 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
     return fail(WPCD_ERR_INVALID, "jacobi_stop_f32 must be in (0, 1) (0 = default)");
   if (c.jacobi_start != 0 && c.jacobi_start != 1) return fail(WPCD_ERR_INVALID, "jacobi_start must be 0 or 1");
   if (c.refine_gemm != 0 && c.refine_gemm != 1) return fail(WPCD_ERR_INVALID, "refine_gemm must be 0 or 1");
-  if (c.jacobi_block < 0 || c.jacobi_block > 6)
-    return fail(WPCD_ERR_INVALID, "jacobi_block must be in [0, 6]");
+  if (c.jacobi_block < 0 || c.jacobi_block > 7)
+    return fail(WPCD_ERR_INVALID, "jacobi_block must be in [0, 7]");
   if (c.refine_close_log10 < 1 || c.refine_close_log10 > 8)
     return fail(WPCD_ERR_INVALID, "refine_close_log10 must be in [1, 8] (0 = default)");
   if (c.refine_rr_steps < 0 || c.refine_rr_steps > 4)

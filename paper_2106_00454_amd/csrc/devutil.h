@@ -609,6 +609,141 @@ __device__ int onesided_jacobi_blocked_scaled(float* W, int n, int ld, float tol
   return sweeps;
 }
 
+// The iteration of onesided_jacobi_blocked_scaled (blocks of 2 columns,
+// scaled rotations, tracked norms; same skip test, stopping rule and return
+// value) in an ordering that lets every lane group keep one block in
+// registers: a sweep splits the blocks [0, nb) into A = [0, h) and
+// B = [h, nb), h = floor(nb / 2); for ceil(nb / 2) steps group g pairs A[g]
+// with B[(g + s) mod |B|], so A[g] stays in its registers and only the B
+// blocks pass through LDS; then A and B are split the same way, side by side
+// (the left child keeps the first floor(|A| / 2) groups of its parent, the
+// right child the next floor(|B| / 2)), down to blocks of one.  Every block
+// pair meets once per sweep and the pairs of a step are disjoint; a sweep
+// has sum_l ceil(ceil(nb / 2^l) / 2) steps (102 for nb = 100, against 99
+// for the round-robin ordering) but moves one block per group and step
+// through LDS instead of two.  At the start of every level the kept blocks
+// go back to LDS before any group loads its next one (one barrier).
+template <int BLOCK, int G, int RMAX>
+__device__ int onesided_jacobi_keep_scaled(float* W, int n, int ld, float tol, float stop, int max_sweeps,
+                                           int* rot_flag, float* nrm2, float* dsc, int& nrot) {
+  constexpr int B = 2;
+  const int nb = (n + B - 1) / B;
+  const int lane = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = BLOCK / G;
+  static_assert(G * RMAX / (2 * B) <= ngrp, "every block pair of a step has a lane group");
+  const float tol2 = tol * tol, stop2 = stop * stop;
+  for (int c = threadIdx.x; c < nb * B; c += BLOCK) {
+    dsc[c] = 1.f;
+    nrm2[c] = 0.f;  // stays 0 for the zero column of odd n
+  }
+  int sweeps = max_sweeps + 1;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    bool big = false;
+    __syncthreads();
+    // exact squared norms of the true columns at the start of the sweep
+    for (int c = grp; c < n; c += ngrp) {
+      const float* col = W + c * ld + lane;
+      float s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k)
+        if (k < RMAX - 1 || lane + k * G < n) s2 = fmaf(col[k * G], col[k * G], s2);
+      s2 = group_sum<G>(s2);
+      if (lane == 0) nrm2[c] = s2 * dsc[c] * dsc[c];
+    }
+    __syncthreads();
+    // the pair inside each block
+    for (int blk = grp; blk < nb; blk += ngrp) {
+      float x[B][RMAX], nx[B], d[B];
+      bool dx[B];
+      load_block_scaled<G, RMAX, B>(W, nrm2, dsc, blk, n, ld, lane, x, nx, d);
+#pragma unroll
+      for (int i = 0; i < B; ++i) dx[i] = false;
+      rotate_scaled<G, RMAX, 1>(x, x, nx, nx, d, d, dx, dx, [](int) { return 0; }, [](int) { return 1; }, tol2,
+                                stop2, big, nrot);
+      store_block_scaled<G, RMAX, B>(W, nrm2, dsc, blk, n, ld, lane, x, nx, d, dx);
+    }
+    // levels of the halving ordering
+    float x[B][RMAX], nx[B], dxs[B];
+    bool dx[B];
+    int keep = -1;
+    for (int lvl = 0, lmax = nb; lmax >= 2; ++lvl, lmax = (lmax + 1) >> 1) {
+      // back to LDS with the kept block (every group), then this level's node
+      if (keep >= 0) store_block_scaled<G, RMAX, B>(W, nrm2, dsc, keep, n, ld, lane, x, nx, dxs, dx);
+      keep = -1;
+      __syncthreads();
+      int lo = 0, hi = nb, g0 = 0;
+      bool mine = true;
+      for (int l = 0; l < lvl; ++l) {
+        const int len = hi - lo, h = len >> 1;
+        if (grp < g0 + (h >> 1)) {
+          hi = lo + h;
+        } else if (grp < g0 + (h >> 1) + ((len - h) >> 1)) {
+          g0 += h >> 1;
+          lo += h;
+        } else {
+          mine = false;
+          break;
+        }
+      }
+      const int len = hi - lo, h = len >> 1, nbk = len - h, gl = grp - g0;
+      mine = mine && len >= 2 && gl < h;
+      if (mine) {
+        keep = lo + gl;
+        load_block_scaled<G, RMAX, B>(W, nrm2, dsc, keep, n, ld, lane, x, nx, dxs);
+#pragma unroll
+        for (int i = 0; i < B; ++i) dx[i] = false;
+      }
+      const int steps = (lmax + 1) >> 1;
+      for (int s = 0; s < steps; ++s) {
+        if (mine && s < nbk) {
+          int qb = gl + s;
+          if (qb >= nbk) qb -= nbk;
+          const int Q = lo + h + qb;
+          float y[B][RMAX], ny[B], dys[B];
+          bool dy[B];
+          load_block_scaled<G, RMAX, B>(W, nrm2, dsc, Q, n, ld, lane, y, ny, dys);
+#pragma unroll
+          for (int i = 0; i < B; ++i) dy[i] = false;
+#pragma unroll
+          for (int st = 0; st < B; ++st)
+            rotate_scaled<G, RMAX, B>(x, y, nx, ny, dxs, dys, dx, dy, [](int i) { return i; },
+                                      [st](int i) { return (i + st) % B; }, tol2, stop2, big, nrot);
+          store_block_scaled<G, RMAX, B>(W, nrm2, dsc, Q, n, ld, lane, y, ny, dys, dy);
+          // a long-kept block folds its scales in registers (as a store would)
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            if (dxs[i] < 0x1p-12f || dxs[i] > 0x1p12f) {
+#pragma unroll
+              for (int k = 0; k < RMAX; ++k) x[i][k] *= dxs[i];
+              dxs[i] = 1.f;
+            }
+        }
+        __syncthreads();
+      }
+    }
+    if (keep >= 0) store_block_scaled<G, RMAX, B>(W, nrm2, dsc, keep, n, ld, lane, x, nx, dxs, dx);
+    if (lane == 0 && big) rot_flag[sweep] = __float_as_int(1.f);  // any group may set it
+    __syncthreads();
+    if (__int_as_float(rot_flag[sweep]) < stop) {
+      sweeps = sweep + 1;
+      break;
+    }
+  }
+  // fold the remaining scales into the columns
+  __syncthreads();
+  for (int c = grp; c < n; c += ngrp) {
+    const float dc = dsc[c];
+    if (dc == 1.f) continue;
+    float* col = W + c * ld + lane;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+      if (k < RMAX - 1 || lane + k * G < n) col[k * G] *= dc;
+  }
+  __syncthreads();
+  return sweeps;
+}
+
 // Work-group reductions through a small shared scratch array (>= BLOCK/64 slots).
 template <int BLOCK, typename T, typename Op>
 __device__ T block_reduce(T v, T* scratch, Op op) {

@@ -29,9 +29,9 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   extern __shared__ float W[];
   __shared__ int s_nrot;
   __shared__ float nrm[kMaxLdsN];
-  constexpr bool kSorted = B == 0 || (B >= 5 && B <= 9);  // sorted columns, tracked norms
-  constexpr bool kScaled = B >= 7 && B <= 9;               // scaled rotations
-  constexpr int kPadCols = (B == 7 || B == 9) ? 2 : (B == 8 ? 4 : 1);  // W holds n rounded up to this many columns
+  constexpr bool kSorted = B == 0 || (B >= 5 && B <= 10);  // sorted columns, tracked norms
+  constexpr bool kScaled = B >= 7 && B <= 10;               // scaled rotations
+  constexpr int kPadCols = (B == 7 || B == 9 || B == 10) ? 2 : (B == 8 ? 4 : 1);  // W holds n rounded up to this many columns
   __shared__ float diag[kSorted ? kMaxLdsN : 1];
   __shared__ int perm[kSorted ? kMaxLdsN : 1];
   __shared__ float dsc[kScaled ? kMaxLdsN : 1];  // column scales of the scaled-rotation variants
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   const int n = it.n, N = it.N;
   // variant 0 reads RMAX*G rows per column unguarded, variants 5 to 9 guard
   // only their last row chunk: the rows up to there (n .. rows-1) are zero
-  const int rows = B == 0 ? max(n, RMAX * G) : ((B >= 5 && B <= 9) ? max(n, (RMAX - 1) * G) : n);
+  const int rows = B == 0 ? max(n, RMAX * G) : ((B >= 5 && B <= 10) ? max(n, (RMAX - 1) * G) : n);
   const int ld = lds_stride(rows);
   const GridDev g = grids[it.grid];
   const double* V = v64 + it.v_off;
@@ -164,6 +164,8 @@ __global__ __launch_bounds__(BLOCK) void jacobi_f32_lds_kernel(const ItemDev* __
   else if constexpr (B == 7)  // blocks of 2 columns, tracked norms, scaled rotations
     sweeps = onesided_jacobi_blocked_scaled<BLOCK, G, RMAX, 2>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc,
                                                                 nrot);
+  else if constexpr (B == 10)  // as 7, halving ordering with one block kept in registers
+    sweeps = onesided_jacobi_keep_scaled<BLOCK, G, RMAX>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc, nrot);
   else if constexpr (B == 8)  // blocks of 4 columns, scaled rotations, one angle per quarter row
     sweeps = onesided_jacobi_parts<BLOCK, RMAX, 4>(W, n, ld, tol, stop, max_sweeps, rot_flag, nrm, dsc, nrot);
   else if constexpr (B == 9)  // blocks of 2 columns, scaled rotations, one angle per half row
@@ -243,19 +245,21 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
     return hipGetLastError();
   };
   // configuration value -> kernel variant: 0 (default) blocks of 2 columns
-  // with tracked norms and scaled rotations, 1 unblocked with three dot
+  // with tracked norms and scaled rotations in the halving ordering that
+  // keeps one block per lane group in registers, 1 unblocked with three dot
   // products per pair, 2 unblocked with tracked norms, 3 blocks of 2 columns
   // with tracked norms and plain rotations, 4 blocks of 4 columns with
   // tracked norms, 5 blocks of 4 columns with scaled rotations and one angle
   // per quarter row, 6 blocks of 2 columns with one angle per half row
-  // (jacobi_quad.h)
-  static constexpr int kVariant[7] = {7, 1, 0, 5, 6, 8, 9};
-  if (block_cols < 0 || block_cols > 6) return hipErrorInvalidValue;
+  // (jacobi_quad.h), 7 as 0 in the round-robin ordering
+  static constexpr int kVariant[8] = {10, 1, 0, 5, 6, 8, 9, 7};
+  if (block_cols < 0 || block_cols > 7) return hipErrorInvalidValue;
   const int B = kVariant[block_cols];
   if (max_n <= 64) {
     if (B == 0) return go(jacobi_f32_lds_kernel<256, 4, 16, 0>, 256, 64);
     if (B == 5) return go(jacobi_f32_lds_kernel<256, 16, 4, 5>, 256, 48);
     if (B == 7) return go(jacobi_f32_lds_kernel<256, 16, 4, 7>, 256, 48, 2);
+    if (B == 10) return go(jacobi_f32_lds_kernel<256, 16, 4, 10>, 256, 48, 2);
     if (B == 8) return go(jacobi_f32_lds_kernel<128, 16, 4, 8>, 128, 48, 4);
     if (B == 9) return go(jacobi_f32_lds_kernel<256, 16, 4, 9>, 256, 48, 2);
     if (B == 6) return go(jacobi_f32_lds_kernel<256, 32, 2, 6>, 256, 32);
@@ -266,6 +270,7 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
     if (B == 0) return go(jacobi_f32_lds_kernel<512, 8, 16, 0>, 512, 128);
     if (B == 5) return go(jacobi_f32_lds_kernel<512, 16, 8, 5>, 512, 112);
     if (B == 7) return go(jacobi_f32_lds_kernel<512, 16, 8, 7>, 512, 112, 2);
+    if (B == 10) return go(jacobi_f32_lds_kernel<512, 16, 8, 10>, 512, 112, 2);
     if (B == 8) return go(jacobi_f32_lds_kernel<256, 16, 8, 8>, 256, 112, 4);
     if (B == 9) return go(jacobi_f32_lds_kernel<512, 16, 8, 9>, 512, 112, 2);
     if (B == 6) return go(jacobi_f32_lds_kernel<512, 32, 4, 6>, 512, 96);
@@ -275,6 +280,7 @@ hipError_t launch_jacobi_f32_lds(const ItemDev* items, const int32_t* sel, int n
   if (B == 0) return go(jacobi_f32_lds_kernel<1024, 8, 25, 0>, 1024, 200);
   if (B == 5) return go(jacobi_f32_lds_kernel<1024, 16, 13, 5>, 1024, 192);
   if (B == 7) return go(jacobi_f32_lds_kernel<1024, 16, 13, 7>, 1024, 192, 2);
+  if (B == 10) return go(jacobi_f32_lds_kernel<1024, 16, 13, 10>, 1024, 192, 2);
   if (B == 8) return go(jacobi_f32_lds_kernel<512, 16, 13, 8>, 512, 192, 4);
   if (B == 9) return go(jacobi_f32_lds_kernel<1024, 16, 13, 9>, 1024, 192, 2);
   if (B == 6) return go(jacobi_f32_lds_kernel<1024, 32, 7, 6>, 1024, 192);

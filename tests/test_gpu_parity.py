@@ -168,7 +168,7 @@ def test_argument_errors_are_reported_before_launch(ctx):
 
 
 # ------------------------------------------------- LDS Jacobi variants
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_lds_jacobi_variants_match_oracle(variant):
     # every variant of the in-LDS FP32 Jacobi (wpcd_config.jacobi_block), on
     # one item of each LDS size class (n = 37, 40, 128, 200), mixed precision
@@ -318,7 +318,7 @@ def test_warm_start_picks_the_nearest_cold_item():
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("variant", [0, 5, 6])
+@pytest.mark.parametrize("variant", [0, 5, 6, 7])
 def test_lds_jacobi_variants_on_a_batch(variant):
     # the LDS Jacobi variants on batches of many items per launch: 24
     # Yamaguchi n = 50 items (13 blocks of 4: an odd block count) and 12
