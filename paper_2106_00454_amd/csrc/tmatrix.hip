@@ -33,11 +33,11 @@ __device__ __forceinline__ double xlogx(double x) { return x == 0.0 ? 0.0 : x * 
 // boundary terms of bin k + 1 (two logs per scattering pair instead of four;
 // the same values, so the same result).  Lane l handles m = l + 64 j.
 constexpr int kMJ = 4;
-template <typename A>
+template <typename A, int K>
 __device__ __forceinline__ void tmatrix_bins_carry(const ItemDev& it, const GridDev& g, const double* V,
                                                    const double* C, const double* eps, const double* lo,
                                                    const double* hi, int b0, int b1, double* t, int lane, int wave) {
-  const int n = it.n, N = it.N, K = it.nch;
+  const int n = it.n, N = it.N;
   constexpr int NW = kBlock / 64;
   const int per = (N + NW - 1) / NW;
   const int k0 = wave * per, k1 = min(N, k0 + per);
@@ -55,8 +55,14 @@ __device__ __forceinline__ void tmatrix_bins_carry(const ItemDev& it, const Grid
   for (int k = k0; k < k1; ++k) {
     const double a = g.eb[k], b = g.eb[k + 1], de = b - a;
     const double ek = g.e0[k];
-    A acc_re[2][2] = {{A(0), A(0)}, {A(0), A(0)}};
-    A acc_im[2][2] = {{A(0), A(0)}, {A(0), A(0)}};
+    A acc_re[K][K], acc_im[K][K];
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        acc_re[p][q] = A(0);
+        acc_im[p][q] = A(0);
+      }
 #pragma unroll
     for (int j = 0; j < kMJ; ++j) {
       const int m = lane + 64 * j;
@@ -77,17 +83,82 @@ __device__ __forceinline__ void tmatrix_bins_carry(const ItemDev& it, const Grid
         gim = ov > 0.0 ? -kPi * ov * w : 0.0;
       }
       const double sh = em - ek;
-      A vc[2];
+      A vc[K];
+#pragma unroll
       for (int q = 0; q < K; ++q) vc[q] = (A)(sh * C[(int64_t)(q * N + k) * n + m]);
       const A gr = (A)gre, gi = (A)gim;
+#pragma unroll
       for (int p = 0; p < K; ++p)
+#pragma unroll
         for (int q = 0; q < K; ++q) {
           const A pr = vc[p] * vc[q];
           acc_re[p][q] = fma(pr, gr, acc_re[p][q]);
           acc_im[p][q] = fma(pr, gi, acc_im[p][q]);
         }
     }
+#pragma unroll
     for (int p = 0; p < K; ++p)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const A sr = wave_total(acc_re[p][q]);
+        const A si = wave_total(acc_im[p][q]);
+        if (lane == 0) {
+          const double vd = V[(int64_t)(p * N + k) * n + (q * N + k)];
+          double* out = t + it.t_off + 2 * ((int64_t)(k * K + p) * K + q);
+          out[0] = vd + (double)sr;
+          out[1] = (double)si;
+        }
+      }
+  }
+}
+
+// Items with n > 64 kMJ: wavefront w takes bins w, w + 4, ...; lanes over m.
+template <typename A, int K>
+__device__ __forceinline__ void tmatrix_bins(const ItemDev& it, const GridDev& g, const double* V, const double* C,
+                                             const double* eps, const double* lo, const double* hi, int b0, int b1,
+                                             double* t, int lane, int wave) {
+  const int n = it.n, N = it.N;
+  for (int k = wave; k < N; k += kBlock / 64) {
+    const double a = g.eb[k], b = g.eb[k + 1], de = b - a;
+    const double ek = g.e0[k];
+    A acc_re[K][K], acc_im[K][K];
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        acc_re[p][q] = A(0);
+        acc_im[p][q] = A(0);
+      }
+    for (int m = lane; m < n; m += 64) {
+      const double em = eps[m];
+      double gre, gim;
+      if (m < b0 || m >= b1) {
+        gre = log((b - em) / (a - em)) / de;
+        gim = 0.0;
+      } else {
+        const double c = lo[m], d = hi[m];
+        const double w = 1.0 / (de * (d - c));
+        gre = (xlogx(b - c) - xlogx(a - c) - xlogx(b - d) + xlogx(a - d)) * w;
+        const double ov = fmin(b, d) - fmax(a, c);
+        gim = ov > 0.0 ? -kPi * ov * w : 0.0;
+      }
+      const double sh = em - ek;
+      A vc[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) vc[q] = (A)(sh * C[(int64_t)(q * N + k) * n + m]);
+      const A gr = (A)gre, gi = (A)gim;
+#pragma unroll
+      for (int p = 0; p < K; ++p)
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const A pr = vc[p] * vc[q];
+          acc_re[p][q] = fma(pr, gr, acc_re[p][q]);
+          acc_im[p][q] = fma(pr, gi, acc_im[p][q]);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < K; ++p)
+#pragma unroll
       for (int q = 0; q < K; ++q) {
         const A sr = wave_total(acc_re[p][q]);
         const A si = wave_total(acc_im[p][q]);
@@ -171,51 +242,17 @@ __global__ __launch_bounds__(kBlock) void tmatrix_kernel(const ItemDev* __restri
   const double* V = v64 + it.v_off;
   const double* C = evec + it.v_off;
   if (n <= 64 * kMJ) {
-    tmatrix_bins_carry<A>(it, g, V, C, eps, lo, hi, b0, b1, t, lane, wave);
+    if (K == 2)
+      tmatrix_bins_carry<A, 2>(it, g, V, C, eps, lo, hi, b0, b1, t, lane, wave);
+    else
+      tmatrix_bins_carry<A, 1>(it, g, V, C, eps, lo, hi, b0, b1, t, lane, wave);
     if (threadIdx.x == 0) status[blockIdx.x] = 0;
     return;
   }
-  for (int k = wave; k < N; k += kBlock / 64) {
-    const double a = g.eb[k], b = g.eb[k + 1], de = b - a;
-    const double ek = g.e0[k];
-    A acc_re[2][2] = {{A(0), A(0)}, {A(0), A(0)}};
-    A acc_im[2][2] = {{A(0), A(0)}, {A(0), A(0)}};
-    for (int m = lane; m < n; m += 64) {
-      const double em = eps[m];
-      double gre, gim;
-      if (m < b0 || m >= b1) {
-        gre = log((b - em) / (a - em)) / de;
-        gim = 0.0;
-      } else {
-        const double c = lo[m], d = hi[m];
-        const double w = 1.0 / (de * (d - c));
-        gre = (xlogx(b - c) - xlogx(a - c) - xlogx(b - d) + xlogx(a - d)) * w;
-        const double ov = fmin(b, d) - fmax(a, c);
-        gim = ov > 0.0 ? -kPi * ov * w : 0.0;
-      }
-      const double sh = em - ek;
-      A vc[2];
-      for (int q = 0; q < K; ++q) vc[q] = (A)(sh * C[(int64_t)(q * N + k) * n + m]);
-      const A gr = (A)gre, gi = (A)gim;
-      for (int p = 0; p < K; ++p)
-        for (int q = 0; q < K; ++q) {
-          const A pr = vc[p] * vc[q];
-          acc_re[p][q] = fma(pr, gr, acc_re[p][q]);
-          acc_im[p][q] = fma(pr, gi, acc_im[p][q]);
-        }
-    }
-    for (int p = 0; p < K; ++p)
-      for (int q = 0; q < K; ++q) {
-        const A sr = wave_total(acc_re[p][q]);
-        const A si = wave_total(acc_im[p][q]);
-        if (lane == 0) {
-          const double vd = V[(int64_t)(p * N + k) * n + (q * N + k)];
-          double* out = t + it.t_off + 2 * ((int64_t)(k * K + p) * K + q);
-          out[0] = vd + (double)sr;
-          out[1] = (double)si;
-        }
-      }
-  }
+  if (K == 2)
+    tmatrix_bins<A, 2>(it, g, V, C, eps, lo, hi, b0, b1, t, lane, wave);
+  else
+    tmatrix_bins<A, 1>(it, g, V, C, eps, lo, hi, b0, b1, t, lane, wave);
   if (threadIdx.x == 0) status[blockIdx.x] = 0;
 }
 
