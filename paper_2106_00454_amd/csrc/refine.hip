@@ -568,51 +568,90 @@ __global__ __launch_bounds__(64 * kReachWaves) void refine_reach_kernel(const It
   }
 }
 
-// One-sided Jacobi on the block-diagonal W of a Rayleigh-Ritz batch (Tb
-// columns, leading dimension ldw): its chains are independent, so each chain
-// runs its own round-robin ordering over its own rows only, and all chains
-// advance together -- a sweep has max(ne_c) - 1 barrier-separated steps
-// instead of Tb - 1.  bstart/blen: the batch's chains (batch-local first
-// column, length), nb of them; poff[c] = sum of (len+1)/2 over earlier chains;
-// pch[i]: the chain of the batch's pair slot i (poff[c] <= i < poff[c + 1]).
-// Same tolerance semantics and return value as onesided_jacobi_lds (the
-// iteration ends after a sweep whose largest rotated cosine is below stop).
+// One-sided Jacobi on the chains of a Rayleigh-Ritz batch: column j of W
+// (leading dimension ldw) holds only the rows of its own chain, at offsets
+// 0 .. len - 1 from the chain's first column, and zeros up to G * RMAX (the
+// off-chain entries of the block-diagonal matrix are not stored).  The
+// chains are independent, so each runs its own round-robin ordering over
+// its own rows, and all chains advance together -- a sweep has
+// max(ne_c) - 1 barrier-separated steps instead of Tb - 1.  bstart/blen: the
+// batch's chains (batch-local first column, length), nb of them; poff[c] =
+// sum of (len+1)/2 over earlier chains; pch[i]: the chain of the batch's pair
+// slot i (poff[c] <= i < poff[c + 1]).  Column loads and stores need no
+// guard (rotations keep the zero rows zero), and the squared column norms
+// (nrm, Tb doubles of LDS) are tracked through the rotations from exact
+// values at the start of every sweep: one dot product per pair.  Same skip
+// test (cosine above tol), stopping rule (a sweep whose largest rotated
+// cosine is below stop) and return value as onesided_jacobi_lds.
 template <int BLOCK, int G, int RMAX>
-__device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short* blen, const short* poff,
-                            const unsigned char* pch, int nb, double tol, double stop, int max_sweeps,
-                            int* rot_flag) {
+__device__ __forceinline__ int chain_jacobi(double* W, int ldw, int Tb, const short* bstart, const short* blen,
+                                            const short* poff, const unsigned char* pch, int nb, double* nrm,
+                                            double tol, double stop, int max_sweeps, int* rot_flag) {
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;
   constexpr int ngrp = BLOCK / G;
   int ne_max = 0;
   for (int c = 0; c < nb; ++c) ne_max = max(ne_max, (blen[c] + 1) & ~1);
   const int ptot = poff[nb];
+  // this group's pair slots (idx = grp + s ngrp): chain, length, first
+  // column and round-robin positions, fixed for the whole iteration; the
+  // positions advance by one per step (rr_index without its division)
+  constexpr int kSlots = 2;
+  static_assert(kSlots * ngrp >= kMaxChain / 2 + kMaxChain / 4, "pair slots of a batch");
+  int sm[kSlots], sne[kSlots], sb0[kSlots], sp0[kSlots], sq0[kSlots];
+#pragma unroll
+  for (int sl = 0; sl < kSlots; ++sl) {
+    const int idx = grp + sl * ngrp;
+    sm[sl] = 0;
+    if (idx < ptot) {
+      const int c = pch[idx];
+      sm[sl] = blen[c];
+      sne[sl] = (sm[sl] + 1) & ~1;
+      sb0[sl] = bstart[c];
+      const int pr = idx - poff[c];
+      sp0[sl] = pr;                 // position of the first index
+      sq0[sl] = sne[sl] - 1 - pr;   // position of the second
+    }
+  }
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int j = grp; j < Tb; j += ngrp) {
+      const double* c = W + j * ldw + lane;
+      double s2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) s2 = fma(c[k * G], c[k * G], s2);
+      s2 = group_sum<G>(s2);
+      if (lane == 0) nrm[j] = s2;
+    }
+    __syncthreads();
     float cmax = 0.0f;  // largest rotated cosine of this lane's pairs in the sweep
+    // (pos - 1 + step) mod (ne - 1) of each slot's two positions
+    int vp[kSlots], vq[kSlots];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+      vp[sl] = sp0[sl] - 1;
+      vq[sl] = sq0[sl] - 1;
+    }
     for (int step = 0; step < ne_max - 1; ++step) {
-      for (int idx = grp; idx < ptot; idx += ngrp) {
-        const int c = pch[idx];
-        const int m = blen[c], ne = (m + 1) & ~1, b0 = bstart[c];
-        if (step >= ne - 1) continue;
-        const int pr = idx - poff[c];
-        const int p = rr_index(pr, step, ne), q = rr_index(ne - 1 - pr, step, ne);
+#pragma unroll
+      for (int sl = 0; sl < kSlots; ++sl) {
+        const int m = sm[sl], ne = sne[sl], b0 = sb0[sl];
+        if (m == 0 || step >= ne - 1) continue;
+        const int p = sp0[sl] == 0 ? 0 : 1 + vp[sl];
+        const int q = sq0[sl] == 0 ? 0 : 1 + vq[sl];
+        if (++vp[sl] == ne - 1) vp[sl] = 0;
+        if (++vq[sl] == ne - 1) vq[sl] = 0;
         if (p >= m || q >= m) continue;
-        double* wp = W + (b0 + p) * ldw + b0;
-        double* wq = W + (b0 + q) * ldw + b0;
+        double* wp = W + (b0 + p) * ldw + lane;
+        double* wq = W + (b0 + q) * ldw + lane;
         double xp[RMAX], xq[RMAX];
-        double al = 0.0, be = 0.0, ga = 0.0;
+        double ga = 0.0;
 #pragma unroll
         for (int k = 0; k < RMAX; ++k) {
-          const int r = lane + k * G;
-          const double a = r < m ? wp[r] : 0.0, b = r < m ? wq[r] : 0.0;
-          xp[k] = a;
-          xq[k] = b;
-          al = fma(a, a, al);
-          be = fma(b, b, be);
-          ga = fma(a, b, ga);
+          xp[k] = wp[k * G];
+          xq[k] = wq[k * G];
+          ga = fma(xp[k], xq[k], ga);
         }
-        al = group_sum<G>(al);
-        be = group_sum<G>(be);
         ga = group_sum<G>(ga);
+        const double al = nrm[b0 + p], be = nrm[b0 + q];
         // cosine |w_p.w_q| / (|w_p||w_q|) (a zero column gives NaN: no rotation)
         const double cosv = fabs(ga) * rsqrt(al * be);
         if (cosv > tol) {
@@ -624,11 +663,12 @@ __device__ int chain_jacobi(double* W, int ldw, const short* bstart, const short
           const double cs = rsqrt(fma(t, t, 1.0)), sn = cs * t;
 #pragma unroll
           for (int k = 0; k < RMAX; ++k) {
-            const int r = lane + k * G;
-            if (r < m) {
-              wp[r] = cs * xp[k] - sn * xq[k];
-              wq[r] = sn * xp[k] + cs * xq[k];
-            }
+            wp[k * G] = cs * xp[k] - sn * xq[k];
+            wq[k * G] = sn * xp[k] + cs * xq[k];
+          }
+          if (lane == 0) {
+            nrm[b0 + p] = al - t * ga;
+            nrm[b0 + q] = be + t * ga;
           }
           cmax = fmaxf(cmax, (float)cosv);
         }
@@ -865,12 +905,17 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     gemm_tile<T64>(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(SP, n, Tb), acc);
     __syncthreads();  // W overlays the staging tiles
+    // each column holds its chain's rows from offset 0 (symmetric: one writer
+    // per pair), zeros below them up to kMaxChain
     tile_store<T64>(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
-      if (r > cc) return;  // symmetric: one writer per pair
-      const double w = (blk[r] == blk[cc]) ? v : 0.0;
-      W[cc * ldw + r] = w;
-      W[r * ldw + cc] = w;
+      if (r > cc || blk[r] != blk[cc]) return;
+      W[cc * ldw + (r - blk[cc])] = v;
+      W[r * ldw + (cc - blk[r])] = v;
     });
+    for (int e = threadIdx.x; e < Tb * kMaxChain; e += kBlock) {
+      const int j = e / kMaxChain, r = e - j * kMaxChain;
+      if (r >= bend[j] - blk[j]) W[j * ldw + r] = 0.0;
+    }
     if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
     __syncthreads();
     // per-chain Gershgorin shift making every diagonal block positive
@@ -878,11 +923,11 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     // which is rewritten after the Jacobi), then each chain's first column
     // takes the extremes over its chain
     for (int q = threadIdx.x; q < Tb; q += kBlock) {
-      const int e = bend[q];
+      const int b0 = blk[q], m = bend[q] - b0;
       double sacc = 0.0;
-      for (int r = blk[q]; r < e; ++r)
-        if (r != q) sacc += fabs(W[q * ldw + r]);
-      const double d = W[q * ldw + q];
+      for (int r = 0; r < m; ++r)
+        if (r != q - b0) sacc += fabs(W[q * ldw + r]);
+      const double d = W[q * ldw + (q - b0)];
       shift[q] = d - sacc;
       nrm[q] = d + sacc;
     }
@@ -899,13 +944,15 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       for (int q = j; q < e; ++q) shift[q] = sh;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < Tb; j += kBlock) W[j * ldw + j] += shift[j];
+    for (int j = threadIdx.x; j < Tb; j += kBlock) W[j * ldw + (j - blk[j])] += shift[j];
     __syncthreads();
-    const int sw = chain_jacobi<kBlock, 8, 8>(W, ldw, bt_start, bt_len, bt_poff, pch, s_nbt, jtol, jstop, 40, rot_flag);
+    static_assert(8 * 8 == kMaxChain && ldw >= kMaxChain, "chain columns of kMaxChain rows");
+    const int sw = chain_jacobi<kBlock, 8, 8>(W, ldw, Tb, bt_start, bt_len, bt_poff, pch, s_nbt, nrm, jtol, jstop, 40,
+                                              rot_flag);
     if (sw > 40 && threadIdx.x == 0) s_fail = 1;
     for (int j = threadIdx.x; j < Tb; j += kBlock) {
       double s2 = 0.0;
-      for (int r = 0; r < Tb; ++r) s2 = fma(W[j * ldw + r], W[j * ldw + r], s2);
+      for (int r = 0; r < bend[j] - blk[j]; ++r) s2 = fma(W[j * ldw + r], W[j * ldw + r], s2);
       nrm[j] = sqrt(s2);
     }
     __syncthreads();
@@ -918,7 +965,8 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
         const double lq = nrm[q] - shift[q];
         rank += (lq < lj || (lq == lj && q < j)) ? 1 : 0;
       }
-      for (int r = 0; r < Tb; ++r) QB[r * Tb + rank] = W[j * ldw + r] / nrm[j];
+      const int e = bend[j];
+      for (int r = 0; r < Tb; ++r) QB[r * Tb + rank] = (r >= b0 && r < e) ? W[j * ldw + (r - b0)] / nrm[j] : 0.0;
       eval[it.e_off + cols[rank]] = lj;
     }
     __syncthreads();
@@ -962,8 +1010,12 @@ __device__ __forceinline__ int long_chain_jacobi(double* C, int ld, int m, doubl
     }
     __syncthreads();
     float cmax = 0.0f;
+    // round-robin positions grp and ne - 1 - grp: (pos - 1 + step) mod (ne - 1)
+    int vp = grp - 1, vq = ne - 2 - grp;
     for (int step = 0; step < ne - 1; ++step) {
-      const int p = rr_index(grp, step, ne), q = rr_index(ne - 1 - grp, step, ne);
+      const int p = grp == 0 ? 0 : 1 + vp, q = 1 + vq;
+      if (++vp == ne - 1) vp = 0;
+      if (++vq == ne - 1) vq = 0;
       if (grp < ne / 2 && p < m && q < m) {
         double* wp = C + p * ld + lane;
         double* wq = C + q * ld + lane;
