@@ -125,7 +125,7 @@ typedef struct {
   int32_t refine_close_log10; /* closeness constant of the first refinement
                             step, c = 10^k (pairs whose first-order update
                             would exceed 1/c are solved by Rayleigh-Ritz);
-                            later steps use 10x more each; 0 = default 3    */
+                            later steps use 100x more each; 0 = default 3   */
   double jacobi_stop_f32; /* FP32 Jacobi (LDS and device-memory): end the
                             iteration after a sweep whose largest rotated
                             pair had |w_p.w_q|/(|w_p||w_q|) below this; must

@@ -9,13 +9,23 @@
 // The first-order update is only accurate where |E_ij| is small.  A pair is
 // called close when c |S_ij + lam_j R_ij| >= |lam_j - lam_i| (or the same with
 // lam_i in the numerator), i.e. when its predicted correction would reach 1/c,
-// with c = 1000 in the first step and 10x more in each later one.  Close
+// with c = 1000 in the first step and 100x more in each later one.  Close
 // pairs take E_ij = R_ij/2 (orthogonalisation only) and every maximal index
 // range spanned by close pairs (a chain) is solved exactly by Rayleigh-Ritz:
 // with P = (I + E)[:, chain], X P spans the refined chain subspace and
 // (X P)^T A (X P) = P^T S P, whose eigenvectors Q (FP64 one-sided Jacobi)
 // rotate the chain: the update becomes X <- X M with M = I + E except
-// M[:, chain] = P Q.
+// M[:, chain] = P Q.  The chain block P^T S P is formed without the n x n x m
+// product S P: with C the chain's columns, P = I_C + E_C and T = S_C +
+// Lam E_C / 2 (n x m, Lam = diag(lam)), V = P^T T gives
+//   P^T S P = V + V^T - T_C - T_C^T + S_CC + E_C^T (S - Lam) E_C,
+// where T_C, S_CC are the rows C of T and S_C.  S - Lam is of the order of the
+// error of X (about 1e-7 |A| from FP32 vectors) and so is E_C off the close
+// pairs (|E| < 1/c there), so the last term is third order in that error and
+// is dropped: up to about 1e-12 |A| in the first step, which can still turn
+// a chain's nearly degenerate pairs by more than 1e-5; the second step's
+// closeness test (1/c = 1e-5) hands such pairs to its own Rayleigh-Ritz, and
+// there the term is far below rounding.
 // This replaces the published cluster threshold (a Frobenius-norm bound that
 // is far too coarse for an FP32 starting point and lets badly conditioned
 // Newton updates through) by a direct bound on the size of each update.
@@ -60,11 +70,13 @@ constexpr int kXcd = 8;        // XCDs; workgroups are dispatched to them round-
 constexpr int kMaxChain = 64;  // columns of one LDS Rayleigh-Ritz batch
 constexpr int kMaxBig = 24;    // longer chains per item, solved in device memory
 constexpr int kBigRows = 19;   // rows per lane of their Jacobi (64 * 19 >= kMaxN)
-// Closeness constant of refinement step st: c = 10^(close_log10 + st) (by
+// Closeness constant of refinement step st: c = 10^(close_log10 + 2 st) (by
 // default 1e3 in the first step, which starts from FP32 vectors and admits
-// Newton updates up to 1e-3; later steps start from much better vectors and
-// take only smaller updates, whose second-order remainders are below FP64
-// orthogonality).
+// Newton updates up to 1e-3; the second step, 1e5, admits updates up to 1e-5,
+// whose second-order remainders stay near 1e-10 even for items whose FP32
+// vectors were poor, and solves the larger residual rotations -- the first
+// step's Newton remainders and the error of its chain blocks -- by
+// Rayleigh-Ritz).
 
 // One-dimensional grid of (item, tile) pairs in which every tile of an item
 // lands on the same XCD (block b runs on XCD b mod 8), so that the item's
@@ -765,9 +777,10 @@ __device__ void find_chains(int n, int* reach, short* seg_start, int* scan_sh, s
 // One work-group per item: Rayleigh quotients, close pairs and chains, and the
 // Rayleigh-Ritz rotation of every chain.  Chains of up to kMaxChain columns
 // are processed in batches of whole chains with at most kMaxChain columns;
-// for a batch with columns cols[0..Tb): P -> W5 (n x Tb), S P -> Y (n x Tb),
-// P^T S P -> LDS (kept block-diagonal, one block per chain), one-sided Jacobi,
-// Q -> LDS, and P Q -> the batch's columns of M (n x n, W6).
+// for a batch with columns cols[0..Tb): P -> W5 (n x Tb), T -> Y (n x Tb),
+// P^T T -> LDS (only the diagonal blocks, one per chain, are kept), which
+// gives P^T S P with the rows C of T and S, one-sided Jacobi, Q -> LDS, and
+// P Q -> the batch's columns of M (n x n, W6).
 // Longer chains (dense parts of the spectrum of large items) are left to
 // refine_bigchain_kernel, their list at the end of the item's W7.  Writes the
 // refined eigenvalues of its chains to eval, the Rayleigh quotients outside
@@ -842,7 +855,7 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   const int nch = s_nch;
   const int nt = (n + kTM - 1) / kTM;
   double* P = ws.W5;   // n x Tb
-  double* SP = ws.Y;   // n x Tb
+  double* TS = ws.Y;   // n x Tb: T = S_C + Lam E / 2
   double* M = ws.W6;  // n x n update matrix (chain columns)
   double* QB = ws.W7;  // Tb x Tb sorted Q of a batch (W7 holds a long chain's matrix later)
   d4 acc[2][2];
@@ -892,31 +905,57 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int k = k0 + u * KS;
-          if (k < n)
-            P[(int64_t)k * Tb + t] = (k == j ? 1.0 : 0.0) + newton_e_of(gv[u], sv[u], lam[k], lj, k == j, closec);
+          if (k < n) {
+            const double e = newton_e_of(gv[u], sv[u], lam[k], lj, k == j, closec);
+            P[(int64_t)k * Tb + t] = (k == j ? 1.0 : 0.0) + e;
+            TS[(int64_t)k * Tb + t] = fma(0.5 * lam[k], e, sv[u]);
+          }
         }
       }
     }
     __syncthreads();
-    for (int tm = 0; tm < nt; ++tm) {
-      gemm_tile<T64>(As, Bs, tm * kTM, 0, n, Tb, n, col_view(S, n, n), col_view<double>(P, n, Tb), acc);
-      tile_store<T64>(tm * kTM, 0, n, Tb, acc, [&](int r, int cc, double v) { SP[(int64_t)r * Tb + cc] = v; });
-    }
-    __syncthreads();
-    gemm_tile<T64>(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(SP, n, Tb), acc);
+    // V = P^T T = T_C + E^T S_C + E^T Lam E / 2, then P^T S P ~ V + V^T - T_C - T_C^T + S_CC
+    gemm_tile<T64>(As, Bs, 0, 0, Tb, Tb, n, col_view<double>(P, n, Tb), col_view<double>(TS, n, Tb), acc);
     __syncthreads();  // W overlays the staging tiles
-    // each column holds its chain's rows from offset 0 (symmetric: one writer
-    // per pair), zeros below them up to kMaxChain
+    // each column holds its chain's rows from offset 0 (V as it is, made
+    // symmetric below), zeros below them up to kMaxChain
     tile_store<T64>(0, 0, Tb, Tb, acc, [&](int r, int cc, double v) {
-      if (r > cc || blk[r] != blk[cc]) return;
-      W[cc * ldw + (r - blk[cc])] = v;
-      W[r * ldw + (cc - blk[r])] = v;
+      if (blk[r] == blk[cc]) W[cc * ldw + (r - blk[cc])] = v;
     });
     for (int e = threadIdx.x; e < Tb * kMaxChain; e += kBlock) {
       const int j = e / kMaxChain, r = e - j * kMaxChain;
       if (r >= bend[j] - blk[j]) W[j * ldw + r] = 0.0;
     }
     if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
+    __syncthreads();
+    // one thread per unordered same-chain pair (a <= b, batch positions);
+    // the loads of two pairs are issued before either is used
+    for (int e0 = threadIdx.x; e0 < Tb * kMaxChain; e0 += 2 * kBlock) {
+      double tv[2][3];
+      int pa[2], pb[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + u * kBlock;
+        const int b = e / kMaxChain;
+        const int a = b < Tb ? blk[b] + (e - b * kMaxChain) : b + 1;  // a > b: no pair
+        pa[u] = a;
+        pb[u] = b;
+        if (a <= b) {
+          tv[u][0] = TS[(int64_t)cols[a] * Tb + b];
+          tv[u][1] = TS[(int64_t)cols[b] * Tb + a];
+          tv[u][2] = S[(int64_t)cols[a] * n + cols[b]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int a = pa[u], b = pb[u];
+        if (a > b) continue;
+        const int b0 = blk[b];
+        const double c = (W[b * ldw + (a - b0)] + W[a * ldw + (b - b0)]) - (tv[u][0] + tv[u][1]) + tv[u][2];
+        W[b * ldw + (a - b0)] = c;
+        W[a * ldw + (b - b0)] = c;
+      }
+    }
     __syncthreads();
     // per-chain Gershgorin shift making every diagonal block positive
     // definite: each column's disc (lower end -> shift, upper end -> nrm,
@@ -1065,7 +1104,7 @@ __device__ __forceinline__ int long_chain_jacobi(double* C, int ld, int m, doubl
 // The chains of more than kMaxChain columns that refine_chain_kernel listed
 // at the end of the item's W7, one work-group per item, after it on the same
 // stream (items with none return at once).  Per chain i0 .. i0+m-1:
-// P = (I + E)[:, chain] -> W5 (n x m), S P -> Y, C = P^T S P, a Gershgorin
+// P = (I + E)[:, chain] -> W5 (n x m), T -> Y, C = P^T S P from P^T T, a Gershgorin
 // shift, the FP64 one-sided Jacobi on C, the sorted Q -> Y, P Q -> the
 // chain's columns of M, eigenvalues |w_j| - shift.  C stays in LDS for
 // m <= kBigLdsN (long_chain_jacobi: 64 lane groups of 4, all pairs of a
@@ -1112,8 +1151,8 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
   const double* S = ws.S;
   const double* G = ws.G;
   double* P = ws.W5;
-  double* SP = ws.Y;
-  double* Q = ws.Y;
+  double* TS = ws.Y;  // T = S_C + Lam E / 2
+  double* Q = ws.Y;   // after T's last use
   double* M = ws.W6;
   const int nt = (n + kTM - 1) / kTM;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1126,43 +1165,68 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
     const int ld = in_lds ? kBigLd : m;
     for (int e = threadIdx.x; e < n * m; e += kBlock) {
       const int k = e / m, t = e - k * m;
-      P[e] = (k == i0 + t ? 1.0 : 0.0) + newton_e(S, G, lam, n, k, i0 + t, closec);
+      const double ek = newton_e(S, G, lam, n, k, i0 + t, closec);
+      P[e] = (k == i0 + t ? 1.0 : 0.0) + ek;
+      TS[e] = fma(0.5 * lam[k], ek, S[(int64_t)k * n + i0 + t]);
     }
     __syncthreads();
-    for (int tm = 0; tm < nt; ++tm)
-      for (int tc = 0; tc < mt; ++tc) {
-        gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, n, m, n, col_view(S, n, n), col_view<double>(P, n, m), acc);
-        tile_store<T64>(tm * kTM, tc * kTM, n, m, acc, [&](int r, int cc, double v) { SP[(int64_t)r * m + cc] = v; });
-      }
-    __syncthreads();
-    auto put_c = [&](int r, int cc, double v) {
-      if (r > cc) return;  // symmetric: one writer per pair
-      C[cc * ld + r] = v;
-      C[r * ld + cc] = v;
-    };
+    // V = P^T T (every tile: V is not symmetric) -> C as it is
+    auto put_c = [&](int r, int cc, double v) { C[cc * ld + r] = v; };
     if (in_lds) {
-      // m <= 126: the upper tiles (0,0), (0,1), (1,1) of C are all computed
-      // before any is stored, since C overlays the staging tiles
+      // m <= 126: the 2 x 2 tiles of V are all computed before any is
+      // stored, since C overlays the staging tiles
       static_assert(kBigLdsN <= 2 * kTM && kBigLd >= 128, "at most 2 x 2 tiles of C in LDS, 128 rows per column");
-      d4 acc3[3][2][2];
-      gemm_tile<T64>(As, Bs, 0, 0, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[0]);
+      d4 acc4[4][2][2];
+      const auto pv = col_view<double>(P, n, m);
+      const auto tv = col_view<double>(TS, n, m);
+      gemm_tile<T64>(As, Bs, 0, 0, m, m, n, pv, tv, acc4[0]);
       if (mt > 1) {
-        gemm_tile<T64>(As, Bs, 0, kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[1]);
-        gemm_tile<T64>(As, Bs, kTM, kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m), acc3[2]);
+        gemm_tile<T64>(As, Bs, 0, kTM, m, m, n, pv, tv, acc4[1]);
+        gemm_tile<T64>(As, Bs, kTM, 0, m, m, n, pv, tv, acc4[2]);
+        gemm_tile<T64>(As, Bs, kTM, kTM, m, m, n, pv, tv, acc4[3]);
       }
       __syncthreads();
-      tile_store<T64>(0, 0, m, m, acc3[0], put_c);
+      tile_store<T64>(0, 0, m, m, acc4[0], put_c);
       if (mt > 1) {
-        tile_store<T64>(0, kTM, m, m, acc3[1], put_c);
-        tile_store<T64>(kTM, kTM, m, m, acc3[2], put_c);
+        tile_store<T64>(0, kTM, m, m, acc4[1], put_c);
+        tile_store<T64>(kTM, 0, m, m, acc4[2], put_c);
+        tile_store<T64>(kTM, kTM, m, m, acc4[3], put_c);
       }
     } else {
       for (int tm = 0; tm < mt; ++tm)
-        for (int tc = tm; tc < mt; ++tc) {
-          gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(SP, n, m),
+        for (int tc = 0; tc < mt; ++tc) {
+          gemm_tile<T64>(As, Bs, tm * kTM, tc * kTM, m, m, n, col_view<double>(P, n, m), col_view<double>(TS, n, m),
                          acc);
           tile_store<T64>(tm * kTM, tc * kTM, m, m, acc, put_c);
         }
+    }
+    __syncthreads();
+    // P^T S P ~ V + V^T - T_C - T_C^T + S_CC, one thread per pair a <= b;
+    // the loads of four pairs are issued before any is used
+    for (int e0 = threadIdx.x; e0 < m * m; e0 += 4 * kBlock) {
+      double tv[4][3];
+      int pa[4], pb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kBlock;
+        const int b = e / m;
+        const int a = b < m ? e - b * m : b + 1;  // a > b: no pair
+        pa[u] = a;
+        pb[u] = b;
+        if (a <= b) {
+          tv[u][0] = TS[(int64_t)(i0 + a) * m + b];
+          tv[u][1] = TS[(int64_t)(i0 + b) * m + a];
+          tv[u][2] = S[(int64_t)(i0 + a) * n + i0 + b];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int a = pa[u], b = pb[u];
+        if (a > b) continue;
+        const double c = (C[b * ld + a] + C[a * ld + b]) - (tv[u][0] + tv[u][1]) + tv[u][2];
+        C[b * ld + a] = c;
+        C[a * ld + b] = c;
+      }
     }
     if (threadIdx.x < 64) rot_flag[threadIdx.x] = 0;
     __syncthreads();
@@ -2020,7 +2084,7 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
     const bool last = st == steps - 1;
     const int out_ws = whole ? ((steps - 1 - st) % 2 == 0 ? 0 : 1) : (st == 0 ? 0 : 1 - cur_ws);
     double closec = 1.0;
-    for (int q = 0; q < close_log10 + st; ++q) closec *= 10.0;
+    for (int q = 0; q < close_log10 + 2 * st; ++q) closec *= 10.0;
     if (whole) {
       if (st == 0) {
         hipLaunchKernelGGL(igemm_kernel<IgY<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
