@@ -295,9 +295,13 @@ __device__ __forceinline__ double newton_e_of(double g, double s, double lk, dou
   if (closec * fabs(num) >= d || closec * fabs(s + lk * r) >= d) return 0.5 * r;
   return num / (lj - lk);
 }
+__device__ __forceinline__ int64_t upper_at(int n, int k, int j) {
+  return k <= j ? (int64_t)k * n + j : (int64_t)j * n + k;
+}
 __device__ __forceinline__ double newton_e(const double* S, const double* G, const double* lam, int n, int k,
                                            int j, double closec) {
-  return newton_e_of(G[(int64_t)k * n + j], S[(int64_t)k * n + j], lam[k], lam[j], j == k, closec);
+  const int64_t e = upper_at(n, k, j);
+  return newton_e_of(G[e], S[e], lam[k], lam[j], j == k, closec);
 }
 
 // Per-item work-space (doubles): P1 | Y | S | G | W5 | W6 | W7, each n*n.
@@ -420,66 +424,90 @@ __device__ int block_xscan(int v, int* sh, int& total) {
 // cl holds reach[p] from refine_reach_kernel: column j lies in a chain iff
 // some interval [p, reach[p]] with reach[p] > p covers it, i.e. reach[j] > j
 // or max_{p<j} reach[p] >= j (a prefix maximum over the work-group).  lam_pre
-// holds the Rayleigh quotients E was built from.  One-dimensional grid over
-// (item, block of 64 rows) from xcd_item_tile; each wavefront takes rows
-// r0 + w + 4 u and issues the loads of kFormRows of them before using any.
-constexpr int kFormRows = 4;
+// holds the Rayleigh quotients E was built from.  S and G are read from their
+// upper triangles only (the whole-item S, G product stores nothing else): one
+// work-group per (item, pair of 32-row blocks I <= J) from xcd_item_tile
+// reads the upper tile (I, J) once and writes both M[k][j] (k in I, j in J,
+// k <= j) and M[j][k] (k < j, from the same S_kj and G_kj) through a
+// transposed copy in LDS, so every store covers consecutive columns.
+constexpr int kFT = 32;                    // form_m tile edge
+constexpr int kFRY = kBlock / kFT;         // tile rows per round
+constexpr int kFRows = kFT / kFRY;         // rounds (loads issued before use)
+inline int form_m_tiles(int max_n) {
+  const int nb = (max_n + kFT - 1) / kFT;
+  return nb * (nb + 1) / 2;
+}
 __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restrict__ items,
                                                         const double* __restrict__ lam_pre, double* work,
                                                         const int32_t* __restrict__ cl, double closec, int tiles,
                                                         int n_items) {
-  __shared__ double lam[kMaxN];
-  __shared__ int rch[kMaxN];
-  __shared__ unsigned char inch[kMaxN];
+  __shared__ double tt[kFT * (kFT + 1)];
+  __shared__ double lam_i[kFT], lam_j[kFT];
+  __shared__ unsigned char in_i[kFT], in_j[kFT];
   __shared__ int scan_sh[kBlock / 64];
   int item, tile;
   if (!xcd_item_tile(tiles, n_items, item, tile)) return;
   const ItemDev it = items[item];
   const int n = it.n;
-  const int r0 = tile * kTM;
-  if (r0 >= n) return;
-  const WS ws(work, it);
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    lam[i] = lam_pre[it.e_off + i];
-    rch[i] = cl ? cl[it.e_off + i] : i;  // no reach list: no chains
+  const int nb = (n + kFT - 1) / kFT;
+  if (tile >= nb * (nb + 1) / 2) return;
+  int bi = 0, rem = tile;  // tile -> (I, J), row by row over the upper block triangle
+  while (rem >= nb - bi) {
+    rem -= nb - bi;
+    ++bi;
   }
-  __syncthreads();
+  const int i0 = bi * kFT, j0 = (bi + rem) * kFT;
+  const WS ws(work, it);
   {
+    // chain membership of the tile's rows and columns (no reach list: no chains)
     const int per = (n + kBlock - 1) / kBlock;
-    const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+    const int a0 = min(n, (int)threadIdx.x * per), a1 = min(n, a0 + per);
     int lm = -1;
-    for (int i = i0; i < i1; ++i) lm = max(lm, rch[i]);
+    for (int c = a0; c < a1; ++c) lm = max(lm, cl ? cl[it.e_off + c] : c);
     int tot;
     int cover = block_xscan<true>(lm, scan_sh, tot);
-    for (int j = i0; j < i1; ++j) {
-      inch[j] = (rch[j] > j || cover >= j) ? 1 : 0;
-      cover = max(cover, rch[j]);
+    for (int c = a0; c < a1; ++c) {
+      const int rc = cl ? cl[it.e_off + c] : c;
+      const unsigned char v = (rc > c || cover >= c) ? 1 : 0;
+      if (c >= i0 && c < i0 + kFT) in_i[c - i0] = v;
+      if (c >= j0 && c < j0 + kFT) in_j[c - j0] = v;
+      cover = max(cover, rc);
+    }
+    if (threadIdx.x < kFT) {
+      const int t = threadIdx.x;
+      lam_i[t] = i0 + t < n ? lam_pre[it.e_off + i0 + t] : 0.0;
+      lam_j[t] = j0 + t < n ? lam_pre[it.e_off + j0 + t] : 0.0;
     }
   }
   __syncthreads();
-  const int r1 = min(n, r0 + kTM);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int KS = kBlock / 64;
-  for (int kb = r0 + w; kb < r1; kb += KS * kFormRows)
-    for (int j0 = 0; j0 < n; j0 += 64) {
-      const int j = j0 + lane;
-      double gv[kFormRows], sv[kFormRows];
+  const int tx = threadIdx.x & (kFT - 1), ty = threadIdx.x / kFT;
+  const int j = j0 + tx;
+  double gv[kFRows], sv[kFRows];
 #pragma unroll
-      for (int u = 0; u < kFormRows; ++u) {
-        const int k = kb + KS * u;
-        const int64_t e = (k < r1 && j < n) ? (int64_t)k * n + j : 0;
-        gv[u] = ws.G[e];
-        sv[u] = ws.S[e];
-      }
-      if (j >= n || inch[j]) continue;
-      const double lj = lam[j];
+  for (int u = 0; u < kFRows; ++u) {
+    const int k = i0 + ty + kFRY * u;
+    const int64_t e = (k < n && j < n && k <= j) ? (int64_t)k * n + j : 0;
+    gv[u] = ws.G[e];
+    sv[u] = ws.S[e];
+  }
+  if (j < n) {
+    const double lj = lam_j[tx];
 #pragma unroll
-      for (int u = 0; u < kFormRows; ++u) {
-        const int k = kb + KS * u;
-        if (k < r1)
-          ws.W6[(int64_t)k * n + j] = (k == j ? 1.0 : 0.0) + newton_e_of(gv[u], sv[u], lam[k], lj, k == j, closec);
-      }
+    for (int u = 0; u < kFRows; ++u) {
+      const int kk = ty + kFRY * u, k = i0 + kk;
+      if (k >= n || k > j) continue;
+      const double lk = lam_i[kk];
+      if (!in_j[tx]) ws.W6[(int64_t)k * n + j] = (k == j ? 1.0 : 0.0) + newton_e_of(gv[u], sv[u], lk, lj, k == j, closec);
+      if (k < j) tt[tx * (kFT + 1) + kk] = newton_e_of(gv[u], sv[u], lj, lk, false, closec);
     }
+  }
+  __syncthreads();
+  // M[j][k] for the tile's columns j (rows of M) and rows k (columns of M)
+#pragma unroll
+  for (int u = 0; u < kFRows; ++u) {
+    const int jj = ty + kFRY * u, jr = j0 + jj, k = i0 + tx;
+    if (jr < n && k < jr && !in_i[tx]) ws.W6[(int64_t)jr * n + k] = tt[jj * (kFT + 1) + tx];
+  }
 }
 
 // X' = X M with M in W6 (form_m_kernel and refine_chain_kernel).
@@ -886,25 +914,27 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
     __syncthreads();
     const int Tb = s_Tb;
     if (Tb == 0) break;
-    // P: lane t of every wavefront takes column t (Tb <= 64), the wavefronts
-    // interleave the rows
-    // (all loads of a round of 8 rows are issued before their use: S and G
-    // come from HBM)
-    if ((int)(threadIdx.x & 63) < Tb) {
-      const int t = threadIdx.x & 63, j = cols[t];
+    // P and T: each wavefront splits into row groups of tpw >= Tb lanes (8,
+    // 16, 32 or 64), lane t of a group takes column t; the groups of all
+    // wavefronts interleave the rows (all loads of a round of 8 rows per
+    // group are issued before their use: S and G come from HBM)
+    const int tpw = Tb <= 8 ? 8 : Tb <= 16 ? 16 : Tb <= 32 ? 32 : 64;
+    if ((int)(threadIdx.x & (tpw - 1)) < Tb) {
+      const int t = threadIdx.x & (tpw - 1), j = cols[t];
       const double lj = lam[j];
       constexpr int U = 8, KS = kBlock / 64;
-      for (int k0 = threadIdx.x >> 6; k0 < n; k0 += U * KS) {
+      const int gpw = 64 / tpw, RS = KS * gpw;  // groups per wavefront, row stride
+      for (int k0 = (threadIdx.x >> 6) * gpw + ((threadIdx.x & 63) / tpw); k0 < n; k0 += U * RS) {
         double gv[U], sv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int k = min(k0 + u * KS, n - 1);
-          gv[u] = G[(int64_t)k * n + j];
-          sv[u] = S[(int64_t)k * n + j];
+          const int64_t e = upper_at(n, min(k0 + u * RS, n - 1), j);
+          gv[u] = G[e];
+          sv[u] = S[e];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int k = k0 + u * KS;
+          const int k = k0 + u * RS;
           if (k < n) {
             const double e = newton_e_of(gv[u], sv[u], lam[k], lj, k == j, closec);
             P[(int64_t)k * Tb + t] = (k == j ? 1.0 : 0.0) + e;
@@ -1165,9 +1195,11 @@ __global__ __launch_bounds__(kBlock) void refine_bigchain_kernel(const ItemDev* 
     const int ld = in_lds ? kBigLd : m;
     for (int e = threadIdx.x; e < n * m; e += kBlock) {
       const int k = e / m, t = e - k * m;
-      const double ek = newton_e(S, G, lam, n, k, i0 + t, closec);
+      const int64_t ue = upper_at(n, k, i0 + t);
+      const double sv = S[ue];
+      const double ek = newton_e_of(G[ue], sv, lam[k], lam[i0 + t], k == i0 + t, closec);
       P[e] = (k == i0 + t ? 1.0 : 0.0) + ek;
-      TS[e] = fma(0.5 * lam[k], ek, S[(int64_t)k * n + i0 + t]);
+      TS[e] = fma(0.5 * lam[k], ek, sv);
     }
     __syncthreads();
     // V = P^T T (every tile: V is not symmetric) -> C as it is
@@ -1887,18 +1919,16 @@ __device__ __forceinline__ void ipass(const P& p, const ItemDev* __restrict__ it
                                                 vo + (unsigned)(4 * r * n) * SZ, 0, 0);
       }
     } else if constexpr (P::OUT == kOutSym) {
-      // symmetric result: element (row, col) also goes to (col, row); in a
-      // diagonal block only row <= col is stored; dropped stores get an
-      // offset past the buffer
+      // symmetric result: only the upper triangle is stored, element (row,
+      // col) at (min, max); in a diagonal block only row <= col is kept;
+      // dropped stores get an offset past the buffer
       const __amdgpu_buffer_rsrc_t o = p.template out<PS>(it, item);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = br * 16 + lk + 4 * r;
         const bool keep = row < n && col < n && !(br == bc && row > col);
-        const unsigned od = keep ? (unsigned)(row * n + col) * 8u : kOob;
-        const unsigned om = keep ? (unsigned)(col * n + row) * 8u : kOob;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, e[r]), o, od, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, e[r]), o, om, 0, 0);
+        const unsigned ou = !keep ? kOob : row <= col ? (unsigned)(row * n + col) * 8u : (unsigned)(col * n + row) * 8u;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, e[r]), o, ou, 0, 0);
       }
     } else {
 #pragma unroll
@@ -2119,8 +2149,8 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
     // take R_ij/2), no chain kernel
     const bool rr = rr_steps <= 0 || st >= steps - rr_steps;
     if (!rr) {
-      hipLaunchKernelGGL(form_m_kernel, dim3(xcd_grid(nt, n_items)), dim3(kBlock), 0, s, items, lam_pre, work,
-                         (const int32_t*)nullptr, closec, nt, n_items);
+      hipLaunchKernelGGL(form_m_kernel, dim3(xcd_grid(form_m_tiles(max_n), n_items)), dim3(kBlock), 0, s, items,
+                         lam_pre, work, (const int32_t*)nullptr, closec, form_m_tiles(max_n), n_items);
     }
     // M: the columns outside chains (form_m, streaming S and G) on the side
     // stream while the chain kernel (latency-bound) writes the chain columns
@@ -2132,8 +2162,8 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
       sm = side;
     }
     if (rr)
-      hipLaunchKernelGGL(form_m_kernel, dim3(xcd_grid(nt, n_items)), dim3(kBlock), 0, sm, items, lam_pre, work, cl,
-                         closec, nt, n_items);
+      hipLaunchKernelGGL(form_m_kernel, dim3(xcd_grid(form_m_tiles(max_n), n_items)), dim3(kBlock), 0, sm, items,
+                         lam_pre, work, cl, closec, form_m_tiles(max_n), n_items);
     // Rayleigh-Ritz of the chains to FP64 accuracy in the last step; in an
     // earlier one the Newton columns keep second-order errors of up to
     // 1/c^2 = 1e-6 and the next step squares what is left, so the chains'
