@@ -1942,6 +1942,59 @@ __device__ __forceinline__ void ipass(const P& p, const ItemDev* __restrict__ it
   for (int j = 0; j < B::NC; ++j) put(acc[j], w, B::col(w, j));
   if (e_live) put(ace, kIBlk - 1, B::ce(w));
   if (x_live) put(acx, kIBlk - 1, kIBlk - 1);
+  if constexpr (P::REACH) {
+    // after G (the second pass of the symmetric S, G product): the work of
+    // refine_reach_kernel from the G blocks in registers and the S elements
+    // this lane stored in the first pass (same blocks, same positions).
+    // Rayleigh quotients lam_i = S_ii / G_ii -> dg; per row p the largest
+    // close q > p (else p) -> pm; then both to lam_pre and cl.  dg and pm are
+    // last read after the previous item's passes (their chunk barriers).
+    if (PS == 1) {
+      static_assert(P::set(PS) == kSetSym, "close-pair test on the symmetric product");
+      const double* S = WS(p.work, it).S;
+      auto diag_lam = [&](const d4& v, int b) {
+        const double e[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = b * 16 + lk + 4 * r, col = b * 16 + li;
+          if (row == col && row < n) dg[row] = S[(int64_t)row * n + row] / e[r];
+        }
+      };
+      diag_lam(acc[0], w);  // block (w, w): column block (w + 0) mod 13
+      if (w == 0 && e_live) diag_lam(ace, kIBlk - 1);  // block (12, 12)
+      for (int i = threadIdx.x; i < n; i += kIT) pm[i] = i;
+      __syncthreads();
+      auto test = [&](const d4& v, int br, int bc) {
+        const double e[4] = {v[0], v[1], v[2], v[3]};
+        const int col = bc * 16 + li;
+        double sv[4];
+        int pp[4], qq[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = br * 16 + lk + 4 * r;
+          const bool keep = row < n && col < n && row != col && !(br == bc && row > col);
+          pp[r] = keep ? min(row, col) : -1;
+          qq[r] = max(row, col);
+          sv[r] = keep ? S[(int64_t)pp[r] * n + qq[r]] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (pp[r] < 0) continue;
+          const double lp = dg[pp[r]], lq = dg[qq[r]], rr = -e[r];
+          const double d = fabs(lq - lp);
+          if (p.closec * fabs(sv[r] + lq * rr) >= d || p.closec * fabs(sv[r] + lp * rr) >= d) atomicMax(&pm[pp[r]], qq[r]);
+        }
+      };
+#pragma unroll
+      for (int j = 0; j < B::NC; ++j) test(acc[j], w, B::col(w, j));
+      if (e_live) test(ace, kIBlk - 1, B::ce(w));
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += kIT) {
+        p.cl[it.e_off + i] = pm[i];
+        p.lam_pre[it.e_off + i] = dg[i];
+      }
+    }
+  }
 }
 
 // The work-group's items: sel[i] (or i without a list) for i = blockIdx.x,
@@ -1950,8 +2003,8 @@ template <class P>
 __global__ __launch_bounds__(kIT, 1) void igemm_kernel(const ItemDev* __restrict__ items,
                                                        const int32_t* __restrict__ sel, int n_items, P p) {
   __shared__ double lds[2][2][kIPanelLds];
-  __shared__ double dg[P::DIAG_A || P::DIAG_B ? kIN : 1];
-  __shared__ int pm[P::PERM ? kIN : 1];
+  __shared__ double dg[P::DIAG_A || P::DIAG_B || P::REACH ? kIN : 1];
+  __shared__ int pm[P::PERM || P::REACH ? kIN : 1];
   if ((int)blockIdx.x >= n_items) return;
   typename Mat<typename P::TA>::raw_t ra[kIStage];
   typename Mat<typename P::TB>::raw_t rb[kIStage];
@@ -1973,7 +2026,7 @@ template <typename XT>
 struct IgY {
   using TA = double;
   using TB = XT;
-  static constexpr bool KA = true, KB = true, DIAG_A = true, DIAG_B = false, PERM = false;
+  static constexpr bool KA = true, KB = true, DIAG_A = true, DIAG_B = false, PERM = false, REACH = false;
   static constexpr int OUT = kOutF64, NPASS = 2;
   static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
   static constexpr bool same_panel(int) { return false; }
@@ -2003,13 +2056,16 @@ template <typename XT>
 struct IgSG {
   using TA = XT;
   using TB = double;
-  static constexpr bool KA = true, KB = true, DIAG_A = false, DIAG_B = false, PERM = false;
+  static constexpr bool KA = true, KB = true, DIAG_A = false, DIAG_B = false, PERM = false, REACH = true;
   static constexpr int OUT = kOutSym, NPASS = 2;
   static constexpr int set(int) { return kSetSym; }
   static constexpr bool same_panel(int ps) { return ps == 1; }
   const XT* xin;
   int xin_ws;
   double* work;
+  double* lam_pre;  // close-pair test (refine_reach_kernel's outputs)
+  int32_t* cl;
+  double closec;
   __device__ Mat<XT> viewA(const ItemDev& it, int) const {
     const XT* X = xin_ws ? reinterpret_cast<const XT*>(WS(work, it).P1) : (xin + it.v_off);
     return col_view(X, it.n, it.n);
@@ -2030,7 +2086,7 @@ template <typename XT>
 struct IgXM {
   using TA = XT;
   using TB = double;
-  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = false, PERM = true;
+  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = false, PERM = true, REACH = false;
   static constexpr int OUT = kOutF64, NPASS = 2;
   static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
   static constexpr bool same_panel(int) { return false; }
@@ -2063,7 +2119,7 @@ struct IgXM {
 struct IgWarm {
   using TA = float;
   using TB = double;
-  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = true, PERM = false;
+  static constexpr bool KA = false, KB = true, DIAG_A = false, DIAG_B = true, PERM = false, REACH = false;
   static constexpr int OUT = kOutF32, NPASS = 2;
   static constexpr int set(int ps) { return ps == 0 ? kSetLo : kSetHi; }
   static constexpr bool same_panel(int) { return false; }
@@ -2120,12 +2176,12 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
         hipLaunchKernelGGL(igemm_kernel<IgY<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
                            IgY<float>{grids, v64, x32, 0, work});
         hipLaunchKernelGGL(igemm_kernel<IgSG<float>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
-                           IgSG<float>{x32, 0, work});
+                           IgSG<float>{x32, 0, work, lam_pre, cl, closec});
       } else {
         hipLaunchKernelGGL(igemm_kernel<IgY<double>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
                            IgY<double>{grids, v64, (const double*)evec, cur_ws, work});
         hipLaunchKernelGGL(igemm_kernel<IgSG<double>>, dim3(ig), dim3(kIT), 0, s, items, nullptr, n_items,
-                           IgSG<double>{(const double*)evec, cur_ws, work});
+                           IgSG<double>{(const double*)evec, cur_ws, work, lam_pre, cl, closec});
       }
     } else if (st == 0) {
       hipLaunchKernelGGL(gemm_y_kernel<float>, dim3(xcd_grid(tiles, n_items)), dim3(T64::NT), 0, s, items, n_items,
@@ -2140,7 +2196,7 @@ hipError_t launch_refine(const ItemDev* items, int n_items, int min_n, int max_n
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    {
+    if (!whole) {  // the whole-item S, G product ran the close-pair test itself
       const int rt = (max_n + kReachRows - 1) / kReachRows;
       hipLaunchKernelGGL(refine_reach_kernel, dim3(xcd_grid(rt, n_items)), dim3(64 * kReachWaves), 0, s, items,
                          lam_pre, work, cl, closec, rt, n_items);
