@@ -843,8 +843,9 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   __shared__ short big_start[kMaxBig], big_len[kMaxBig];
   __shared__ short bt_start[kMaxChain / 2], bt_len[kMaxChain / 2], bt_poff[kMaxChain / 2 + 1];
   __shared__ short bend[kMaxChain];
+  __shared__ short src[kMaxChain];
   __shared__ unsigned char pch[kMaxChain];
-  __shared__ int s_nch, s_c1, s_Tb, s_fail, s_nbig, s_nbt;
+  __shared__ int s_nch, s_c0, s_c1, s_Tb, s_fail, s_nbig, s_nbt;
   __shared__ short seg_start[kMaxN];
   __shared__ int scan_sh[kBlock / 64];
   const ItemDev it = items[blockIdx.x];
@@ -889,17 +890,12 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
   d4 acc[2][2];
   while (true) {
     // next batch: chains [c0, c1) with at most kMaxChain columns in total
+    // (thread 0 picks them, then every thread fills the per-column tables)
     if (threadIdx.x == 0) {
       const int c0 = s_c1;
       int c1 = c0, Tb = 0, nbt = 0;
       bt_poff[0] = 0;
       while (c1 < nch && Tb + ch_len[c1] <= kMaxChain) {
-        for (int t = 0; t < ch_len[c1]; ++t) {
-          cols[Tb + t] = ch_start[c1] + t;
-          blk[Tb + t] = Tb;
-          bend[Tb + t] = (short)(Tb + ch_len[c1]);
-        }
-        for (int t = 0; t < (ch_len[c1] + 1) / 2; ++t) pch[bt_poff[nbt] + t] = (unsigned char)nbt;
         bt_start[nbt] = (short)Tb;
         bt_len[nbt] = ch_len[c1];
         bt_poff[nbt + 1] = (short)(bt_poff[nbt] + (ch_len[c1] + 1) / 2);
@@ -907,13 +903,28 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
         Tb += ch_len[c1];
         ++c1;
       }
+      s_c0 = c0;
       s_c1 = c1;
       s_Tb = Tb;
       s_nbt = nbt;
     }
     __syncthreads();
-    const int Tb = s_Tb;
+    const int Tb = s_Tb, c0 = s_c0;
     if (Tb == 0) break;
+    if (threadIdx.x < kMaxChain) {
+      const int nbt = s_nbt, t = threadIdx.x;
+      int b = 0;  // the batch chain of column t, and of pair slot t
+      while (b + 1 < nbt && bt_start[b + 1] <= t) ++b;
+      if (t < Tb) {
+        cols[t] = ch_start[c0 + b] + (t - bt_start[b]);
+        blk[t] = bt_start[b];
+        bend[t] = (short)(bt_start[b] + bt_len[b]);
+      }
+      int bp = 0;
+      while (bp + 1 < nbt && bt_poff[bp + 1] <= t) ++bp;
+      if (t < bt_poff[nbt]) pch[t] = (unsigned char)bp;
+    }
+    __syncthreads();
     // P and T: each wavefront splits into row groups of tpw >= Tb lanes (8,
     // 16, 32 or 64), lane t of a group takes column t; the groups of all
     // wavefronts interleave the rows (all loads of a round of 8 rows per
@@ -1030,13 +1041,17 @@ __global__ __launch_bounds__(kBlock, 2) void refine_chain_kernel(const ItemDev* 
       const int b0 = blk[j];
       const double lj = nrm[j] - shift[j];
       int rank = b0;
-      for (int q = b0; q < Tb && blk[q] == b0; ++q) {
+      for (int q = b0; q < bend[j]; ++q) {
         const double lq = nrm[q] - shift[q];
         rank += (lq < lj || (lq == lj && q < j)) ? 1 : 0;
       }
-      const int e = bend[j];
-      for (int r = 0; r < Tb; ++r) QB[r * Tb + rank] = (r >= b0 && r < e) ? W[j * ldw + (r - b0)] / nrm[j] : 0.0;
+      src[rank] = (short)j;
       eval[it.e_off + cols[rank]] = lj;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < Tb * Tb; e += kBlock) {
+      const int r = e / Tb, c = e - r * Tb, j = src[c], b0 = blk[c];
+      QB[e] = (r >= b0 && r < bend[c]) ? W[j * ldw + (r - b0)] / nrm[j] : 0.0;
     }
     __syncthreads();
     // P Q -> the batch's columns of M
