@@ -458,6 +458,17 @@ __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restric
   }
   const int i0 = bi * kFT, j0 = (bi + rem) * kFT;
   const WS ws(work, it);
+  // the tile's S and G loads go out first: they do not wait for the chain scan
+  const int tx = threadIdx.x & (kFT - 1), ty = threadIdx.x / kFT;
+  const int j = j0 + tx;
+  double gv[kFRows], sv[kFRows];
+#pragma unroll
+  for (int u = 0; u < kFRows; ++u) {
+    const int k = i0 + ty + kFRY * u;
+    const int64_t e = (k < n && j < n && k <= j) ? (int64_t)k * n + j : 0;
+    gv[u] = ws.G[e];
+    sv[u] = ws.S[e];
+  }
   {
     // chain membership of the tile's rows and columns (no reach list: no chains)
     const int per = (n + kBlock - 1) / kBlock;
@@ -480,16 +491,6 @@ __global__ __launch_bounds__(kBlock) void form_m_kernel(const ItemDev* __restric
     }
   }
   __syncthreads();
-  const int tx = threadIdx.x & (kFT - 1), ty = threadIdx.x / kFT;
-  const int j = j0 + tx;
-  double gv[kFRows], sv[kFRows];
-#pragma unroll
-  for (int u = 0; u < kFRows; ++u) {
-    const int k = i0 + ty + kFRY * u;
-    const int64_t e = (k < n && j < n && k <= j) ? (int64_t)k * n + j : 0;
-    gv[u] = ws.G[e];
-    sv[u] = ws.S[e];
-  }
   if (j < n) {
     const double lj = lam_j[tx];
 #pragma unroll
