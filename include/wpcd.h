@@ -129,7 +129,7 @@ typedef struct {
   double jacobi_stop_f32; /* FP32 Jacobi (LDS and device-memory): end the
                             iteration after a sweep whose largest rotated
                             pair had |w_p.w_q|/(|w_p||w_q|) below this; must
-                            lie in (0, 1); 0 = default max(1e-4, 8 x
+                            lie in (0, 1); 0 = default max(2e-4, 8 x
                             jacobi_tol_f32).  The FP64 path always uses
                             8 x jacobi_tol_f64                               */
   int32_t jacobi_start;  /* start of the LDS FP32 Jacobi in wpcd_eigh: 0

@@ -217,7 +217,7 @@ int wpcd_create(wpcd_ctx* out, int hip_device, const wpcd_config* cfg) {
   // without growing its chains; 3e-4 does grow them (coupled n = 200 batch:
   // 2.90 sweeps at 3e-5, 2.50 at 1e-4 with the same refinement time); never
   // below 8 x tol, where rotations at the skip threshold would recur
-  if (c.jacobi_stop_f32 == 0.0) c.jacobi_stop_f32 = std::max(1e-4, 8.0 * c.jacobi_tol_f32);
+  if (c.jacobi_stop_f32 == 0.0) c.jacobi_stop_f32 = std::max(2e-4, 8.0 * c.jacobi_tol_f32);
   if (c.max_sweeps < 1 || c.max_sweeps > 60) return fail(WPCD_ERR_INVALID, "max_sweeps must be in [1, 60]");
   if (c.refine_steps < 0 || c.refine_steps > 4) return fail(WPCD_ERR_INVALID, "refine_steps must be in [0, 4]");
   if (!(c.jacobi_tol_f32 > 0) || !(c.jacobi_tol_f64 > 0)) return fail(WPCD_ERR_INVALID, "tolerances must be > 0");
