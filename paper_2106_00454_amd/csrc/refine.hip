@@ -31,11 +31,15 @@
 // Newton updates through) by a direct bound on the size of each update.
 //
 // Kernels per step: Y = A X, {S, G} = X^T {Y, X} and X M are dense FP64
-// contractions on the matrix cores (v_mfma_f64_16x16x4f64), one work-group per
-// 64 x 64 output tile of one item (S and G: upper tiles only, mirrored);
-// refine_reach_kernel (16 rows per work-group) forms the Rayleigh quotients
-// and the close pairs, refine_chain_kernel (one work-group per item) the
-// chains and their Rayleigh-Ritz rotations.  A final kernel sorts the
+// contractions on the matrix cores (v_mfma_f64_16x16x4f64): for batches of
+// 193..208-row items whole-item products (one persistent work-group per CU;
+// S and G stored as upper triangles, and the S, G product also forms the
+// Rayleigh quotients and the close pairs), otherwise one work-group per
+// 64 x 64 output tile of one item (S and G: upper tiles, mirrored) and
+// refine_reach_kernel for the Rayleigh quotients and close pairs.  Readers
+// of S and G take the upper triangle only.  form_m_kernel writes M = I + E
+// outside the chains, refine_chain_kernel (one work-group per item) finds
+// the chains and their Rayleigh-Ritz rotations.  A final kernel sorts the
 // eigenpairs by eigenvalue and writes them to the caller's arrays.
 #include <float.h>
 
