@@ -69,7 +69,7 @@ def _check(tag, b, host, k, n_gauss, packet, K, us, mode, tlab):
         assert it["eig_status"] > 0 and it["t_status"] == 0, msg
         assert dd <= DELTA_TOL and dm <= DELTA_TOL and ds <= SIGMA_TOL, msg
         assert resid <= 1e-9 * hmax, msg
-        assert orth <= (3e-8 if mode == wp.MIXED else 1e-13), msg
+        assert orth <= (3e-9 if mode == wp.MIXED else 1e-13), msg
 
 
 def _yamaguchi_items(n):
